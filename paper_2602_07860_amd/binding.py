@@ -1,0 +1,128 @@
+"""ctypes binding of the C ABI in include/motion_blur_raster.h (same names).
+
+Argument marshalling only: every step of the rendering runs in the HIP
+library.  Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+from .build import LIB
+
+RB_OK, RB_EINVAL, RB_ERANGE, RB_EWORKSPACE, RB_EBEHIND, RB_EOVERFLOW, RB_EDEVICE, RB_EUNSUPPORTED = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+RB_SOLVER_FAST, RB_SOLVER_RECOMPUTE = 0, 1
+RB_MAX_CHANNELS = 4
+RB_MAX_FACES = 1 << 23
+RB_MAX_CHUNK = 8
+HDR_FACE_RANGE, HDR_BEHIND, HDR_OVERFLOW = 1, 2, 4
+
+EXPORTED = ["rb_workspace_size", "rb_validate", "rb_render_blur_fwd", "rb_render_blur_bwd",
+            "rb_read_header", "rb_status_string"]
+
+
+class rb_camera(ctypes.Structure):
+    _fields_ = [("view", ctypes.c_float * 12), ("tan_half_fov", ctypes.c_float),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+class rb_motion(ctypes.Structure):
+    _fields_ = [("num_segments", ctypes.c_int32), ("keyframe_model", ctypes.c_void_p)]
+
+
+class rb_options(ctypes.Structure):
+    _fields_ = [("num_subframes", ctypes.c_int32), ("delta", ctypes.c_float),
+                ("eps_cutoff", ctypes.c_float), ("solver", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("chunk_len", ctypes.c_int32),
+                ("chunks_per_wave", ctypes.c_int32), ("list_capacity", ctypes.c_int64)]
+
+
+class rb_header(ctypes.Structure):
+    _fields_ = [("error_bits", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("list_entries", ctypes.c_int64), ("list_capacity", ctypes.c_int64)]
+
+
+class RenderError(RuntimeError):
+    def __init__(self, status: int, where: str = ""):
+        self.status = status
+        super().__init__(f"{where}: {rb_status_string(status)} ({status})")
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return LIB
+
+
+def lib():
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            raise RuntimeError(f"HIP library not built: {LIB} missing (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB)
+        P = ctypes.POINTER
+        vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+        L.rb_workspace_size.restype = i32
+        L.rb_workspace_size.argtypes = [i32, i32, i32, P(rb_motion), P(rb_camera), P(rb_options), P(sz)]
+        L.rb_validate.restype = i32
+        L.rb_validate.argtypes = [i32, i32, i32, P(rb_motion), P(rb_camera), P(rb_options), sz]
+        L.rb_render_blur_fwd.restype = i32
+        L.rb_render_blur_fwd.argtypes = [vp, i32, vp, i32, vp, i32, P(rb_motion), P(rb_camera),
+                                         P(rb_options), vp, vp, sz, vp]
+        L.rb_render_blur_bwd.restype = i32
+        L.rb_render_blur_bwd.argtypes = [vp, i32, vp, i32, vp, i32, P(rb_motion), P(rb_camera),
+                                         P(rb_options), vp, vp, vp, vp, sz, vp]
+        L.rb_read_header.restype = i32
+        L.rb_read_header.argtypes = [vp, P(rb_header), vp]
+        L.rb_status_string.restype = ctypes.c_char_p
+        L.rb_status_string.argtypes = [i32]
+        _lib = L
+    return _lib
+
+
+def rb_workspace_size(V, F, C, motion: rb_motion, camera: rb_camera, options: rb_options) -> int:
+    out = ctypes.c_size_t()
+    st = lib().rb_workspace_size(V, F, C, ctypes.byref(motion), ctypes.byref(camera),
+                                 ctypes.byref(options), ctypes.byref(out))
+    if st != RB_OK:
+        raise RenderError(st, "rb_workspace_size")
+    return out.value
+
+
+def rb_validate(V, F, C, motion, camera, options, workspace_bytes) -> int:
+    m = ctypes.byref(motion) if motion is not None else None
+    c = ctypes.byref(camera) if camera is not None else None
+    o = ctypes.byref(options) if options is not None else None
+    return lib().rb_validate(V, F, C, m, c, o, workspace_bytes)
+
+
+def rb_render_blur_fwd(verts, V, faces, F, attrs, C, motion, camera, options, image,
+                       workspace, workspace_bytes, stream) -> int:
+    return lib().rb_render_blur_fwd(verts, V, faces, F, attrs, C, ctypes.byref(motion),
+                                    ctypes.byref(camera), ctypes.byref(options), image,
+                                    workspace, workspace_bytes, stream)
+
+
+def rb_render_blur_bwd(verts, V, faces, F, attrs, C, motion, camera, options, grad_image,
+                       grad_verts, grad_attrs, workspace, workspace_bytes, stream) -> int:
+    return lib().rb_render_blur_bwd(verts, V, faces, F, attrs, C, ctypes.byref(motion),
+                                    ctypes.byref(camera), ctypes.byref(options), grad_image,
+                                    grad_verts, grad_attrs, workspace, workspace_bytes, stream)
+
+
+def rb_read_header(workspace, stream) -> rb_header:
+    h = rb_header()
+    st = lib().rb_read_header(workspace, ctypes.byref(h), stream)
+    if st != RB_OK:
+        raise RenderError(st, "rb_read_header")
+    return h
+
+
+def rb_status_string(status: int) -> str:
+    try:
+        return lib().rb_status_string(status).decode()
+    except RuntimeError:
+        return f"status {status}"

@@ -1,0 +1,209 @@
+// Host entry points of the C ABI declared in motion_blur_raster.h:
+// argument validation, the launch plan (tiles, sub-frame chunks, workspace
+// layout) and the kernel sequence.  No allocation, no synchronization (except
+// rb_read_header, documented as waiting).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "rb_internal.h"
+
+namespace rb {
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static rb_status make_plan(int32_t V, int32_t F, int32_t C, const rb_motion *motion, const rb_camera *cam,
+                           const rb_options *opt, Plan &p)
+{
+    if (!motion || !cam || !opt) return RB_EINVAL;
+    if (V <= 0 || F <= 0 || C <= 0) return RB_EINVAL;
+    if (motion->num_segments <= 0 || opt->num_subframes <= 0) return RB_EINVAL;
+    if (cam->width <= 0 || cam->height <= 0) return RB_EINVAL;
+    if (!(cam->tan_half_fov > 0.0f) || !std::isfinite(cam->tan_half_fov)) return RB_EINVAL;
+    if (!(opt->delta > 0.0f) || !std::isfinite(opt->delta)) return RB_EINVAL;
+    if (!(opt->eps_cutoff > 0.0f && opt->eps_cutoff < 1.0f)) return RB_EINVAL;
+    for (int i = 0; i < 12; ++i)
+        if (!std::isfinite(cam->view[i])) return RB_EINVAL;
+    if (opt->solver != RB_SOLVER_FAST && opt->solver != RB_SOLVER_RECOMPUTE) return RB_EINVAL;
+    if (opt->chunk_len < 0 || opt->chunks_per_wave < 0 || opt->list_capacity < 0) return RB_EINVAL;
+    if (C > RB_MAX_CHANNELS) return RB_EUNSUPPORTED;
+    if (F >= RB_MAX_FACES) return RB_EUNSUPPORTED;
+    const int T = opt->chunk_len == 0 ? 4 : opt->chunk_len;
+    if (T != 1 && T != 2 && T != 4 && T != 8) return RB_EUNSUPPORTED;
+    const int S = motion->num_segments, K = opt->num_subframes;
+    // sub-frame index arithmetic k*S must stay in int range
+    if ((long long)K * S >= (1LL << 31)) return RB_EUNSUPPORTED;
+
+    p.V = V;
+    p.F = F;
+    p.C = C;
+    p.S = S;
+    p.K = K;
+    p.W = cam->width;
+    p.H = cam->height;
+    p.tanf = cam->tan_half_fov;
+    p.delta = opt->delta;
+    const double dmax = (double)opt->delta * std::log(1.0 / (double)opt->eps_cutoff);
+    p.dmax = (float)dmax;
+    p.halo = (float)(std::sqrt(dmax) * (1.0 + 1e-6));
+    std::memcpy(p.view, cam->view, sizeof(p.view));
+    p.solver = opt->solver;
+    p.tiles_x = (p.W + kTile - 1) / kTile;
+    p.tiles_y = (p.H + kTile - 1) / kTile;
+    p.ntiles = p.tiles_x * p.tiles_y;
+    p.T = T;
+    int nmax = 0;
+    for (int s = 0; s < S; ++s) {
+        int lo = seg_first(s, K, S), hi = (s == S - 1) ? K : seg_first(s + 1, K, S);
+        nmax = std::max(nmax, hi - lo);
+    }
+    p.CPS = std::max(1, (nmax + T - 1) / T);
+    p.NC = S * p.CPS;
+    if (opt->chunks_per_wave > 0) {
+        p.G = opt->chunks_per_wave;
+    } else {
+        // enough waves to fill 256 CUs several times over
+        const int64_t target_groups = std::max<int64_t>(1, 16384 / p.ntiles);
+        p.G = (int)std::max<int64_t>(1, (p.NC + target_groups - 1) / target_groups);
+    }
+    p.G = std::min(p.G, p.NC);
+    p.NG = (p.NC + p.G - 1) / p.G;
+    p.cap = opt->list_capacity > 0 ? opt->list_capacity
+                                   : std::max<int64_t>(1 << 20, (int64_t)64 * F * std::min(p.NC, 64));
+    p.ncounts = (int64_t)2 * p.NC * p.ntiles;
+    p.nblocks_scan = std::max<int64_t>(1, (p.ncounts + 4095) / 4096);
+
+    size_t o = 0;
+    p.o_hdr = o;
+    o = align256(o + sizeof(DevHeader));
+    p.o_kf = o;
+    o = align256(o + (size_t)(S + 1) * V * sizeof(float4));
+    p.o_cnt = o;
+    o = align256(o + (size_t)p.ncounts * 4);
+    p.o_off = o;
+    o = align256(o + (size_t)p.ncounts * 8);
+    p.o_cur = o;
+    o = align256(o + (size_t)p.ncounts * 4);
+    p.o_bsum = o;
+    o = align256(o + (size_t)p.nblocks_scan * 8);
+    p.o_list = o;
+    o = align256(o + (size_t)p.cap * 4);
+    p.o_vis_id = o;
+    o = align256(o + (size_t)p.ntiles * K * kWave * 4);
+    p.o_vis_p = o;
+    o = align256(o + (size_t)p.ntiles * K * kWave * 4);
+    p.o_part = o;
+    o = align256(o + (size_t)p.NG * p.ntiles * (C + 1) * kWave * 4);
+    p.o_gkf = o;
+    o = align256(o + (size_t)(S + 1) * V * 2 * 4);
+    p.total = o;
+    return RB_OK;
+}
+
+static Bufs carve(const Plan &p, void *ws)
+{
+    char *b = (char *)ws;
+    Bufs r;
+    r.hdr = (DevHeader *)(b + p.o_hdr);
+    r.kf = (float4 *)(b + p.o_kf);
+    r.cnt = (int32_t *)(b + p.o_cnt);
+    r.off = (int64_t *)(b + p.o_off);
+    r.cur = (int32_t *)(b + p.o_cur);
+    r.bsum = (int64_t *)(b + p.o_bsum);
+    r.list = (uint32_t *)(b + p.o_list);
+    r.vis_id = (int32_t *)(b + p.o_vis_id);
+    r.vis_p = (float *)(b + p.o_vis_p);
+    r.part = (float *)(b + p.o_part);
+    r.gkf = (float *)(b + p.o_gkf);
+    return r;
+}
+
+}  // namespace rb
+
+using namespace rb;
+
+extern "C" {
+
+rb_status rb_workspace_size(int32_t V, int32_t F, int32_t C, const rb_motion *motion, const rb_camera *camera,
+                            const rb_options *options, size_t *bytes)
+{
+    if (!bytes) return RB_EINVAL;
+    Plan p;
+    rb_status st = make_plan(V, F, C, motion, camera, options, p);
+    if (st != RB_OK) return st;
+    *bytes = p.total;
+    return RB_OK;
+}
+
+rb_status rb_validate(int32_t V, int32_t F, int32_t C, const rb_motion *motion, const rb_camera *camera,
+                      const rb_options *options, size_t workspace_bytes)
+{
+    Plan p;
+    rb_status st = make_plan(V, F, C, motion, camera, options, p);
+    if (st != RB_OK) return st;
+    if (!motion->keyframe_model) return RB_EINVAL;
+    if (workspace_bytes < p.total) return RB_EWORKSPACE;
+    return RB_OK;
+}
+
+rb_status rb_render_blur_fwd(const float *verts, int32_t V, const int32_t *faces, int32_t F, const float *attrs,
+                             int32_t C, const rb_motion *motion, const rb_camera *camera, const rb_options *options,
+                             float *image, void *workspace, size_t workspace_bytes, void *stream)
+{
+    if (!verts || !faces || !attrs || !image || !workspace) return RB_EINVAL;
+    rb_status st = rb_validate(V, F, C, motion, camera, options, workspace_bytes);
+    if (st != RB_OK) return st;
+    Plan p;
+    make_plan(V, F, C, motion, camera, options, p);
+    Bufs b = carve(p, workspace);
+    Inputs in{verts, faces, attrs, motion->keyframe_model};
+    hipError_t e = launch_forward(p, in, b, image, (hipStream_t)stream);
+    return e == hipSuccess ? RB_OK : RB_EDEVICE;
+}
+
+rb_status rb_render_blur_bwd(const float *verts, int32_t V, const int32_t *faces, int32_t F, const float *attrs,
+                             int32_t C, const rb_motion *motion, const rb_camera *camera, const rb_options *options,
+                             const float *grad_image, float *grad_verts, float *grad_attrs, void *workspace,
+                             size_t workspace_bytes, void *stream)
+{
+    if (!verts || !faces || !attrs || !grad_image || !grad_verts || !grad_attrs || !workspace) return RB_EINVAL;
+    rb_status st = rb_validate(V, F, C, motion, camera, options, workspace_bytes);
+    if (st != RB_OK) return st;
+    Plan p;
+    make_plan(V, F, C, motion, camera, options, p);
+    Bufs b = carve(p, workspace);
+    Inputs in{verts, faces, attrs, motion->keyframe_model};
+    hipError_t e = launch_backward(p, in, b, grad_image, grad_verts, grad_attrs, (hipStream_t)stream);
+    return e == hipSuccess ? RB_OK : RB_EDEVICE;
+}
+
+rb_status rb_read_header(const void *workspace, rb_header *out, void *stream)
+{
+    if (!workspace || !out) return RB_EINVAL;
+    DevHeader h;
+    hipStream_t st = (hipStream_t)stream;
+    if (hipMemcpyAsync(&h, workspace, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess) return RB_EDEVICE;
+    if (hipStreamSynchronize(st) != hipSuccess) return RB_EDEVICE;
+    out->error_bits = h.error_bits;
+    out->reserved = 0;
+    out->list_entries = h.list_entries;
+    out->list_capacity = h.list_capacity;
+    return RB_OK;
+}
+
+const char *rb_status_string(rb_status s)
+{
+    switch (s) {
+    case RB_OK: return "ok";
+    case RB_EINVAL: return "invalid argument";
+    case RB_ERANGE: return "face index out of range";
+    case RB_EWORKSPACE: return "workspace too small";
+    case RB_EBEHIND: return "vertex behind the camera";
+    case RB_EOVERFLOW: return "bin list capacity exceeded";
+    case RB_EDEVICE: return "HIP runtime error";
+    case RB_EUNSUPPORTED: return "unsupported size or option";
+    default: return "unknown status";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,103 @@
+// Internal plan shared by the host entry points (rb_api.cpp) and the kernels
+// (rb_kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <cstddef>
+#include <cstdint>
+
+#include <hip/hip_runtime.h>
+
+#include "motion_blur_raster.h"
+
+namespace rb {
+
+constexpr int kTile = 8;                  // tile edge in pixels: one 64-lane wave per tile
+constexpr int kWave = 64;
+constexpr float kTauDet = 1e-10f;         // |det F(tau)| at or below this: face skipped
+constexpr int kHdrFaceRange = 1, kHdrBehind = 2, kHdrOverflow = 4;
+
+// First sub-frame of segment s: the smallest k with floor(k S / (K-1)) >= s,
+// i.e. sub-frame t_k = k/(K-1) falls in segment min(floor(t_k S), S-1).
+__host__ __device__ inline int seg_first(int s, int K, int S)
+{
+    if (K <= 1) return s == 0 ? 0 : 1;
+    if (s <= 0) return 0;
+    long long num = (long long)s * (K - 1);
+    return (int)((num + S - 1) / S);
+}
+
+// Chunk c = s * CPS + j: the j-th of CPS near-equal runs of segment s's
+// sub-frames [k0, k0 + n).
+struct Chunk {
+    int s, k0, n;
+};
+
+__host__ __device__ inline Chunk chunk_info(int c, int K, int S, int CPS)
+{
+    int s = c / CPS, j = c - s * CPS;
+    int klo = seg_first(s, K, S);
+    int khi = (s == S - 1) ? K : seg_first(s + 1, K, S);
+    int n = khi - klo;
+    Chunk ch;
+    ch.s = s;
+    ch.k0 = klo + (int)(((long long)j * n) / CPS);
+    ch.n = klo + (int)(((long long)(j + 1) * n) / CPS) - ch.k0;
+    return ch;
+}
+
+// Workspace header as laid out on the device (first 256 bytes).
+struct DevHeader {
+    int32_t error_bits;
+    int32_t reserved;
+    int64_t list_entries;
+    int64_t list_capacity;
+    int64_t pad[5];
+};
+
+// Everything a launch needs, derived on the host from sizes and options.
+struct Plan {
+    // problem
+    int V, F, C, S, K, W, H;
+    float tanf, delta, dmax, halo;
+    float view[12];
+    int solver;
+    // tiling and sub-frame chunks
+    int tiles_x, tiles_y, ntiles;
+    int T;          // chunk length (template)
+    int CPS;        // chunks per segment
+    int NC;         // chunks = S * CPS
+    int G;          // chunks per wave
+    int NG;         // chunk groups = ceil(NC / G)
+    int64_t cap;    // list capacity (entries)
+    // workspace byte offsets
+    size_t o_hdr, o_kf, o_cnt, o_off, o_cur, o_bsum, o_list, o_vis_id, o_vis_p, o_part, o_gkf, total;
+    int64_t ncounts;  // 2 * NC * ntiles
+    int64_t nblocks_scan;
+};
+
+// Pointers into a workspace for one call.
+struct Bufs {
+    DevHeader *hdr;
+    float4 *kf;          // [S+1][V] (x, y, camera depth, 0)
+    int32_t *cnt;        // [2][NC][ntiles] list lengths (fg, bg)
+    int64_t *off;        // [2][NC][ntiles] list starts
+    int32_t *cur;        // [2][NC][ntiles] fill cursors
+    int64_t *bsum;       // scan block sums
+    uint32_t *list;      // entries: face << 8 | sub-frame mask
+    int32_t *vis_id;     // [ntiles][K][64] winner face, or -1 - (#zero factors, max 2) for background
+    float *vis_p;        // [ntiles][K][64] background product over non-zero factors
+    float *part;         // [NG][ntiles][C+1][64] partial sums
+    float *gkf;          // [S+1][V][2] keyframe gradient
+};
+
+struct Inputs {
+    const float *verts;
+    const int32_t *faces;
+    const float *attrs;
+    const float *model;
+};
+
+hipError_t launch_forward(const Plan &p, const Inputs &in, const Bufs &b, float *image, hipStream_t st);
+hipError_t launch_backward(const Plan &p, const Inputs &in, const Bufs &b, const float *grad_image,
+                           float *grad_verts, float *grad_attrs, hipStream_t st);
+
+}  // namespace rb
