@@ -135,6 +135,21 @@ rb_status rb_render_blur_bwd(const float *verts, int32_t V, const int32_t *faces
  * stream.  Returns RB_OK, RB_EINVAL or RB_EDEVICE. */
 rb_status rb_read_header(const void *workspace, rb_header *out, void *stream);
 
+/* Kernel timing for benchmarks.  While enabled, every forward / backward
+ * call records HIP events on its stream around each of its phases
+ * (projection, binning, rasterization, image reduction; backward
+ * rasterization, vertex-gradient mapping).  rb_profile_read SYNCHRONIZES on
+ * those events, returns the accumulated milliseconds and call counts, and
+ * clears them.  Enabling or disabling also clears.  Thread-safe. */
+typedef struct {
+    double project_ms, bin_ms, raster_fwd_ms, reduce_ms;   /* forward phases  */
+    double raster_bwd_ms, vertex_grad_ms;                  /* backward phases */
+    int64_t fwd_calls, bwd_calls;
+} rb_profile_stats;
+
+rb_status rb_profile_enable(int32_t enable);
+rb_status rb_profile_read(rb_profile_stats *out);
+
 /* Static description of a status code. */
 const char *rb_status_string(rb_status status);
 

@@ -19,7 +19,7 @@ RB_MAX_CHUNK = 8
 HDR_FACE_RANGE, HDR_BEHIND, HDR_OVERFLOW = 1, 2, 4
 
 EXPORTED = ["rb_workspace_size", "rb_validate", "rb_render_blur_fwd", "rb_render_blur_bwd",
-            "rb_read_header", "rb_status_string"]
+            "rb_read_header", "rb_profile_enable", "rb_profile_read", "rb_status_string"]
 
 
 class rb_camera(ctypes.Structure):
@@ -41,6 +41,13 @@ class rb_options(ctypes.Structure):
 class rb_header(ctypes.Structure):
     _fields_ = [("error_bits", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("list_entries", ctypes.c_int64), ("list_capacity", ctypes.c_int64)]
+
+
+class rb_profile_stats(ctypes.Structure):
+    _fields_ = [("project_ms", ctypes.c_double), ("bin_ms", ctypes.c_double),
+                ("raster_fwd_ms", ctypes.c_double), ("reduce_ms", ctypes.c_double),
+                ("raster_bwd_ms", ctypes.c_double), ("vertex_grad_ms", ctypes.c_double),
+                ("fwd_calls", ctypes.c_int64), ("bwd_calls", ctypes.c_int64)]
 
 
 class RenderError(RuntimeError):
@@ -77,6 +84,10 @@ def lib():
                                          P(rb_options), vp, vp, vp, vp, sz, vp]
         L.rb_read_header.restype = i32
         L.rb_read_header.argtypes = [vp, P(rb_header), vp]
+        L.rb_profile_enable.restype = i32
+        L.rb_profile_enable.argtypes = [i32]
+        L.rb_profile_read.restype = i32
+        L.rb_profile_read.argtypes = [P(rb_profile_stats)]
         L.rb_status_string.restype = ctypes.c_char_p
         L.rb_status_string.argtypes = [i32]
         _lib = L
@@ -119,6 +130,20 @@ def rb_read_header(workspace, stream) -> rb_header:
     if st != RB_OK:
         raise RenderError(st, "rb_read_header")
     return h
+
+
+def rb_profile_enable(enable: bool) -> None:
+    st = lib().rb_profile_enable(1 if enable else 0)
+    if st != RB_OK:
+        raise RenderError(st, "rb_profile_enable")
+
+
+def rb_profile_read() -> rb_profile_stats:
+    s = rb_profile_stats()
+    st = lib().rb_profile_read(ctypes.byref(s))
+    if st != RB_OK:
+        raise RenderError(st, "rb_profile_read")
+    return s
 
 
 def rb_status_string(status: int) -> str:

@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <vector>
 
 #include "rb_internal.h"
 
@@ -77,7 +79,9 @@ static rb_status make_plan(int32_t V, int32_t F, int32_t C, const rb_motion *mot
     p.o_hdr = o;
     o = align256(o + sizeof(DevHeader));
     p.o_kf = o;
-    o = align256(o + (size_t)(S + 1) * V * sizeof(float4));
+    o = align256(o + (size_t)(S + 1) * V * sizeof(double2));
+    p.o_kfz = o;
+    o = align256(o + (size_t)(S + 1) * V * sizeof(float));
     p.o_cnt = o;
     o = align256(o + (size_t)p.ncounts * 4);
     p.o_off = o;
@@ -105,7 +109,8 @@ static Bufs carve(const Plan &p, void *ws)
     char *b = (char *)ws;
     Bufs r;
     r.hdr = (DevHeader *)(b + p.o_hdr);
-    r.kf = (float4 *)(b + p.o_kf);
+    r.kf = (double2 *)(b + p.o_kf);
+    r.kfz = (float *)(b + p.o_kfz);
     r.cnt = (int32_t *)(b + p.o_cnt);
     r.off = (int64_t *)(b + p.o_off);
     r.cur = (int32_t *)(b + p.o_cur);
@@ -116,6 +121,36 @@ static Bufs carve(const Plan &p, void *ws)
     r.part = (float *)(b + p.o_part);
     r.gkf = (float *)(b + p.o_gkf);
     return r;
+}
+
+// ---- benchmark timing (rb_profile_*)
+struct ProfRec {
+    int kind;   // 0 forward, 1 backward
+    PhaseEvents pe;
+};
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static std::vector<ProfRec> g_prof;
+
+static void prof_clear_locked()
+{
+    for (auto &r : g_prof)
+        for (auto e : r.pe.ev)
+            if (e) (void)hipEventDestroy(e);
+    g_prof.clear();
+}
+
+// events for one call, or nullptr when timing is off
+static const PhaseEvents *prof_begin(int kind, PhaseEvents &pe)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof_on) return nullptr;
+    const int n = kind == 0 ? 5 : 4;
+    for (int i = 0; i < 5; ++i) pe.ev[i] = nullptr;
+    for (int i = 0; i < n; ++i)
+        if (hipEventCreate(&pe.ev[i]) != hipSuccess) pe.ev[i] = nullptr;
+    g_prof.push_back(ProfRec{kind, pe});
+    return &pe;
 }
 
 }  // namespace rb
@@ -157,7 +192,9 @@ rb_status rb_render_blur_fwd(const float *verts, int32_t V, const int32_t *faces
     make_plan(V, F, C, motion, camera, options, p);
     Bufs b = carve(p, workspace);
     Inputs in{verts, faces, attrs, motion->keyframe_model};
-    hipError_t e = launch_forward(p, in, b, image, (hipStream_t)stream);
+    PhaseEvents pe;
+    const PhaseEvents *pp = prof_begin(0, pe);
+    hipError_t e = launch_forward(p, in, b, image, (hipStream_t)stream, pp);
     return e == hipSuccess ? RB_OK : RB_EDEVICE;
 }
 
@@ -173,7 +210,9 @@ rb_status rb_render_blur_bwd(const float *verts, int32_t V, const int32_t *faces
     make_plan(V, F, C, motion, camera, options, p);
     Bufs b = carve(p, workspace);
     Inputs in{verts, faces, attrs, motion->keyframe_model};
-    hipError_t e = launch_backward(p, in, b, grad_image, grad_verts, grad_attrs, (hipStream_t)stream);
+    PhaseEvents pe;
+    const PhaseEvents *pp = prof_begin(1, pe);
+    hipError_t e = launch_backward(p, in, b, grad_image, grad_verts, grad_attrs, (hipStream_t)stream, pp);
     return e == hipSuccess ? RB_OK : RB_EDEVICE;
 }
 
@@ -189,6 +228,47 @@ rb_status rb_read_header(const void *workspace, rb_header *out, void *stream)
     out->list_entries = h.list_entries;
     out->list_capacity = h.list_capacity;
     return RB_OK;
+}
+
+rb_status rb_profile_enable(int32_t enable)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    prof_clear_locked();
+    g_prof_on = enable != 0;
+    return RB_OK;
+}
+
+rb_status rb_profile_read(rb_profile_stats *out)
+{
+    if (!out) return RB_EINVAL;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    std::memset(out, 0, sizeof(*out));
+    rb_status st = RB_OK;
+    auto span = [&](hipEvent_t a, hipEvent_t b) -> double {
+        float ms = 0.0f;
+        if (!a || !b) return 0.0;
+        if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+            st = RB_EDEVICE;
+            return 0.0;
+        }
+        return (double)ms;
+    };
+    for (auto &r : g_prof) {
+        const hipEvent_t *e = r.pe.ev;
+        if (r.kind == 0) {
+            out->project_ms += span(e[0], e[1]);
+            out->bin_ms += span(e[1], e[2]);
+            out->raster_fwd_ms += span(e[2], e[3]);
+            out->reduce_ms += span(e[3], e[4]);
+            out->fwd_calls += 1;
+        } else {
+            out->raster_bwd_ms += span(e[1], e[2]);
+            out->vertex_grad_ms += span(e[0], e[1]) + span(e[2], e[3]);
+            out->bwd_calls += 1;
+        }
+    }
+    prof_clear_locked();
+    return st;
 }
 
 const char *rb_status_string(rb_status s)

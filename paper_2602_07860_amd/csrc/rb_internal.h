@@ -69,7 +69,7 @@ struct Plan {
     int NG;         // chunk groups = ceil(NC / G)
     int64_t cap;    // list capacity (entries)
     // workspace byte offsets
-    size_t o_hdr, o_kf, o_cnt, o_off, o_cur, o_bsum, o_list, o_vis_id, o_vis_p, o_part, o_gkf, total;
+    size_t o_hdr, o_kf, o_kfz, o_cnt, o_off, o_cur, o_bsum, o_list, o_vis_id, o_vis_p, o_part, o_gkf, total;
     int64_t ncounts;  // 2 * NC * ntiles
     int64_t nblocks_scan;
 };
@@ -77,7 +77,9 @@ struct Plan {
 // Pointers into a workspace for one call.
 struct Bufs {
     DevHeader *hdr;
-    float4 *kf;          // [S+1][V] (x, y, camera depth, 0)
+    double2 *kf;         // [S+1][V] keyframe (x, y), kept in double: edge-on (sliver)
+                         // faces make barycentrics sensitive to 1e-8 position errors
+    float *kfz;          // [S+1][V] keyframe camera depth
     int32_t *cnt;        // [2][NC][ntiles] list lengths (fg, bg)
     int64_t *off;        // [2][NC][ntiles] list starts
     int32_t *cur;        // [2][NC][ntiles] fill cursors
@@ -96,8 +98,14 @@ struct Inputs {
     const float *model;
 };
 
-hipError_t launch_forward(const Plan &p, const Inputs &in, const Bufs &b, float *image, hipStream_t st);
+// Optional phase events (benchmark timing); null entries are skipped.
+struct PhaseEvents {
+    hipEvent_t ev[5];
+};
+
+hipError_t launch_forward(const Plan &p, const Inputs &in, const Bufs &b, float *image, hipStream_t st,
+                          const PhaseEvents *pe);
 hipError_t launch_backward(const Plan &p, const Inputs &in, const Bufs &b, const float *grad_image,
-                           float *grad_verts, float *grad_attrs, hipStream_t st);
+                           float *grad_verts, float *grad_attrs, hipStream_t st, const PhaseEvents *pe);
 
 }  // namespace rb

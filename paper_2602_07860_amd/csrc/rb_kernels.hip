@@ -2,7 +2,12 @@
 //
 // Work decomposition
 //   * keyframes: one thread per (keyframe, vertex) projects M_s P0 (App. I)
-//     in double precision and stores float4 (x, y, camera depth, 0).
+//     in double precision and keeps (x, y) in double, depth in float.  A face
+//     seen almost edge-on has a tiny area, so its barycentrics move by
+//     (position error)/(height); float32 keyframes alone would cost ~1e-5 of
+//     the image there.  Each list entry turns the doubles into float32
+//     coordinates relative to the tile anchor at the chunk's middle time,
+//     where they are small and exact to ~1e-9.
 //   * chunks: the sub-frames t_k = k/(K-1) (Sec. 3.2) of each linear segment
 //     (Sec. 3.3) are cut into chunks of at most T consecutive sub-frames that
 //     share one segment, hence one pair of keyframes and one set of
@@ -101,7 +106,7 @@ struct ViewArgs {
 // Keyframe projection (App. I): X = view (M_s P0), x = X.x/(X.z tan), y = X.y/(X.z tan)
 __global__ void k_project(const float *__restrict__ verts, const float *__restrict__ model,
                           const int32_t *__restrict__ faces, int V, int S, int F, ViewArgs vw,
-                          float4 *__restrict__ kf, DevHeader *hdr)
+                          double2 *__restrict__ kf, float *__restrict__ kfz, DevHeader *hdr)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t nkf = (int64_t)(S + 1) * V;
@@ -119,7 +124,8 @@ __global__ void k_project(const float *__restrict__ verts, const float *__restri
                    (double)vw.m[4 * r + 3];
         double t = (double)vw.tanf;
         double x = c[0] / (c[2] * t), y = c[1] / (c[2] * t);
-        kf[i] = make_float4((float)x, (float)y, (float)c[2], 0.0f);
+        kf[i] = make_double2(x, y);
+        kfz[i] = (float)c[2];
         if (!(c[2] > 1e-6)) atomicOr(&hdr->error_bits, kHdrBehind);
     } else if (i < nkf + F) {
         int f = (int)(i - nkf);
@@ -130,7 +136,7 @@ __global__ void k_project(const float *__restrict__ verts, const float *__restri
 
 struct BinArgs {
     const int32_t *faces;
-    const float4 *kf;
+    const double2 *kf;
     int32_t *cnt;
     const int64_t *off;
     int32_t *cur;
@@ -190,12 +196,12 @@ __global__ __launch_bounds__(256) void k_bin(BinArgs a, int pass)
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
         int v = clampi(a.faces[3 * f + q], 0, a.V - 1);
-        float4 p = a.kf[(size_t)ch.s * a.V + v];
-        float4 r = a.kf[(size_t)(ch.s + 1) * a.V + v];
-        ax[q] = p.x;
-        ay[q] = p.y;
-        bx[q] = r.x - p.x;
-        by[q] = r.y - p.y;
+        double2 p = a.kf[(size_t)ch.s * a.V + v];
+        double2 r = a.kf[(size_t)(ch.s + 1) * a.V + v];
+        ax[q] = (float)p.x;
+        ay[q] = (float)p.y;
+        bx[q] = (float)(r.x - p.x);
+        by[q] = (float)(r.y - p.y);
     }
     int ftx0[T], ftx1[T], fty0[T], fty1[T], btx0[T], btx1[T], bty0[T], bty1[T];
     int ux0 = INT_MAX, ux1 = INT_MIN, uy0 = INT_MAX, uy1 = INT_MIN;
@@ -331,7 +337,8 @@ __global__ void k_scan3(int64_t *__restrict__ off, const int64_t *__restrict__ b
 // ----------------------------------------------------------------- raster
 
 struct RasterArgs {
-    const float4 *kf;
+    const double2 *kf;
+    const float *kfz;
     const int32_t *faces;
     const float *attrs;
     const int32_t *cnt;
@@ -348,74 +355,122 @@ struct RasterArgs {
 
 constexpr int NCH = RB_MAX_CHANNELS;
 
-// One face of one list entry, seen from one tile: anchor-local keyframe data.
+// One face of one list entry, seen from one tile, over one chunk: float32
+// coordinates relative to the tile anchor, formed in double precision.
 struct FaceData {
     int v[3];
-    float x0[3], y0[3];   // segment-start position minus the tile anchor
-    float dx[3], dy[3];   // segment displacement
-    float z0[3], dz[3];   // camera depth and its change
+    float xc[3], yc[3];     // positions at the chunk's middle time tc
+    float dx[3], dy[3];     // segment displacement (position at tau = xc + (tau - tc) dx)
+    float xk0[3], yk0[3];   // keyframe s (segment start)
+    float xk1[3], yk1[3];   // keyframe s + 1 (segment end)
+    float ecx[3], ecy[3];   // edge i = v[(i+2)%3] - v[(i+1)%3] at tc
+    float dex[3], dey[3];   // change of edge i over the segment
+    float z0[3], dz[3];     // camera depth at the segment start and its change
+    float tc;
 };
 
-__device__ __forceinline__ void load_face(const RasterArgs &a, int f, int s, float ua, float va, FaceData &fd)
+__device__ __forceinline__ void load_face(const RasterArgs &a, int f, int s, double ua, double va, float tc,
+                                          FaceData &fd)
 {
+    double X0[3], Y0[3], X1[3], Y1[3], Xc[3], Yc[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
         int v = clampi(a.faces[3 * f + q], 0, a.V - 1);
         fd.v[q] = v;
-        float4 p = a.kf[(size_t)s * a.V + v];
-        float4 r = a.kf[(size_t)(s + 1) * a.V + v];
-        fd.x0[q] = p.x - ua;
-        fd.y0[q] = p.y - va;
-        fd.dx[q] = r.x - p.x;
-        fd.dy[q] = r.y - p.y;
-        fd.z0[q] = p.z;
-        fd.dz[q] = r.z - p.z;
+        const double2 p = a.kf[(size_t)s * a.V + v];
+        const double2 r = a.kf[(size_t)(s + 1) * a.V + v];
+        X0[q] = p.x;
+        Y0[q] = p.y;
+        X1[q] = r.x;
+        Y1[q] = r.y;
+        Xc[q] = fma((double)tc, r.x - p.x, p.x);
+        Yc[q] = fma((double)tc, r.y - p.y, p.y);
+        fd.xc[q] = (float)(Xc[q] - ua);
+        fd.yc[q] = (float)(Yc[q] - va);
+        fd.dx[q] = (float)(r.x - p.x);
+        fd.dy[q] = (float)(r.y - p.y);
+        fd.xk0[q] = (float)(p.x - ua);
+        fd.yk0[q] = (float)(p.y - va);
+        fd.xk1[q] = (float)(r.x - ua);
+        fd.yk1[q] = (float)(r.y - va);
+        const float z0 = a.kfz[(size_t)s * a.V + v], z1 = a.kfz[(size_t)(s + 1) * a.V + v];
+        fd.z0[q] = z0;
+        fd.dz[q] = z1 - z0;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int j = (i + 1) % 3, k = (i + 2) % 3;
+        fd.ecx[i] = (float)(Xc[k] - Xc[j]);
+        fd.ecy[i] = (float)(Yc[k] - Yc[j]);
+        fd.dex[i] = (float)((X1[k] - X1[j]) - (X0[k] - X0[j]));
+        fd.dey[i] = (float)((Y1[k] - Y1[j]) - (Y0[k] - Y0[j]));
+    }
+    fd.tc = tc;
+}
+
+// anchor-local vertex positions at local time tau
+__device__ __forceinline__ void pos_at(const FaceData &fd, float tau, float xt[3], float yt[3])
+{
+    const float t = tau - fd.tc;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        xt[q] = fmaf(t, fd.dx[q], fd.xc[q]);
+        yt[q] = fmaf(t, fd.dy[q], fd.yc[q]);
     }
 }
 
 // Per-lane barycentric numerators N_i(tau) (w_i = N_i / sum N) at the pixel
-// (du, dv) from the anchor.  FAST: coefficients of eq 8 once per (pixel,
-// face, segment), Horner per sub-frame.  RECOMPUTE: fresh lerp and adjugate
-// row products per sub-frame (eqs 3, 5).
+// (du, dv) from the anchor; N_i = (v_j - p) x (v_k - v_j) with (i, j, k)
+// cyclic, i.e. row i of adj(F) p (eq 7).
+//
+// FAST (eq 8): under linear motion N_i is a quadratic in the local time, with
+// coefficients computed once per (pixel, face, chunk) and evaluated by Horner's
+// rule per sub-frame.  The quadratic is expanded about the chunk's middle time
+// tc (t' = tau - tc): the same polynomial as the segment-start expansion, but
+// built from pixel-to-vertex and edge vectors at tc, which keeps float32
+// cancellation small when a segment moves far.
+// RECOMPUTE: per sub-frame, lerp the three vertices (eq 5) and take the
+// adjugate row products afresh (eqs 2-3).
 template <int SOLVER>
 struct Bary {
-    float c1[3], c2[3], c3[3];   // FAST: A1, A2, A3.  RECOMPUTE: px, py (start), unused
+    float c1[3], c2[3], c3[3];
     __device__ __forceinline__ void setup(const FaceData &fd, float du, float dv)
     {
-        float px[3], py[3];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            px[q] = fd.x0[q] - du;
-            py[q] = fd.y0[q] - dv;
-        }
         if (SOLVER == RB_SOLVER_FAST) {
+            float ax[3], ay[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                ax[q] = fd.xc[q] - du;
+                ay[q] = fd.yc[q] - dv;
+            }
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                const int j = (i + 1) % 3, k = (i + 2) % 3;
-                c1[i] = fmaf(fd.dx[j], fd.dy[k], -fd.dx[k] * fd.dy[j]);
-                c2[i] = fmaf(px[j], fd.dy[k], fd.dx[j] * py[k]) - fmaf(px[k], fd.dy[j], fd.dx[k] * py[j]);
-                c3[i] = fmaf(px[j], py[k], -px[k] * py[j]);
+                const int j = (i + 1) % 3;
+                c1[i] = fmaf(fd.dx[j], fd.dey[i], -fd.dy[j] * fd.dex[i]);
+                c2[i] = fmaf(ax[j], fd.dey[i], -ay[j] * fd.dex[i]) + fmaf(fd.dx[j], fd.ecy[i], -fd.dy[j] * fd.ecx[i]);
+                c3[i] = fmaf(ax[j], fd.ecy[i], -ay[j] * fd.ecx[i]);
             }
         } else {
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                c1[i] = px[i];
-                c2[i] = py[i];
+                c1[i] = fd.xc[i] - du;
+                c2[i] = fd.yc[i] - dv;
                 c3[i] = 0.0f;
             }
         }
     }
     __device__ __forceinline__ void eval(const FaceData &fd, float tau, float N[3]) const
     {
+        const float t = tau - fd.tc;
         if (SOLVER == RB_SOLVER_FAST) {
 #pragma unroll
-            for (int i = 0; i < 3; ++i) N[i] = fmaf(fmaf(c1[i], tau, c2[i]), tau, c3[i]);
+            for (int i = 0; i < 3; ++i) N[i] = fmaf(fmaf(c1[i], t, c2[i]), t, c3[i]);
         } else {
             float xt[3], yt[3];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                xt[i] = fmaf(tau, fd.dx[i], c1[i]);
-                yt[i] = fmaf(tau, fd.dy[i], c2[i]);
+                xt[i] = fmaf(t, fd.dx[i], c1[i]);
+                yt[i] = fmaf(t, fd.dy[i], c2[i]);
             }
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
@@ -435,8 +490,8 @@ struct EdgeSet {
     {
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            ax[q] = X ? fd.x0[q] + fd.dx[q] : fd.x0[q];
-            ay[q] = X ? fd.y0[q] + fd.dy[q] : fd.y0[q];
+            ax[q] = X ? fd.xk1[q] : fd.xk0[q];
+            ay[q] = X ? fd.yk1[q] : fd.yk0[q];
         }
 #pragma unroll
         for (int e = 0; e < 3; ++e) {
@@ -481,11 +536,7 @@ __device__ __forceinline__ void bg_eval(const FaceData &fd, const EdgeSet &es, f
     }
     // sub-frame positions of the chosen edge's end points (anchor-local)
     float xt[3], yt[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        xt[i] = fmaf(tau, fd.dx[i], fd.x0[i]);
-        yt[i] = fmaf(tau, fd.dy[i], fd.y0[i]);
-    }
+    pos_at(fd, tau, xt, yt);
     float xa = r.be == 0 ? xt[0] : (r.be == 1 ? xt[1] : xt[2]);
     float ya = r.be == 0 ? yt[0] : (r.be == 1 ? yt[1] : yt[2]);
     float xb = r.be == 0 ? xt[1] : (r.be == 1 ? xt[2] : xt[0]);
@@ -499,7 +550,8 @@ __device__ __forceinline__ void bg_eval(const FaceData &fd, const EdgeSet &es, f
 struct TileGeom {
     int tile, grp, px, py;
     bool inimg;
-    float ua, va, du, dv;
+    double ua, va;   // tile anchor (between the 4 centre pixels) in normalized coordinates
+    float du, dv;    // this lane's pixel centre relative to the anchor (exact for W, H powers of 2)
 };
 
 __device__ __forceinline__ bool tile_geom(const RasterArgs &a, TileGeom &g)
@@ -514,8 +566,8 @@ __device__ __forceinline__ bool tile_geom(const RasterArgs &a, TileGeom &g)
     g.px = tx * kTile + (lane & 7);
     g.py = ty * kTile + (lane >> 3);
     g.inimg = g.px < a.W && g.py < a.H;
-    g.ua = (float)(16 * tx + 8 - a.W) / (float)a.W;
-    g.va = (float)(a.H - 16 * ty - 8) / (float)a.H;
+    g.ua = (double)(16 * tx + 8 - a.W) / (double)a.W;
+    g.va = (double)(a.H - 16 * ty - 8) / (double)a.H;
     g.du = (float)(2 * (lane & 7) - 7) / (float)a.W;
     g.dv = (float)(7 - 2 * (lane >> 3)) / (float)a.H;
     return true;
@@ -531,6 +583,17 @@ __device__ __forceinline__ void chunk_taus(const RasterArgs &a, const Chunk &ch,
         tau[j] = a.K > 1 ? (float)rem / (float)(a.K - 1) : 0.0f;
         if (j < ch.n && 2 * rem > a.K - 1) xbits |= 1u << j;
     }
+}
+
+// middle local time of a chunk: the expansion point of the fast solver
+template <int T>
+__device__ __forceinline__ float chunk_centre(const float tau[T], int n)
+{
+    float last = tau[0];
+#pragma unroll
+    for (int j = 1; j < T; ++j)
+        if (j < n) last = tau[j];
+    return 0.5f * (tau[0] + last);
 }
 
 template <int T, int SOLVER>
@@ -552,6 +615,7 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a)
         float tau[T];
         uint32_t xbits;
         chunk_taus<T>(a, ck, tau, xbits);
+        const float tcen = chunk_centre<T>(tau, ck.n);
         float zb[T], rgb[T][NCH], P[T];
         int zid[T], nz[T];
 #pragma unroll
@@ -575,7 +639,7 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a)
                 const uint32_t msk = ent & live;
                 if (!msk) continue;
                 FaceData fd;
-                load_face(a, f, ck.s, g.ua, g.va, fd);
+                load_face(a, f, ck.s, g.ua, g.va, tcen, fd);
                 float at[3][NCH];
 #pragma unroll
                 for (int q = 0; q < 3; ++q)
@@ -627,7 +691,7 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a)
                 const uint32_t msk = ent & bgbits;
                 if (!msk) continue;
                 FaceData fd;
-                load_face(a, f, ck.s, g.ua, g.va, fd);
+                load_face(a, f, ck.s, g.ua, g.va, tcen, fd);
                 EdgeSet es0, es1;
                 if (msk & ~xbits) es0.setup(fd, 0);
                 if (msk & xbits) es1.setup(fd, 1);
@@ -773,6 +837,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a, GradArgs ga)
         float tau[T];
         uint32_t xbits;
         chunk_taus<T>(a, ck, tau, xbits);
+        const float tcen = chunk_centre<T>(tau, ck.n);
         int vid[T];
         float vp[T];
 #pragma unroll
@@ -805,7 +870,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a, GradArgs ga)
                 const uint32_t msk = wave_or(hits) & ent & fgbits;
                 if (!msk) continue;
                 FaceData fd;
-                load_face(a, f, ck.s, g.ua, g.va, fd);
+                load_face(a, f, ck.s, g.ua, g.va, tcen, fd);
                 float at[3][NCH];
 #pragma unroll
                 for (int q = 0; q < 3; ++q)
@@ -838,11 +903,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a, GradArgs ga)
                     const float invD = 1.0f / (N[0] + N[1] + N[2]);
                     const float w[3] = {N[0] * invD, N[1] * invD, N[2] * invD};
                     float xt[3], yt[3];
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) {
-                        xt[q] = fmaf(tau[j], fd.dx[q], fd.x0[q]);
-                        yt[q] = fmaf(tau[j], fd.dy[q], fd.y0[q]);
-                    }
+                    pos_at(fd, tau[j], xt, yt);
                     const float gxs =
                         fmaf(gw[0], yt[1] - yt[2], fmaf(gw[1], yt[2] - yt[0], gw[2] * (yt[0] - yt[1]))) * invD;
                     const float gys =
@@ -881,7 +942,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a, GradArgs ga)
                 const uint32_t msk = ent & bgbits;
                 if (!msk) continue;
                 FaceData fd;
-                load_face(a, f, ck.s, g.ua, g.va, fd);
+                load_face(a, f, ck.s, g.ua, g.va, tcen, fd);
                 EdgeSet es0, es1;
                 if (msk & ~xbits) es0.setup(fd, 0);
                 if (msk & xbits) es1.setup(fd, 1);
@@ -916,11 +977,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a, GradArgs ga)
                     // d = |p* - p|^2, p* = (1 - sg) v_a(tau) + sg v_b(tau)
                     const float gpx = 2.0f * gd * (be.psx - g.du), gpy = 2.0f * gd * (be.psy - g.dv);
                     float xt[3], yt[3];
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) {
-                        xt[q] = fmaf(tau[j], fd.dx[q], fd.x0[q]);
-                        yt[q] = fmaf(tau[j], fd.dy[q], fd.y0[q]);
-                    }
+                    pos_at(fd, tau[j], xt, yt);
                     // per-vertex gradient at tau (gt) and at keyframe X (gk)
                     float gtx[3], gty[3], gkx[3], gky[3];
 #pragma unroll
@@ -1024,6 +1081,7 @@ static RasterArgs raster_args(const Plan &p, const Inputs &in, const Bufs &b)
 {
     RasterArgs a;
     a.kf = b.kf;
+    a.kfz = b.kfz;
     a.faces = in.faces;
     a.attrs = in.attrs;
     a.cnt = b.cnt;
@@ -1053,8 +1111,13 @@ static RasterArgs raster_args(const Plan &p, const Inputs &in, const Bufs &b)
     return a;
 }
 
+static inline void mark(const PhaseEvents *pe, int i, hipStream_t st)
+{
+    if (pe && pe->ev[i]) (void)hipEventRecord(pe->ev[i], st);
+}
+
 template <int T>
-static hipError_t fwd_T(const Plan &p, const Inputs &in, const Bufs &b, hipStream_t st)
+static hipError_t fwd_T(const Plan &p, const Inputs &in, const Bufs &b, hipStream_t st, const PhaseEvents *pe)
 {
     BinArgs ba;
     ba.faces = in.faces;
@@ -1083,6 +1146,7 @@ static hipError_t fwd_T(const Plan &p, const Inputs &in, const Bufs &b, hipStrea
     hipLaunchKernelGGL(k_scan2, dim3(1), dim3(kScanThreads), 0, st, b.bsum, p.nblocks_scan, b.hdr, p.cap);
     hipLaunchKernelGGL(k_scan3, dim3(grid_for(p.ncounts, 256)), dim3(256), 0, st, b.off, b.bsum, p.ncounts);
     hipLaunchKernelGGL(k_bin<T>, dim3(grid_for(nbin, 256)), dim3(256), 0, st, ba, 1);
+    mark(pe, 2, st);
     RasterArgs ra = raster_args(p, in, b);
     const int64_t waves = (int64_t)p.ntiles * p.NG;
     const unsigned blocks = grid_for(waves, 4);
@@ -1090,11 +1154,14 @@ static hipError_t fwd_T(const Plan &p, const Inputs &in, const Bufs &b, hipStrea
         hipLaunchKernelGGL((k_raster_fwd<T, RB_SOLVER_FAST>), dim3(blocks), dim3(256), 0, st, ra);
     else
         hipLaunchKernelGGL((k_raster_fwd<T, RB_SOLVER_RECOMPUTE>), dim3(blocks), dim3(256), 0, st, ra);
+    mark(pe, 3, st);
     return hipGetLastError();
 }
 
-hipError_t launch_forward(const Plan &p, const Inputs &in, const Bufs &b, float *image, hipStream_t st)
+hipError_t launch_forward(const Plan &p, const Inputs &in, const Bufs &b, float *image, hipStream_t st,
+                          const PhaseEvents *pe)
 {
+    mark(pe, 0, st);
     hipLaunchKernelGGL(k_init, dim3(grid_for(p.ncounts, 256) > 4096 ? 4096 : grid_for(p.ncounts, 256) + 1), dim3(256), 0,
                        st, b.hdr, p.cap, b.cnt, b.cur, p.ncounts);
     ViewArgs vw;
@@ -1102,18 +1169,20 @@ hipError_t launch_forward(const Plan &p, const Inputs &in, const Bufs &b, float 
     vw.tanf = p.tanf;
     const int64_t nproj = (int64_t)(p.S + 1) * p.V + p.F;
     hipLaunchKernelGGL(k_project, dim3(grid_for(nproj, 256)), dim3(256), 0, st, in.verts, in.model, in.faces, p.V,
-                       p.S, p.F, vw, b.kf, b.hdr);
+                       p.S, p.F, vw, b.kf, b.kfz, b.hdr);
+    mark(pe, 1, st);
     hipError_t e;
     switch (p.T) {
-    case 1: e = fwd_T<1>(p, in, b, st); break;
-    case 2: e = fwd_T<2>(p, in, b, st); break;
-    case 4: e = fwd_T<4>(p, in, b, st); break;
-    default: e = fwd_T<8>(p, in, b, st); break;
+    case 1: e = fwd_T<1>(p, in, b, st, pe); break;
+    case 2: e = fwd_T<2>(p, in, b, st, pe); break;
+    case 4: e = fwd_T<4>(p, in, b, st, pe); break;
+    default: e = fwd_T<8>(p, in, b, st, pe); break;
     }
     if (e != hipSuccess) return e;
     const int64_t npix = (int64_t)(p.C + 1) * p.W * p.H;
     hipLaunchKernelGGL(k_reduce_image, dim3(grid_for(npix, 256)), dim3(256), 0, st, b.part, image, p.C, p.W, p.H,
                        p.tiles_x, p.ntiles, p.NG, 1.0f / (float)p.K, b.hdr);
+    mark(pe, 4, st);
     return hipGetLastError();
 }
 
@@ -1130,8 +1199,9 @@ static void bwd_T(const Plan &p, const Inputs &in, const Bufs &b, const GradArgs
 }
 
 hipError_t launch_backward(const Plan &p, const Inputs &in, const Bufs &b, const float *grad_image, float *grad_verts,
-                           float *grad_attrs, hipStream_t st)
+                           float *grad_attrs, hipStream_t st, const PhaseEvents *pe)
 {
+    mark(pe, 0, st);
     const int64_t ngkf = (int64_t)(p.S + 1) * p.V * 2;
     hipLaunchKernelGGL(k_zero, dim3(grid_for(ngkf, 256) > 4096 ? 4096 : grid_for(ngkf, 256)), dim3(256), 0, st, b.gkf,
                        ngkf);
@@ -1143,17 +1213,20 @@ hipError_t launch_backward(const Plan &p, const Inputs &in, const Bufs &b, const
     ga.gkf = b.gkf;
     ga.gattr = grad_attrs;
     ga.invK = 1.0f / (float)p.K;
+    mark(pe, 1, st);
     switch (p.T) {
     case 1: bwd_T<1>(p, in, b, ga, st); break;
     case 2: bwd_T<2>(p, in, b, ga, st); break;
     case 4: bwd_T<4>(p, in, b, ga, st); break;
     default: bwd_T<8>(p, in, b, ga, st); break;
     }
+    mark(pe, 2, st);
     ViewArgs vw;
     for (int i = 0; i < 12; ++i) vw.m[i] = p.view[i];
     vw.tanf = p.tanf;
     hipLaunchKernelGGL(k_kf_to_vertex, dim3(grid_for(p.V, 256)), dim3(256), 0, st, in.verts, in.model, b.gkf, p.V,
                        p.S, vw, grad_verts);
+    mark(pe, 3, st);
     return hipGetLastError();
 }
 
