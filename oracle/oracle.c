@@ -502,6 +502,16 @@ static int orc_guard(const orc_ctx *cx, orc_tls *t, int n, int s, int X, double 
     return 0;
 }
 
+static int orc_threads(const orc_scene *sc)
+{
+#ifdef _OPENMP
+    return sc->nthreads > 0 ? sc->nthreads : omp_get_max_threads();
+#else
+    (void)sc;
+    return 1;
+#endif
+}
+
 static int orc_build(orc_ctx *cx, const orc_scene *sc)
 {
     memset(cx, 0, sizeof(*cx));
@@ -509,6 +519,7 @@ static int orc_build(orc_ctx *cx, const orc_scene *sc)
     int V = sc->V, S = sc->S, K = sc->K, F = sc->F;
     cx->KF = (double *)malloc(sizeof(double) * (size_t)(S + 1) * V * 3);
     if (!cx->KF) return -1;
+#pragma omp parallel for schedule(static) num_threads(orc_threads(sc))
     for (int s = 0; s <= S; ++s)
         for (int v = 0; v < V; ++v)
             orc_project(sc->view, sc->model + s * 12, sc->tan_half_fov, sc->verts + v * 3,
@@ -538,6 +549,7 @@ static int orc_build(orc_ctx *cx, const orc_scene *sc)
     }
     cx->swept = (double *)malloc(sizeof(double) * (size_t)S * F * 4);
     if (!cx->swept) return -1;
+#pragma omp parallel for collapse(2) schedule(static) num_threads(orc_threads(sc))
     for (int s = 0; s < S; ++s) {
         for (int f = 0; f < F; ++f) {
             double *b = cx->swept + ((size_t)s * F + f) * 4;

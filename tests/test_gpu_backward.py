@@ -51,9 +51,10 @@ def test_medium_gradients_vs_oracle():
 
 
 def test_medium_gradient_vs_frozen_fd_64_vertices():
-    # central FD (eps = 1e-3 world units, Richardson-extrapolated) of the
-    # oracle's frozen-decision surrogate along a random direction per vertex,
-    # for 64 vertices drawn with seed 102 among those the loss depends on
+    # central FD (eps = 1e-3 world units, two Richardson levels: eps, eps/2,
+    # eps/4) of the oracle's frozen-decision surrogate along a random direction
+    # per vertex, for 64 vertices drawn with seed 102 among those the loss
+    # depends on.  The perturbed vertices go to the FP64 oracle unrounded.
     sc = wl.make_workload(wl.MEDIUM)
     rows = (0, sc.height, 128)
     say(f"case: FD {sc.name} rows {rows}")
@@ -67,30 +68,27 @@ def test_medium_gradient_vs_frozen_fd_64_vertices():
     live = np.where(np.abs(og.grad_verts).sum(1) > 0)[0]
     rng = np.random.default_rng(102)
     picks = rng.choice(live, size=min(64, len(live)), replace=False)
-    fds, gpus = [], []
+
+    def loss(vi, d, h):
+        v = sc.verts.astype(np.float64).copy()
+        v[vi] += h * d
+        r = oracle.render(sc.with_(verts=v), rows=rows, replay=base.decisions)
+        return float(np.sum(G * r.image))
+
+    fds, gpus, adj = [], [], []
+    eps = 1e-3
     for vi in picks:
         d = rng.normal(size=3)
         d /= np.linalg.norm(d)
-
-        def L(h):
-            v = sc.verts.astype(np.float64).copy()
-            v[vi] += h * d
-            r = oracle.render(sc.with_(verts=v.astype(np.float32)), rows=rows, replay=base.decisions)
-            return float(np.sum(G * r.image)), (v.astype(np.float32)[vi].astype(np.float64) - sc.verts[vi])
-
-        eps = 1e-3
-        (lp, dp), (lm, dm) = L(eps), L(-eps)
-        (lp2, dp2), (lm2, dm2) = L(eps / 2), L(-eps / 2)
-        # float32 inputs: use the realised step along d
-        h1 = float(np.dot(dp - dm, d))
-        h2 = float(np.dot(dp2 - dm2, d))
-        D1 = (lp - lm) / h1
-        D2 = (lp2 - lm2) / h2
-        fds.append((4 * D2 - D1) / 3)
+        D = [(loss(vi, d, h) - loss(vi, d, -h)) / (2 * h) for h in (eps, eps / 2, eps / 4)]
+        R1 = [(4 * D[1] - D[0]) / 3, (4 * D[2] - D[1]) / 3]
+        fds.append((16 * R1[1] - R1[0]) / 15)
         gpus.append(float(gv[vi] @ d))
-    fds, gpus = np.array(fds), np.array(gpus)
-    e = rel_l2(gpus, fds)
-    say(f"FD rel-L2 over {len(picks)} vertices: {e:.2e}")
+        adj.append(float(og.grad_verts[vi] @ d))
+    fds, gpus, adj = np.array(fds), np.array(gpus), np.array(adj)
+    e, e_or = rel_l2(gpus, fds), rel_l2(adj, fds)
+    say(f"FD rel-L2 over {len(picks)} vertices: GPU {e:.2e}, oracle adjoint {e_or:.2e}")
+    assert e_or <= 1e-4      # the FD itself is accurate
     assert e <= GRAD_RTOL
 
 
