@@ -40,6 +40,8 @@
 #define ORC_GUARD_W 2e-5       /* guard band on min_i w_i for parity reporting */
 #define ORC_GUARD_DEPTH 1e-6   /* relative depth near-tie */
 #define ORC_GUARD_EDGE 1e-9    /* relative near-tie between edge distances */
+#define ORC_GUARD_SIGMA 2e-5   /* edge parameter near a clamp bound (times max |w|) */
+#define ORC_GUARD_EDGE_GRAD 1e-5 /* relative edge near-tie that may change the gradient */
 #define ORC_MAX_AMBIG 6
 
 enum { CNT_BBOX, CNT_COV, CNT_FG, CNT_BG, CNT_BGPAIRS, CNT_SETUP, CNT_FLAGGED, CNT_SKIP, ORC_NCNT };
@@ -437,12 +439,23 @@ static int orc_background(const orc_ctx *cx, orc_tls *t, int n, int s, int X, do
 {
     int m = 0;
     double prod = 1.0;
-    *edge_tie = 0;
+    *edge_tie = 0;   /* bit 0: closest points of two edges tie; bit 1: edge parameter at a clamp bound */
     for (int j = 0; j < n; ++j) {
         if (t->ev[j].skip) continue;
         double gap;
         if (orc_bg_face(cx, &t->ev[j], s, X, u, v, -1, 0, &t->bt[m], &gap)) {
-            if (gap < ORC_GUARD_EDGE) *edge_tie = 1;
+            /* two edges whose closest points differ are nearly as close: the
+             * value is continuous across the switch, the frozen-decision
+             * derivative (which vertices and whether the edge parameter
+             * carries gradient) is not */
+            if (gap < ORC_GUARD_EDGE) *edge_tie |= 3;
+            else if (gap < ORC_GUARD_EDGE_GRAD) *edge_tie |= 2;
+            /* the edge parameter within rounding distance of 0 or 1: the value
+             * is continuous there but the frozen-decision derivative is not */
+            const orc_bgterm *bq = &t->bt[m];
+            double wm = fmax(1.0, fmax(fabs(bq->w[0]), fmax(fabs(bq->w[1]), fabs(bq->w[2]))));
+            double gs = ORC_GUARD_SIGMA * wm;
+            if (fabs(bq->sigma_raw) < gs || fabs(bq->sigma_raw - 1.0) < gs) *edge_tie |= 2;
             prod *= t->bt[m].om;
             ++m;
         }
@@ -451,25 +464,28 @@ static int orc_background(const orc_ctx *cx, orc_tls *t, int n, int s, int X, do
     return m;
 }
 
-/* Parity guard band: 1 if a decision of this (pixel, sub-frame) lies within
- * rounding distance of flipping and the flip would move the sub-frame value by
- * more than thr.  Enumerates every in/out choice of the faces whose min w is
- * within ORC_GUARD_W of 0, plus depth near-ties of each resulting z-buffer. */
+/* Parity guard band of the foreground decision of one (pixel, sub-frame).
+ * Enumerates every in/out choice of the faces whose min w is within
+ * ORC_GUARD_W of 0, plus depth near-ties of each resulting z-buffer.
+ * Returns bit 0 if a flip would move the sub-frame value by more than thr,
+ * bit 1 if the z-buffer winner (whose vertices receive the gradient) could
+ * change at all. */
 static int orc_guard(const orc_ctx *cx, orc_tls *t, int n, int s, int X, double u, double v,
                      int nominal, const double *val, double thr)
 {
     const orc_scene *sc = cx->sc;
     int amb[ORC_MAX_AMBIG], na = 0;
     for (int j = 0; j < n; ++j) {
-        if (fabs(t->ev[j].D) >= 0.5 * ORC_TAU_DET && fabs(t->ev[j].D) <= 2.0 * ORC_TAU_DET) return 1;
+        if (fabs(t->ev[j].D) >= 0.5 * ORC_TAU_DET && fabs(t->ev[j].D) <= 2.0 * ORC_TAU_DET) return 3;
         if (t->ev[j].skip) continue;
         if (fabs(t->ev[j].mw) < ORC_GUARD_W) {
-            if (na == ORC_MAX_AMBIG) return 1;
+            if (na == ORC_MAX_AMBIG) return 3;
             amb[na++] = j;
         }
     }
     double bgalpha = -1.0;
     double alt[16];
+    int bits = 0;
     for (int mask = 0; mask < (1 << na); ++mask) {
         for (int j = 0; j < n; ++j) t->incl[j] = t->ev[j].cover;
         for (int a = 0; a < na; ++a) t->incl[amb[a]] = (mask >> a) & 1;
@@ -487,6 +503,7 @@ static int orc_guard(const orc_ctx *cx, orc_tls *t, int n, int s, int X, double 
                 cand = r;
             }
             if (cand == nominal) continue;
+            bits |= 2;
             if (cand >= 0) {
                 orc_shade(sc, &t->ev[cand], alt);
                 alt[sc->C] = 1.0;
@@ -496,10 +513,10 @@ static int orc_guard(const orc_ctx *cx, orc_tls *t, int n, int s, int X, double 
                 alt[sc->C] = bgalpha;
             }
             for (int c = 0; c <= sc->C; ++c)
-                if (fabs(alt[c] - val[c]) > thr) return 1;
+                if (fabs(alt[c] - val[c]) > thr) return 3;
         }
     }
-    return 0;
+    return bits;
 }
 
 static int orc_threads(const orc_scene *sc)
@@ -577,7 +594,11 @@ static void orc_free_ctx(orc_ctx *cx)
 /*
  * Render (and optionally differentiate).  image [C+1][H][W] receives the
  * averaged (rgb, alpha) for every rendered row (others untouched).  flags
- * [H][W] (optional) counts guard-band sub-frames per pixel.  counters[8]
+ * [H][W] (optional, zeroed by the caller) ORs per pixel over its sub-frames:
+ * bit 0 when a decision within rounding distance of flipping could move the
+ * value beyond tolerance, bit 1 when such a decision could change which
+ * vertices receive gradient (winner identity, clamp state of the closest
+ * point).  counters[8]
  * (optional): bbox pairs, covering pairs, fg pixel-subframes, bg
  * pixel-subframes, contributing bg pairs, distinct (pixel, face, segment)
  * setups, guard-flagged pixel-subframes, skipped degenerate pairs.
@@ -753,10 +774,9 @@ int orc_render(const orc_scene *sc, double *image, int *flags, double *counters,
                             }
                     }
                     if (flags && !rep) {
-                        if (edge_tie || orc_guard(&cx, t, n, ss, X, u, v, winner, val, thr)) {
-                            flags[(size_t)r * W + c] += 1;
-                            t->cnt[CNT_FLAGGED] += 1;
-                        }
+                        int fb = edge_tie | orc_guard(&cx, t, n, ss, X, u, v, winner, val, thr);
+                        if (fb) flags[(size_t)r * W + c] |= fb;
+                        if (fb & 1) t->cnt[CNT_FLAGGED] += 1;
                     }
                     if (rec) rend[(size_t)c * K + k] = t->rl_n;
                     for (int c2 = 0; c2 <= C; ++c2) acc[(size_t)c * (C + 1) + c2] += val[c2];

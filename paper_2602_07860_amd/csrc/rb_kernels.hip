@@ -19,16 +19,16 @@
 //     foreground (exact box) and background (box grown by the influence
 //     radius sqrt(d_max)).  Count, exclusive scan, fill.
 //   * raster: one 64-lane wave per (8x8 tile, group of chunks); lane = pixel.
-//     Per chunk the wave walks the foreground list (z-buffer per lane and
-//     sub-frame in registers), then, only for sub-frames with uncovered lanes,
-//     the background list (soft product per lane and sub-frame).  The
-//     per-(pixel, face, segment) fast-solver coefficients are set up once per
-//     list entry and evaluated by Horner's rule for each masked sub-frame.
-//   * backward: same walk over the lists, reading the forward's per
-//     (pixel, sub-frame) visibility; per-face adjoint contributions are summed
-//     over the chunk's sub-frames in registers, then over the wave, then added
-//     atomically to per-keyframe vertex gradients; a last kernel maps them
-//     through the projection to rest-vertex gradients.
+//     List entries are staged in LDS a batch at a time (one entry per lane);
+//     foreground faces are tested by every lane (z-buffer in registers);
+//     background (pixel, face) pairs are filtered by a distance lower bound
+//     and compacted into an LDS queue so that all 64 lanes evaluate useful
+//     pairs (details above k_raster_fwd).
+//   * backward: same walks over the lists, reading the forward's per
+//     (pixel, sub-frame) visibility; per-entry LDS gradient slots collect the
+//     lanes' contributions and are added atomically to per-keyframe vertex
+//     gradients; a last kernel maps those through the projection to
+//     rest-vertex gradients.
 #include <cfloat>
 #include <climits>
 
@@ -335,6 +335,26 @@ __global__ void k_scan3(int64_t *__restrict__ off, const int64_t *__restrict__ b
 }
 
 // ----------------------------------------------------------------- raster
+//
+// One 64-lane wave per (8x8 tile, group of chunks), lane = pixel.  For each
+// chunk the wave walks its two lists in batches of NB entries.  A batch is
+// staged in LDS by the whole wave at once, one entry per lane: the entry's
+// face indices and double keyframes are gathered in parallel and turned into
+// a FaceRec of float32 anchor-local coordinates, so the per-face setup costs
+// one lane instead of every lane, and one round of memory latency per batch
+// instead of one per entry.
+//
+//  * foreground: every lane tests every staged face against its pixel for
+//    each sub-frame of the entry's mask (z-buffer in registers, eq 9);
+//  * background: a cheap lower bound of the squared distance (pixel to the
+//    face's box at the sub-frame) selects the (pixel, face, sub-frame mask)
+//    triples that can reach d <= d_max; they are appended to an LDS queue and
+//    evaluated 64 at a time with every lane busy.  The soft product of eq 15
+//    is accumulated as sum log2(1 - A) with LDS atomics (zero factors counted
+//    apart).
+//  * backward: same walks; per-entry gradient slots in LDS gather the
+//    contributions of all lanes, and are flushed to global memory with one
+//    atomic per non-zero value and batch.
 
 struct RasterArgs {
     const double2 *kf;
@@ -354,68 +374,70 @@ struct RasterArgs {
 };
 
 constexpr int NCH = RB_MAX_CHANNELS;
+constexpr int NB = 32;        // list entries staged per batch
+constexpr int NGA = 12 + 3 * NCH;   // per-entry gradient slot: 3 vertices x 2 keyframes x (x, y), attributes
 
-// One face of one list entry, seen from one tile, over one chunk: float32
-// coordinates relative to the tile anchor, formed in double precision.
-struct FaceData {
+// One list entry staged in LDS.  Edge i runs from vertex (i+1)%3 to (i+2)%3.
+struct __align__(16) FaceRec {
+    float xc[3], yc[3];       // positions at the chunk's middle time tc, minus the tile anchor
+    float dx[3], dy[3];       // segment displacement
+    float e0x[3], e0y[3];     // edge i at the segment start
+    float e1x[3], e1y[3];     // edge i at the segment end
+    float iee0[3], iee1[3];   // 1 / |edge i|^2 at start / end (0 for a degenerate edge)
+    float z0[3], dz[3];       // camera depth at the start and its change
+    float at[3][NCH];         // vertex attributes
     int v[3];
-    float xc[3], yc[3];     // positions at the chunk's middle time tc
-    float dx[3], dy[3];     // segment displacement (position at tau = xc + (tau - tc) dx)
-    float xk0[3], yk0[3];   // keyframe s (segment start)
-    float xk1[3], yk1[3];   // keyframe s + 1 (segment end)
-    float ecx[3], ecy[3];   // edge i = v[(i+2)%3] - v[(i+1)%3] at tc
-    float dex[3], dey[3];   // change of edge i over the segment
-    float z0[3], dz[3];     // camera depth at the segment start and its change
-    float tc;
+    int f;
+    uint32_t msk;             // sub-frames of the chunk this entry touches
+    int pad[3];
 };
 
-__device__ __forceinline__ void load_face(const RasterArgs &a, int f, int s, double ua, double va, float tc,
-                                          FaceData &fd)
+__device__ __forceinline__ void lds_sync()
 {
-    double X0[3], Y0[3], X1[3], Y1[3], Xc[3], Yc[3];
+    // LDS operations of one wave execute in order; keep the compiler from
+    // moving memory accesses across this point
+    __builtin_amdgcn_wave_barrier();
+    __asm__ volatile("" ::: "memory");
+}
+
+__device__ __forceinline__ void stage_rec(const RasterArgs &a, uint32_t ent, uint32_t live, int s, double ua,
+                                          double va, float tc, bool with_attr, FaceRec &r)
+{
+    const int f = (int)(ent >> 8);
+    r.f = f;
+    r.msk = ent & live;
+    double X0[3], Y0[3], X1[3], Y1[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-        int v = clampi(a.faces[3 * f + q], 0, a.V - 1);
-        fd.v[q] = v;
+        const int v = clampi(a.faces[3 * f + q], 0, a.V - 1);
+        r.v[q] = v;
         const double2 p = a.kf[(size_t)s * a.V + v];
-        const double2 r = a.kf[(size_t)(s + 1) * a.V + v];
+        const double2 e = a.kf[(size_t)(s + 1) * a.V + v];
         X0[q] = p.x;
         Y0[q] = p.y;
-        X1[q] = r.x;
-        Y1[q] = r.y;
-        Xc[q] = fma((double)tc, r.x - p.x, p.x);
-        Yc[q] = fma((double)tc, r.y - p.y, p.y);
-        fd.xc[q] = (float)(Xc[q] - ua);
-        fd.yc[q] = (float)(Yc[q] - va);
-        fd.dx[q] = (float)(r.x - p.x);
-        fd.dy[q] = (float)(r.y - p.y);
-        fd.xk0[q] = (float)(p.x - ua);
-        fd.yk0[q] = (float)(p.y - va);
-        fd.xk1[q] = (float)(r.x - ua);
-        fd.yk1[q] = (float)(r.y - va);
+        X1[q] = e.x;
+        Y1[q] = e.y;
+        r.xc[q] = (float)(fma((double)tc, e.x - p.x, p.x) - ua);
+        r.yc[q] = (float)(fma((double)tc, e.y - p.y, p.y) - va);
+        r.dx[q] = (float)(e.x - p.x);
+        r.dy[q] = (float)(e.y - p.y);
         const float z0 = a.kfz[(size_t)s * a.V + v], z1 = a.kfz[(size_t)(s + 1) * a.V + v];
-        fd.z0[q] = z0;
-        fd.dz[q] = z1 - z0;
+        r.z0[q] = z0;
+        r.dz[q] = z1 - z0;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) r.at[q][c] = (with_attr && c < a.C) ? a.attrs[(size_t)v * a.C + c] : 0.0f;
     }
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         const int j = (i + 1) % 3, k = (i + 2) % 3;
-        fd.ecx[i] = (float)(Xc[k] - Xc[j]);
-        fd.ecy[i] = (float)(Yc[k] - Yc[j]);
-        fd.dex[i] = (float)((X1[k] - X1[j]) - (X0[k] - X0[j]));
-        fd.dey[i] = (float)((Y1[k] - Y1[j]) - (Y0[k] - Y0[j]));
-    }
-    fd.tc = tc;
-}
-
-// anchor-local vertex positions at local time tau
-__device__ __forceinline__ void pos_at(const FaceData &fd, float tau, float xt[3], float yt[3])
-{
-    const float t = tau - fd.tc;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        xt[q] = fmaf(t, fd.dx[q], fd.xc[q]);
-        yt[q] = fmaf(t, fd.dy[q], fd.yc[q]);
+        const double ax = X0[k] - X0[j], ay = Y0[k] - Y0[j], bx = X1[k] - X1[j], by = Y1[k] - Y1[j];
+        r.e0x[i] = (float)ax;
+        r.e0y[i] = (float)ay;
+        r.e1x[i] = (float)bx;
+        r.e1y[i] = (float)by;
+        const double ea = ax * ax + ay * ay, eb = bx * bx + by * by;
+        r.iee0[i] = ea > 0.0 ? (float)(1.0 / ea) : 0.0f;
+        r.iee1[i] = eb > 0.0 ? (float)(1.0 / eb) : 0.0f;
     }
 }
 
@@ -434,34 +456,36 @@ __device__ __forceinline__ void pos_at(const FaceData &fd, float tau, float xt[3
 template <int SOLVER>
 struct Bary {
     float c1[3], c2[3], c3[3];
-    __device__ __forceinline__ void setup(const FaceData &fd, float du, float dv)
+    __device__ __forceinline__ void setup(const FaceRec &r, float tc, float du, float dv)
     {
         if (SOLVER == RB_SOLVER_FAST) {
             float ax[3], ay[3];
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
-                ax[q] = fd.xc[q] - du;
-                ay[q] = fd.yc[q] - dv;
+                ax[q] = r.xc[q] - du;
+                ay[q] = r.yc[q] - dv;
             }
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
                 const int j = (i + 1) % 3;
-                c1[i] = fmaf(fd.dx[j], fd.dey[i], -fd.dy[j] * fd.dex[i]);
-                c2[i] = fmaf(ax[j], fd.dey[i], -ay[j] * fd.dex[i]) + fmaf(fd.dx[j], fd.ecy[i], -fd.dy[j] * fd.ecx[i]);
-                c3[i] = fmaf(ax[j], fd.ecy[i], -ay[j] * fd.ecx[i]);
+                const float dex = r.e1x[i] - r.e0x[i], dey = r.e1y[i] - r.e0y[i];
+                const float ecx = fmaf(tc, dex, r.e0x[i]), ecy = fmaf(tc, dey, r.e0y[i]);
+                c1[i] = fmaf(r.dx[j], dey, -r.dy[j] * dex);
+                c2[i] = fmaf(ax[j], dey, -ay[j] * dex) + fmaf(r.dx[j], ecy, -r.dy[j] * ecx);
+                c3[i] = fmaf(ax[j], ecy, -ay[j] * ecx);
             }
         } else {
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                c1[i] = fd.xc[i] - du;
-                c2[i] = fd.yc[i] - dv;
+                c1[i] = r.xc[i] - du;
+                c2[i] = r.yc[i] - dv;
                 c3[i] = 0.0f;
             }
         }
     }
-    __device__ __forceinline__ void eval(const FaceData &fd, float tau, float N[3]) const
+    __device__ __forceinline__ void eval(const FaceRec &r, float t, float N[3]) const
     {
-        const float t = tau - fd.tc;
+        // t = tau - tc
         if (SOLVER == RB_SOLVER_FAST) {
 #pragma unroll
             for (int i = 0; i < 3; ++i) N[i] = fmaf(fmaf(c1[i], t, c2[i]), t, c3[i]);
@@ -469,8 +493,8 @@ struct Bary {
             float xt[3], yt[3];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                xt[i] = fmaf(t, fd.dx[i], c1[i]);
-                yt[i] = fmaf(t, fd.dy[i], c2[i]);
+                xt[i] = fmaf(t, r.dx[i], c1[i]);
+                yt[i] = fmaf(t, r.dy[i], c2[i]);
             }
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
@@ -481,70 +505,116 @@ struct Bary {
     }
 };
 
-// Closest point of the keyframe triangle F(X) to q = F(X) w (App. B edge
-// projections, edges (0,1), (1,2), (2,0), first edge wins ties) and the
-// eq 14 distance at the sub-frame.
-struct EdgeSet {
-    float ax[3], ay[3], ex[3], ey[3], inv_ee[3];
-    __device__ __forceinline__ void setup(const FaceData &fd, int X)
-    {
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            ax[q] = X ? fd.xk1[q] : fd.xk0[q];
-            ay[q] = X ? fd.yk1[q] : fd.yk0[q];
-        }
-#pragma unroll
-        for (int e = 0; e < 3; ++e) {
-            const int b = (e + 1) % 3;
-            ex[e] = ax[b] - ax[e];
-            ey[e] = ay[b] - ay[e];
-            float ee = fmaf(ex[e], ex[e], ey[e] * ey[e]);
-            inv_ee[e] = ee > 0.0f ? 1.0f / ee : 0.0f;
-        }
-    }
-};
-
+// Background term of one (pixel, face, sub-frame): closest point of the
+// keyframe triangle F(X) to q = F(X) w by the three clamped edge projections
+// of App. B (edges (0,1), (1,2), (2,0), first wins ties; eq 13), mapped to
+// the sub-frame (eq 14): d = |p - F(tau) w*|^2.  q itself is never formed:
+// outside a nearly edge-on face |w| is large and q = sum w_i v_i would
+// amplify position rounding; the edge search only needs q - v_e, which is
+// w_{e+1} E_e - w_{e+2} E_{e+2} with the (double-derived) edge vectors
+// E_e = v_{e+1} - v_e.
 struct BgEval {
     float w[3];
-    float qx, qy, sr, sg, psx, psy, d;
-    int be;
+    float rx, ry;             // q - v_be in F(X)
+    float sr, sg;             // raw and clamped edge parameter
+    float psx, psy, d;        // closest point at tau (anchor-local) and squared distance
+    int be;                   // chosen edge: vertices be and (be+1)%3
 };
 
-__device__ __forceinline__ void bg_eval(const FaceData &fd, const EdgeSet &es, float tau, const float N[3],
-                                        float invD, float du, float dv, BgEval &r)
+// closest-point edge e of F(X) (from vertex e to e+1) is FaceRec edge (e+2)%3
+__device__ __forceinline__ void kedges(const FaceRec &r, int X, float tc, float Ex[3], float Ey[3], float iee[3])
 {
+    const float tx = (X ? 1.0f : 0.0f) - tc;
+    float kx[3], ky[3];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) r.w[i] = N[i] * invD;
-    r.qx = fmaf(r.w[0], es.ax[0], fmaf(r.w[1], es.ax[1], r.w[2] * es.ax[2]));
-    r.qy = fmaf(r.w[0], es.ay[0], fmaf(r.w[1], es.ay[1], r.w[2] * es.ay[2]));
-    float best = FLT_MAX;
-    r.be = 0;
-    r.sr = 0.0f;
-    r.sg = 0.0f;
+    for (int q = 0; q < 3; ++q) {
+        kx[q] = fmaf(tx, r.dx[q], r.xc[q]);
+        ky[q] = fmaf(tx, r.dy[q], r.yc[q]);
+    }
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
-        float rx = r.qx - es.ax[e], ry = r.qy - es.ay[e];
-        float sr = fmaf(rx, es.ex[e], ry * es.ey[e]) * es.inv_ee[e];
-        float sg = __builtin_amdgcn_fmed3f(sr, 0.0f, 1.0f);
-        float hx = fmaf(-sg, es.ex[e], rx), hy = fmaf(-sg, es.ey[e], ry);
-        float dist = fmaf(hx, hx, hy * hy);
-        bool better = dist < best || e == 0;
-        best = better ? dist : best;
-        r.be = better ? e : r.be;
-        r.sr = better ? sr : r.sr;
-        r.sg = better ? sg : r.sg;
+        const int i = (e + 2) % 3, b = (e + 1) % 3;
+        Ex[e] = kx[b] - kx[e];
+        Ey[e] = ky[b] - ky[e];
+        iee[e] = X ? r.iee1[i] : r.iee0[i];
     }
-    // sub-frame positions of the chosen edge's end points (anchor-local)
+}
+
+__device__ __forceinline__ void bg_eval(const FaceRec &r, float tc, float tau, int X, const float N[3], float invD,
+                                        float du, float dv, BgEval &b)
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i) b.w[i] = N[i] * invD;
+    float Ex[3], Ey[3], iee[3];
+    kedges(r, X, tc, Ex, Ey, iee);
+    float best = FLT_MAX;
+    b.be = 0;
+    b.sr = 0.0f;
+    b.sg = 0.0f;
+    b.rx = 0.0f;
+    b.ry = 0.0f;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const int e1 = (e + 1) % 3, e2 = (e + 2) % 3;
+        const float rx = fmaf(b.w[e1], Ex[e], -b.w[e2] * Ex[e2]);
+        const float ry = fmaf(b.w[e1], Ey[e], -b.w[e2] * Ey[e2]);
+        const float sr = fmaf(rx, Ex[e], ry * Ey[e]) * iee[e];
+        const float sg = __builtin_amdgcn_fmed3f(sr, 0.0f, 1.0f);
+        const float hx = fmaf(-sg, Ex[e], rx), hy = fmaf(-sg, Ey[e], ry);
+        const float dist = fmaf(hx, hx, hy * hy);
+        const bool better = dist < best || e == 0;
+        best = better ? dist : best;
+        b.be = better ? e : b.be;
+        b.sr = better ? sr : b.sr;
+        b.sg = better ? sg : b.sg;
+        b.rx = better ? rx : b.rx;
+        b.ry = better ? ry : b.ry;
+    }
+    const float t = tau - tc;
     float xt[3], yt[3];
-    pos_at(fd, tau, xt, yt);
-    float xa = r.be == 0 ? xt[0] : (r.be == 1 ? xt[1] : xt[2]);
-    float ya = r.be == 0 ? yt[0] : (r.be == 1 ? yt[1] : yt[2]);
-    float xb = r.be == 0 ? xt[1] : (r.be == 1 ? xt[2] : xt[0]);
-    float yb = r.be == 0 ? yt[1] : (r.be == 1 ? yt[2] : yt[0]);
-    r.psx = fmaf(r.sg, xb - xa, xa);
-    r.psy = fmaf(r.sg, yb - ya, ya);
-    float ddx = r.psx - du, ddy = r.psy - dv;
-    r.d = fmaf(ddx, ddx, ddy * ddy);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        xt[q] = fmaf(t, r.dx[q], r.xc[q]);
+        yt[q] = fmaf(t, r.dy[q], r.yc[q]);
+    }
+    const float xa = b.be == 0 ? xt[0] : (b.be == 1 ? xt[1] : xt[2]);
+    const float ya = b.be == 0 ? yt[0] : (b.be == 1 ? yt[1] : yt[2]);
+    const float xb = b.be == 0 ? xt[1] : (b.be == 1 ? xt[2] : xt[0]);
+    const float yb = b.be == 0 ? yt[1] : (b.be == 1 ? yt[2] : yt[0]);
+    b.psx = fmaf(b.sg, xb - xa, xa);
+    b.psy = fmaf(b.sg, yb - ya, ya);
+    const float ddx = b.psx - du, ddy = b.psy - dv;
+    b.d = fmaf(ddx, ddx, ddy * ddy);
+}
+
+// log2(1 - A) with A = exp(-x): series in A for small A, log of the
+// cancellation-free 1 - A otherwise
+__device__ __forceinline__ float log2_one_minus(float A, float om)
+{
+    if (A < 0.015625f) {
+        float s = fmaf(A, 0.2f, 0.25f);
+        s = fmaf(A, s, 1.0f / 3.0f);
+        s = fmaf(A, s, 0.5f);
+        s = fmaf(A, s, 1.0f);
+        return -A * s * 1.4426950408889634f;
+    }
+    return __log2f(om);
+}
+
+// squared distance from the pixel to the face's box at local time t (lower
+// bound of d of eq 14, since the closest point lies in the triangle)
+__device__ __forceinline__ float box_dist2(const FaceRec &r, float t, float du, float dv)
+{
+    float xt[3], yt[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        xt[q] = fmaf(t, r.dx[q], r.xc[q]);
+        yt[q] = fmaf(t, r.dy[q], r.yc[q]);
+    }
+    const float x0 = fminf(xt[0], fminf(xt[1], xt[2])), x1 = fmaxf(xt[0], fmaxf(xt[1], xt[2]));
+    const float y0 = fminf(yt[0], fminf(yt[1], yt[2])), y1 = fmaxf(yt[0], fmaxf(yt[1], yt[2]));
+    const float ex = fmaxf(fmaxf(x0 - du, du - x1), 0.0f), ey = fmaxf(fmaxf(y0 - dv, dv - y1), 0.0f);
+    return fmaf(ex, ex, ey * ey);
 }
 
 struct TileGeom {
@@ -553,6 +623,9 @@ struct TileGeom {
     double ua, va;   // tile anchor (between the 4 centre pixels) in normalized coordinates
     float du, dv;    // this lane's pixel centre relative to the anchor (exact for W, H powers of 2)
 };
+
+__device__ __forceinline__ float lane_du(int lane, int W) { return (float)(2 * (lane & 7) - 7) / (float)W; }
+__device__ __forceinline__ float lane_dv(int lane, int H) { return (float)(7 - 2 * (lane >> 3)) / (float)H; }
 
 __device__ __forceinline__ bool tile_geom(const RasterArgs &a, TileGeom &g)
 {
@@ -568,8 +641,8 @@ __device__ __forceinline__ bool tile_geom(const RasterArgs &a, TileGeom &g)
     g.inimg = g.px < a.W && g.py < a.H;
     g.ua = (double)(16 * tx + 8 - a.W) / (double)a.W;
     g.va = (double)(a.H - 16 * ty - 8) / (double)a.H;
-    g.du = (float)(2 * (lane & 7) - 7) / (float)a.W;
-    g.dv = (float)(7 - 2 * (lane >> 3)) / (float)a.H;
+    g.du = lane_du(lane, a.W);
+    g.dv = lane_dv(lane, a.H);
     return true;
 }
 
@@ -596,34 +669,105 @@ __device__ __forceinline__ float chunk_centre(const float tau[T], int n)
     return 0.5f * (tau[0] + last);
 }
 
+template <int T>
+struct FwdShared {
+    FaceRec rec[NB];
+    float lsum[T][kWave];   // sum of log2(1 - A) over non-zero factors
+    int nz[T][kWave];       // number of zero factors (A == 1)
+    uint32_t q[2 * kWave];  // background work queue: entry | pixel << 8 | sub-frame mask << 16
+};
+
+template <int T>
+struct BwdShared {
+    FaceRec rec[NB];
+    float P[T][kWave];      // forward product over non-zero factors
+    int nz[T][kWave];
+    float ga[kWave];        // dL/dalpha of the pixel (already divided by K)
+    uint32_t q[2 * kWave];
+    float gacc[NB][NGA];    // per-entry gradient slots
+};
+
+// Stage entries [base, base + nb) of a list into LDS, one per lane.
+template <class SH>
+__device__ __forceinline__ void stage_batch(const RasterArgs &a, SH &sh, int64_t beg, int base, int nb, uint32_t live,
+                                            int s, const TileGeom &g, float tc, bool with_attr)
+{
+    const int lane = threadIdx.x & 63;
+    lds_sync();
+    if (lane < nb) {
+        const uint32_t ent = a.list[beg + base + lane];
+        FaceRec r;
+        stage_rec(a, ent, live, s, g.ua, g.va, tc, with_attr, r);
+        sh.rec[lane] = r;
+    }
+    lds_sync();
+}
+
+// Background queue item evaluation (forward): accumulate log2(1 - A) into
+// the pixel's slot.
+template <int T, int SOLVER>
+__device__ __forceinline__ void bg_process_fwd(const RasterArgs &a, FwdShared<T> &sh, int qh, int cnt,
+                                               const float tau[T], uint32_t xbits, float tc)
+{
+    const int lane = threadIdx.x & 63;
+    lds_sync();
+    if (lane < cnt) {
+        const uint32_t it = sh.q[(qh + lane) & (2 * kWave - 1)];
+        const int e = (int)(it & 0xff), pl = (int)((it >> 8) & 0xff);
+        const uint32_t bits = it >> 16;
+        const FaceRec &r = sh.rec[e];
+        const float du = lane_du(pl, a.W), dv = lane_dv(pl, a.H);
+        Bary<SOLVER> bc;
+        bc.setup(r, tc, du, dv);
+#pragma unroll
+        for (int j = 0; j < T; ++j) {
+            if (!((bits >> j) & 1u)) continue;
+            float N[3];
+            bc.eval(r, tau[j] - tc, N);
+            const float D = N[0] + N[1] + N[2];
+            if (!(fabsf(D) > kTauDet)) continue;
+            BgEval b;
+            bg_eval(r, tc, tau[j], (xbits >> j) & 1u, N, 1.0f / D, du, dv, b);
+            if (!(b.d <= a.dmax)) continue;
+            const float A = exp2f(b.d * a.neg_log2e_over_delta);
+            const float om = one_minus_exp_neg(b.d * a.inv_delta, A);
+            if (om > 0.0f)
+                atomicAdd(&sh.lsum[j][pl], log2_one_minus(A, om));
+            else
+                atomicAdd(&sh.nz[j][pl], 1);
+        }
+    }
+    lds_sync();
+}
+
 template <int T, int SOLVER>
 __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a)
 {
+    __shared__ FwdShared<T> shm[4];
     TileGeom g;
     if (!tile_geom(a, g)) return;
     if (a.hdr->error_bits & kHdrOverflow) return;
     const int lane = threadIdx.x & 63;
+    FwdShared<T> &sh = shm[threadIdx.x >> 6];
     float acc[NCH + 1];
 #pragma unroll
     for (int ch = 0; ch <= NCH; ++ch) acc[ch] = 0.0f;
 
     const int c_end = min((g.grp + 1) * a.G, a.NC);
     for (int c = g.grp * a.G; c < c_end; ++c) {
-        Chunk ck = chunk_info(c, a.K, a.S, a.CPS);
+        const Chunk ck = chunk_info(c, a.K, a.S, a.CPS);
         if (ck.n <= 0) continue;
         const uint32_t live = (1u << ck.n) - 1u;
         float tau[T];
         uint32_t xbits;
         chunk_taus<T>(a, ck, tau, xbits);
-        const float tcen = chunk_centre<T>(tau, ck.n);
-        float zb[T], rgb[T][NCH], P[T];
-        int zid[T], nz[T];
+        const float tc = chunk_centre<T>(tau, ck.n);
+        float zb[T], rgb[T][NCH];
+        int zid[T];
 #pragma unroll
         for (int j = 0; j < T; ++j) {
             zb[j] = FLT_MAX;
             zid[j] = -1;
-            P[j] = 1.0f;
-            nz[j] = 0;
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) rgb[j][ch] = 0.0f;
         }
@@ -633,43 +777,39 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a)
             const int64_t idx = (int64_t)c * a.ntiles + g.tile;
             const int64_t beg = a.off[idx];
             const int n_e = a.cnt[idx];
-            for (int e = 0; e < n_e; ++e) {
-                const uint32_t ent = __builtin_amdgcn_readfirstlane(a.list[beg + e]);
-                const int f = (int)(ent >> 8);
-                const uint32_t msk = ent & live;
-                if (!msk) continue;
-                FaceData fd;
-                load_face(a, f, ck.s, g.ua, g.va, tcen, fd);
-                float at[3][NCH];
+            for (int base = 0; base < n_e; base += NB) {
+                const int nb = min(NB, n_e - base);
+                stage_batch(a, sh, beg, base, nb, live, ck.s, g, tc, true);
+                for (int e = 0; e < nb; ++e) {
+                    const FaceRec &r = sh.rec[e];
+                    const uint32_t msk = __builtin_amdgcn_readfirstlane(r.msk);
+                    if (!msk) continue;
+                    const int f = __builtin_amdgcn_readfirstlane(r.f);
+                    Bary<SOLVER> bc;
+                    bc.setup(r, tc, g.du, g.dv);
 #pragma unroll
-                for (int q = 0; q < 3; ++q)
+                    for (int j = 0; j < T; ++j) {
+                        if (!((msk >> j) & 1u)) continue;
+                        float N[3];
+                        bc.eval(r, tau[j] - tc, N);
+                        const float D = N[0] + N[1] + N[2];
+                        if (!(fabsf(D) > kTauDet)) continue;
+                        const bool cov = D > 0.0f ? fminf(N[0], fminf(N[1], N[2])) >= 0.0f
+                                                  : fmaxf(N[0], fmaxf(N[1], N[2])) <= 0.0f;
+                        if (!cov) continue;
+                        const float invD = 1.0f / D;
+                        float zt[3];
 #pragma unroll
-                    for (int ch = 0; ch < NCH; ++ch)
-                        at[q][ch] = ch < a.C ? a.attrs[(size_t)fd.v[q] * a.C + ch] : 0.0f;
-                Bary<SOLVER> bc;
-                bc.setup(fd, g.du, g.dv);
+                        for (int q = 0; q < 3; ++q) zt[q] = fmaf(tau[j], r.dz[q], r.z0[q]);
+                        const float z = fmaf(N[0], zt[0], fmaf(N[1], zt[1], N[2] * zt[2])) * invD;
+                        if (z < zb[j] || (z == zb[j] && f < zid[j])) {
+                            zb[j] = z;
+                            zid[j] = f;
+                            const float w0 = N[0] * invD, w1 = N[1] * invD, w2 = N[2] * invD;
 #pragma unroll
-                for (int j = 0; j < T; ++j) {
-                    if (!((msk >> j) & 1u)) continue;
-                    float N[3];
-                    bc.eval(fd, tau[j], N);
-                    const float D = N[0] + N[1] + N[2];
-                    if (!(fabsf(D) > kTauDet)) continue;
-                    const bool cov = D > 0.0f ? fminf(N[0], fminf(N[1], N[2])) >= 0.0f
-                                              : fmaxf(N[0], fmaxf(N[1], N[2])) <= 0.0f;
-                    if (!cov) continue;
-                    const float invD = 1.0f / D;
-                    float zt[3];
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) zt[q] = fmaf(tau[j], fd.dz[q], fd.z0[q]);
-                    const float z = fmaf(N[0], zt[0], fmaf(N[1], zt[1], N[2] * zt[2])) * invD;
-                    if (z < zb[j] || (z == zb[j] && f < zid[j])) {
-                        zb[j] = z;
-                        zid[j] = f;
-                        const float w0 = N[0] * invD, w1 = N[1] * invD, w2 = N[2] * invD;
-#pragma unroll
-                        for (int ch = 0; ch < NCH; ++ch)
-                            rgb[j][ch] = fmaf(w0, at[0][ch], fmaf(w1, at[1][ch], w2 * at[2][ch]));
+                            for (int ch = 0; ch < NCH; ++ch)
+                                rgb[j][ch] = fmaf(w0, r.at[0][ch], fmaf(w1, r.at[1][ch], w2 * r.at[2][ch]));
+                        }
                     }
                 }
             }
@@ -678,47 +818,49 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a)
         // ---- background: soft aggregation (eqs 10, 13-15) where uncovered
         uint32_t bgbits = 0;
 #pragma unroll
-        for (int j = 0; j < T; ++j)
+        for (int j = 0; j < T; ++j) {
+            sh.lsum[j][lane] = 0.0f;
+            sh.nz[j][lane] = 0;
             if (__ballot(g.inimg && zid[j] < 0)) bgbits |= 1u << j;
+        }
         bgbits &= live;
         if (bgbits) {
             const int64_t idx = ((int64_t)a.NC + c) * a.ntiles + g.tile;
             const int64_t beg = a.off[idx];
             const int n_e = a.cnt[idx];
-            for (int e = 0; e < n_e; ++e) {
-                const uint32_t ent = __builtin_amdgcn_readfirstlane(a.list[beg + e]);
-                const int f = (int)(ent >> 8);
-                const uint32_t msk = ent & bgbits;
-                if (!msk) continue;
-                FaceData fd;
-                load_face(a, f, ck.s, g.ua, g.va, tcen, fd);
-                EdgeSet es0, es1;
-                if (msk & ~xbits) es0.setup(fd, 0);
-                if (msk & xbits) es1.setup(fd, 1);
-                Bary<SOLVER> bc;
-                bc.setup(fd, g.du, g.dv);
+            int qh = 0, qn = 0;
+            for (int base = 0; base < n_e; base += NB) {
+                const int nb = min(NB, n_e - base);
+                stage_batch(a, sh, beg, base, nb, live, ck.s, g, tc, false);
+                for (int e = 0; e < nb; ++e) {
+                    const FaceRec &r = sh.rec[e];
+                    const uint32_t msk = __builtin_amdgcn_readfirstlane(r.msk) & bgbits;
+                    if (!msk) continue;
+                    uint32_t bits = 0;
 #pragma unroll
-                for (int j = 0; j < T; ++j) {
-                    if (!((msk >> j) & 1u)) continue;
-                    if (!(g.inimg && zid[j] < 0)) continue;
-                    float N[3];
-                    bc.eval(fd, tau[j], N);
-                    const float D = N[0] + N[1] + N[2];
-                    if (!(fabsf(D) > kTauDet)) continue;
-                    BgEval be;
-                    bg_eval(fd, ((xbits >> j) & 1u) ? es1 : es0, tau[j], N, 1.0f / D, g.du, g.dv, be);
-                    if (!(be.d <= a.dmax)) continue;
-                    const float A = exp2f(be.d * a.neg_log2e_over_delta);
-                    const float om = one_minus_exp_neg(be.d * a.inv_delta, A);
-                    if (om > 0.0f)
-                        P[j] *= om;
-                    else
-                        nz[j] += 1;
+                    for (int j = 0; j < T; ++j) {
+                        if (!((msk >> j) & 1u)) continue;
+                        if (g.inimg && zid[j] < 0 && box_dist2(r, tau[j] - tc, g.du, g.dv) <= a.dmax)
+                            bits |= 1u << j;
+                    }
+                    const uint64_t bal = __ballot(bits != 0);
+                    if (!bal) continue;
+                    const int pos = qn + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
+                    if (bits) sh.q[pos & (2 * kWave - 1)] = (uint32_t)e | ((uint32_t)lane << 8) | (bits << 16);
+                    qn += __popcll(bal);
+                    if (qn - qh >= kWave) {
+                        bg_process_fwd<T, SOLVER>(a, sh, qh, kWave, tau, xbits, tc);
+                        qh += kWave;
+                    }
                 }
+                if (qn > qh) bg_process_fwd<T, SOLVER>(a, sh, qh, qn - qh, tau, xbits, tc);
+                qh = qn;
             }
         }
 
         // ---- shade, store visibility, accumulate the sub-frame average
+        lds_sync();
 #pragma unroll
         for (int j = 0; j < T; ++j) {
             if (j >= ck.n) continue;
@@ -733,9 +875,11 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a)
                 a.vis_id[vi] = zid[j];
                 a.vis_p[vi] = 0.0f;
             } else {
-                acc[NCH] += nz[j] > 0 ? 1.0f : 1.0f - P[j];
-                a.vis_id[vi] = -1 - min(nz[j], 2);
-                a.vis_p[vi] = P[j];
+                const int nz = sh.nz[j][lane];
+                const float P = exp2f(sh.lsum[j][lane]);
+                acc[NCH] += nz > 0 ? 1.0f : 1.0f - P;
+                a.vis_id[vi] = -1 - min(nz, 2);
+                a.vis_p[vi] = P;
             }
         }
     }
@@ -769,57 +913,166 @@ struct GradArgs {
     float invK;
 };
 
-template <bool ATTR>
-__device__ __forceinline__ void flush_face(bool hit, float (&gK)[12], float (&gA)[3][NCH], const FaceData &fd, int s,
-                                           const RasterArgs &a, const GradArgs &ga)
+// Add a lane's per-entry contribution to the entry's LDS slot.
+__device__ __forceinline__ void slot_add(float *slot, int i, float v)
 {
-    const uint64_t bal = __ballot(hit);
-    if (!bal) return;
+    if (v != 0.0f) atomicAdd(&slot[i], v);
+}
+
+// Flush the staged entries' gradient slots to global memory and clear them.
+template <int T>
+__device__ __forceinline__ void flush_slots(BwdShared<T> &sh, int nb, int s, const RasterArgs &a, const GradArgs &ga,
+                                            bool with_attr)
+{
     const int lane = threadIdx.x & 63;
-    if (__popcll(bal) <= 2) {
-        if (hit) {
+    lds_sync();
+    if (lane < nb) {
+        const FaceRec &r = sh.rec[lane];
+        float *slot = sh.gacc[lane];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+#pragma unroll
+            for (int sl = 0; sl < 2; ++sl) {
+                float *p = ga.gkf + ((size_t)(s + sl) * a.V + r.v[q]) * 2;
+                const float gx = slot[q * 4 + sl * 2], gy = slot[q * 4 + sl * 2 + 1];
+                if (gx != 0.0f) unsafeAtomicAdd(p, gx);
+                if (gy != 0.0f) unsafeAtomicAdd(p + 1, gy);
+            }
+            if (with_attr)
+                for (int c = 0; c < a.C; ++c) {
+                    const float gv = slot[12 + q * NCH + c];
+                    if (gv != 0.0f) unsafeAtomicAdd(ga.gattr + (size_t)r.v[q] * a.C + c, gv);
+                }
+        }
+#pragma unroll
+        for (int i = 0; i < NGA; ++i) slot[i] = 0.0f;
+    }
+    lds_sync();
+}
+
+// Background adjoint of one queue item: dalpha/dA_j = prod_{m != j}(1 - A_m),
+// dA/dd = -A/delta, then the chain through d = |p - p*|^2, the closest point
+// (edge parameter where unclamped), q = F(X) w and w(tau) (dw = -F^-1 dF w).
+template <int T, int SOLVER>
+__device__ __forceinline__ void bg_process_bwd(const RasterArgs &a, BwdShared<T> &sh, int qh, int cnt,
+                                               const float tau[T], uint32_t xbits, float tc)
+{
+    const int lane = threadIdx.x & 63;
+    lds_sync();
+    if (lane < cnt) {
+        const uint32_t it = sh.q[(qh + lane) & (2 * kWave - 1)];
+        const int e = (int)(it & 0xff), pl = (int)((it >> 8) & 0xff);
+        const uint32_t bits = it >> 16;
+        const FaceRec &r = sh.rec[e];
+        const float du = lane_du(pl, a.W), dv = lane_dv(pl, a.H);
+        const float galpha = sh.ga[pl];
+        Bary<SOLVER> bc;
+        bc.setup(r, tc, du, dv);
+        float gK[12];
+#pragma unroll
+        for (int q = 0; q < 12; ++q) gK[q] = 0.0f;
+#pragma unroll
+        for (int j = 0; j < T; ++j) {
+            if (!((bits >> j) & 1u)) continue;
+            const float t = tau[j] - tc;
+            float N[3];
+            bc.eval(r, t, N);
+            const float D = N[0] + N[1] + N[2];
+            if (!(fabsf(D) > kTauDet)) continue;
+            const float invD = 1.0f / D;
+            const int X = (xbits >> j) & 1u;
+            BgEval b;
+            bg_eval(r, tc, tau[j], X, N, invD, du, dv, b);
+            if (!(b.d <= a.dmax)) continue;
+            const float A = exp2f(b.d * a.neg_log2e_over_delta);
+            const float om = one_minus_exp_neg(b.d * a.inv_delta, A);
+            const int nzc = sh.nz[j][pl];
+            const float P = sh.P[j][pl];
+            const float Pe = nzc == 0 ? P / om : (nzc == 1 ? (om > 0.0f ? 0.0f : P) : 0.0f);
+            const float gd = -galpha * Pe * A * a.inv_delta;
+            if (gd == 0.0f) continue;
+            const float gpx = 2.0f * gd * (b.psx - du), gpy = 2.0f * gd * (b.psy - dv);
+            float xt[3], yt[3];
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
+                xt[q] = fmaf(t, r.dx[q], r.xc[q]);
+                yt[q] = fmaf(t, r.dy[q], r.yc[q]);
+            }
+            // per-vertex gradient at tau (gt) and at keyframe X (gk)
+            float gtx[3], gty[3], gkx[3], gky[3];
 #pragma unroll
-                for (int sl = 0; sl < 2; ++sl) {
-                    float *p = ga.gkf + ((size_t)(s + sl) * a.V + fd.v[q]) * 2;
-                    if (gK[q * 4 + sl * 2] != 0.0f) unsafeAtomicAdd(p, gK[q * 4 + sl * 2]);
-                    if (gK[q * 4 + sl * 2 + 1] != 0.0f) unsafeAtomicAdd(p + 1, gK[q * 4 + sl * 2 + 1]);
+            for (int q = 0; q < 3; ++q) {
+                const float wq = b.be == q ? 1.0f - b.sg : (b.be == (q + 2) % 3 ? b.sg : 0.0f);
+                gtx[q] = wq * gpx;
+                gty[q] = wq * gpy;
+                gkx[q] = 0.0f;
+                gky[q] = 0.0f;
+            }
+            const bool interior = !(b.sr < 0.0f) && !(b.sr > 1.0f);
+            if (interior) {
+                const int ea = b.be;
+                float Ex[3], Ey[3], iee3[3];
+                kedges(r, X, tc, Ex, Ey, iee3);
+                const float exs = ea == 0 ? Ex[0] : (ea == 1 ? Ex[1] : Ex[2]);
+                const float eys = ea == 0 ? Ey[0] : (ea == 1 ? Ey[1] : Ey[2]);
+                const float iee = ea == 0 ? iee3[0] : (ea == 1 ? iee3[1] : iee3[2]);
+                // edge ea+2 (from vertex ea+2 back to ea): v_{ea+2} - v_ea = -E_{ea+2}
+                const float e2x = ea == 0 ? Ex[2] : (ea == 1 ? Ex[0] : Ex[1]);
+                const float e2y = ea == 0 ? Ey[2] : (ea == 1 ? Ey[0] : Ey[1]);
+                const float xa = ea == 0 ? xt[0] : (ea == 1 ? xt[1] : xt[2]);
+                const float ya = ea == 0 ? yt[0] : (ea == 1 ? yt[1] : yt[2]);
+                const float xb = ea == 0 ? xt[1] : (ea == 1 ? xt[2] : xt[0]);
+                const float yb = ea == 0 ? yt[1] : (ea == 1 ? yt[2] : yt[0]);
+                const float gsig = fmaf(gpx, xb - xa, gpy * (yb - ya));
+                const float rx = b.rx, ry = b.ry;
+                const float grx = gsig * exs * iee, gry = gsig * eys * iee;
+                const float gex = gsig * fmaf(-2.0f * b.sr, exs, rx) * iee;
+                const float gey = gsig * fmaf(-2.0f * b.sr, eys, ry) * iee;
+                // dL/dw_i = g_r . (v_i - v_ea): 0, E_ea, -E_{ea+2} for i = ea, ea+1, ea+2
+                const float g1 = fmaf(grx, exs, gry * eys), g2 = -fmaf(grx, e2x, gry * e2y);
+                float gwq[3];
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    const bool isa = ea == q, isb = ea == (q + 2) % 3;
+                    gkx[q] = fmaf(b.w[q], grx, isa ? -grx - gex : (isb ? gex : 0.0f));
+                    gky[q] = fmaf(b.w[q], gry, isa ? -gry - gey : (isb ? gey : 0.0f));
+                    gwq[q] = isa ? 0.0f : (isb ? g1 : g2);
                 }
-                if (ATTR)
-                    for (int ch = 0; ch < a.C; ++ch)
-                        if (gA[q][ch] != 0.0f) unsafeAtomicAdd(ga.gattr + (size_t)fd.v[q] * a.C + ch, gA[q][ch]);
+                const float gxs =
+                    fmaf(gwq[0], yt[1] - yt[2], fmaf(gwq[1], yt[2] - yt[0], gwq[2] * (yt[0] - yt[1]))) * invD;
+                const float gys =
+                    fmaf(gwq[0], xt[2] - xt[1], fmaf(gwq[1], xt[0] - xt[2], gwq[2] * (xt[1] - xt[0]))) * invD;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    gtx[q] = fmaf(-b.w[q], gxs, gtx[q]);
+                    gty[q] = fmaf(-b.w[q], gys, gty[q]);
+                }
+            }
+            const float t1 = tau[j], t0 = 1.0f - tau[j];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                gK[q * 4 + 0] += fmaf(t0, gtx[q], X ? 0.0f : gkx[q]);
+                gK[q * 4 + 1] += fmaf(t0, gty[q], X ? 0.0f : gky[q]);
+                gK[q * 4 + 2] += fmaf(t1, gtx[q], X ? gkx[q] : 0.0f);
+                gK[q * 4 + 3] += fmaf(t1, gty[q], X ? gky[q] : 0.0f);
             }
         }
-        return;
-    }
+        float *slot = sh.gacc[e];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-#pragma unroll
-        for (int sl = 0; sl < 2; ++sl) {
-            float sx = wave_sum(hit ? gK[q * 4 + sl * 2] : 0.0f);
-            float sy = wave_sum(hit ? gK[q * 4 + sl * 2 + 1] : 0.0f);
-            if (lane == 0) {
-                float *p = ga.gkf + ((size_t)(s + sl) * a.V + fd.v[q]) * 2;
-                unsafeAtomicAdd(p, sx);
-                unsafeAtomicAdd(p + 1, sy);
-            }
-        }
-        if (ATTR)
-            for (int ch = 0; ch < a.C; ++ch) {
-                float sa = wave_sum(hit ? gA[q][ch] : 0.0f);
-                if (lane == 0) unsafeAtomicAdd(ga.gattr + (size_t)fd.v[q] * a.C + ch, sa);
-            }
+        for (int q = 0; q < 12; ++q) slot_add(slot, q, gK[q]);
     }
+    lds_sync();
 }
 
 template <int T, int SOLVER>
 __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a, GradArgs ga)
 {
+    __shared__ BwdShared<T> shm[4];
     TileGeom g;
     if (!tile_geom(a, g)) return;
     if (a.hdr->error_bits & kHdrOverflow) return;
     const int lane = threadIdx.x & 63;
+    BwdShared<T> &sh = shm[threadIdx.x >> 6];
     float gI[NCH + 1];
 #pragma unroll
     for (int ch = 0; ch <= NCH; ++ch) gI[ch] = 0.0f;
@@ -827,28 +1080,31 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a, GradArgs ga)
         for (int ch = 0; ch < a.C; ++ch) gI[ch] = ga.grad_image[((size_t)ch * a.H + g.py) * a.W + g.px] * ga.invK;
         gI[NCH] = ga.grad_image[((size_t)a.C * a.H + g.py) * a.W + g.px] * ga.invK;
     }
-    const float galpha = gI[NCH];
+    sh.ga[lane] = gI[NCH];
+    if (lane < NB)
+        for (int i = 0; i < NGA; ++i) sh.gacc[lane][i] = 0.0f;
 
     const int c_end = min((g.grp + 1) * a.G, a.NC);
     for (int c = g.grp * a.G; c < c_end; ++c) {
-        Chunk ck = chunk_info(c, a.K, a.S, a.CPS);
+        const Chunk ck = chunk_info(c, a.K, a.S, a.CPS);
         if (ck.n <= 0) continue;
         const uint32_t live = (1u << ck.n) - 1u;
         float tau[T];
         uint32_t xbits;
         chunk_taus<T>(a, ck, tau, xbits);
-        const float tcen = chunk_centre<T>(tau, ck.n);
+        const float tc = chunk_centre<T>(tau, ck.n);
         int vid[T];
-        float vp[T];
 #pragma unroll
         for (int j = 0; j < T; ++j) {
             vid[j] = -4;
-            vp[j] = 0.0f;
+            float vp = 0.0f;
             if (j < ck.n) {
                 const size_t vi = ((size_t)g.tile * a.K + (ck.k0 + j)) * kWave + lane;
                 vid[j] = a.vis_id[vi];
-                vp[j] = a.vis_p[vi];
+                vp = a.vis_p[vi];
             }
+            sh.P[j][lane] = vp;
+            sh.nz[j][lane] = vid[j] <= -1 && vid[j] >= -3 ? -1 - vid[j] : 0;
         }
 
         // ---- foreground: dL/dw through the static solve (dw = -F^-1 dF w)
@@ -860,181 +1116,124 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a, GradArgs ga)
             const int64_t idx = (int64_t)c * a.ntiles + g.tile;
             const int64_t beg = a.off[idx];
             const int n_e = a.cnt[idx];
-            for (int e = 0; e < n_e; ++e) {
-                const uint32_t ent = __builtin_amdgcn_readfirstlane(a.list[beg + e]);
-                const int f = (int)(ent >> 8);
-                uint32_t hits = 0;
+            for (int base = 0; base < n_e; base += NB) {
+                const int nb = min(NB, n_e - base);
+                stage_batch(a, sh, beg, base, nb, live, ck.s, g, tc, true);
+                for (int e = 0; e < nb; ++e) {
+                    const FaceRec &r = sh.rec[e];
+                    const int f = __builtin_amdgcn_readfirstlane(r.f);
+                    uint32_t hits = 0;
 #pragma unroll
-                for (int j = 0; j < T; ++j)
-                    if (vid[j] == f) hits |= 1u << j;
-                const uint32_t msk = wave_or(hits) & ent & fgbits;
-                if (!msk) continue;
-                FaceData fd;
-                load_face(a, f, ck.s, g.ua, g.va, tcen, fd);
-                float at[3][NCH];
-#pragma unroll
-                for (int q = 0; q < 3; ++q)
-#pragma unroll
-                    for (int ch = 0; ch < NCH; ++ch)
-                        at[q][ch] = ch < a.C ? a.attrs[(size_t)fd.v[q] * a.C + ch] : 0.0f;
-                float gw[3];
-#pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    gw[q] = 0.0f;
-#pragma unroll
-                    for (int ch = 0; ch < NCH; ++ch) gw[q] = fmaf(gI[ch], at[q][ch], gw[q]);
-                }
-                Bary<SOLVER> bc;
-                bc.setup(fd, g.du, g.dv);
-                float gK[12], gA[3][NCH];
-#pragma unroll
-                for (int q = 0; q < 12; ++q) gK[q] = 0.0f;
-#pragma unroll
-                for (int q = 0; q < 3; ++q)
-#pragma unroll
-                    for (int ch = 0; ch < NCH; ++ch) gA[q][ch] = 0.0f;
-                bool hit = false;
-#pragma unroll
-                for (int j = 0; j < T; ++j) {
-                    if (!((msk >> j) & 1u)) continue;
-                    if (vid[j] != f) continue;
-                    float N[3];
-                    bc.eval(fd, tau[j], N);
-                    const float invD = 1.0f / (N[0] + N[1] + N[2]);
-                    const float w[3] = {N[0] * invD, N[1] * invD, N[2] * invD};
-                    float xt[3], yt[3];
-                    pos_at(fd, tau[j], xt, yt);
-                    const float gxs =
-                        fmaf(gw[0], yt[1] - yt[2], fmaf(gw[1], yt[2] - yt[0], gw[2] * (yt[0] - yt[1]))) * invD;
-                    const float gys =
-                        fmaf(gw[0], xt[2] - xt[1], fmaf(gw[1], xt[0] - xt[2], gw[2] * (xt[1] - xt[0]))) * invD;
-                    const float t1 = tau[j], t0 = 1.0f - tau[j];
+                    for (int j = 0; j < T; ++j)
+                        if (vid[j] == f) hits |= 1u << j;
+                    const uint32_t msk = wave_or(hits) & __builtin_amdgcn_readfirstlane(r.msk) & fgbits;
+                    if (!msk) continue;
+                    float gw[3];
 #pragma unroll
                     for (int q = 0; q < 3; ++q) {
-                        const float gx = -w[q] * gxs, gy = -w[q] * gys;
-                        gK[q * 4 + 0] = fmaf(t0, gx, gK[q * 4 + 0]);
-                        gK[q * 4 + 1] = fmaf(t0, gy, gK[q * 4 + 1]);
-                        gK[q * 4 + 2] = fmaf(t1, gx, gK[q * 4 + 2]);
-                        gK[q * 4 + 3] = fmaf(t1, gy, gK[q * 4 + 3]);
+                        gw[q] = 0.0f;
 #pragma unroll
-                        for (int ch = 0; ch < NCH; ++ch) gA[q][ch] = fmaf(w[q], gI[ch], gA[q][ch]);
+                        for (int ch = 0; ch < NCH; ++ch) gw[q] = fmaf(gI[ch], r.at[q][ch], gw[q]);
                     }
-                    hit = true;
+                    Bary<SOLVER> bc;
+                    bc.setup(r, tc, g.du, g.dv);
+                    float gK[12], gA[3][NCH];
+#pragma unroll
+                    for (int q = 0; q < 12; ++q) gK[q] = 0.0f;
+#pragma unroll
+                    for (int q = 0; q < 3; ++q)
+#pragma unroll
+                        for (int ch = 0; ch < NCH; ++ch) gA[q][ch] = 0.0f;
+                    bool hit = false;
+#pragma unroll
+                    for (int j = 0; j < T; ++j) {
+                        if (!((msk >> j) & 1u)) continue;
+                        if (vid[j] != f) continue;
+                        const float t = tau[j] - tc;
+                        float N[3];
+                        bc.eval(r, t, N);
+                        const float invD = 1.0f / (N[0] + N[1] + N[2]);
+                        const float w[3] = {N[0] * invD, N[1] * invD, N[2] * invD};
+                        float xt[3], yt[3];
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) {
+                            xt[q] = fmaf(t, r.dx[q], r.xc[q]);
+                            yt[q] = fmaf(t, r.dy[q], r.yc[q]);
+                        }
+                        const float gxs =
+                            fmaf(gw[0], yt[1] - yt[2], fmaf(gw[1], yt[2] - yt[0], gw[2] * (yt[0] - yt[1]))) * invD;
+                        const float gys =
+                            fmaf(gw[0], xt[2] - xt[1], fmaf(gw[1], xt[0] - xt[2], gw[2] * (xt[1] - xt[0]))) * invD;
+                        const float t1 = tau[j], t0 = 1.0f - tau[j];
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) {
+                            const float gx = -w[q] * gxs, gy = -w[q] * gys;
+                            gK[q * 4 + 0] = fmaf(t0, gx, gK[q * 4 + 0]);
+                            gK[q * 4 + 1] = fmaf(t0, gy, gK[q * 4 + 1]);
+                            gK[q * 4 + 2] = fmaf(t1, gx, gK[q * 4 + 2]);
+                            gK[q * 4 + 3] = fmaf(t1, gy, gK[q * 4 + 3]);
+#pragma unroll
+                            for (int ch = 0; ch < NCH; ++ch) gA[q][ch] = fmaf(w[q], gI[ch], gA[q][ch]);
+                        }
+                        hit = true;
+                    }
+                    if (hit) {
+                        float *slot = sh.gacc[e];
+#pragma unroll
+                        for (int q = 0; q < 12; ++q) slot_add(slot, q, gK[q]);
+#pragma unroll
+                        for (int q = 0; q < 3; ++q)
+#pragma unroll
+                            for (int ch = 0; ch < NCH; ++ch) slot_add(slot, 12 + q * NCH + ch, gA[q][ch]);
+                    }
                 }
-                flush_face<true>(hit, gK, gA, fd, ck.s, a, ga);
+                flush_slots<T>(sh, nb, ck.s, a, ga, true);
             }
         }
 
-        // ---- background: dalpha/dA_j = prod_{m != j} (1 - A_m), chain
-        //      through d, the closest point, q = F(X) w and w(tau)
+        // ---- background
         uint32_t bgbits = 0;
 #pragma unroll
         for (int j = 0; j < T; ++j)
-            if (__ballot(vid[j] <= -1 && vid[j] >= -3 && galpha != 0.0f)) bgbits |= 1u << j;
+            if (__ballot(vid[j] <= -1 && vid[j] >= -3 && gI[NCH] != 0.0f)) bgbits |= 1u << j;
         bgbits &= live;
         if (bgbits) {
             const int64_t idx = ((int64_t)a.NC + c) * a.ntiles + g.tile;
             const int64_t beg = a.off[idx];
             const int n_e = a.cnt[idx];
-            for (int e = 0; e < n_e; ++e) {
-                const uint32_t ent = __builtin_amdgcn_readfirstlane(a.list[beg + e]);
-                const int f = (int)(ent >> 8);
-                const uint32_t msk = ent & bgbits;
-                if (!msk) continue;
-                FaceData fd;
-                load_face(a, f, ck.s, g.ua, g.va, tcen, fd);
-                EdgeSet es0, es1;
-                if (msk & ~xbits) es0.setup(fd, 0);
-                if (msk & xbits) es1.setup(fd, 1);
-                Bary<SOLVER> bc;
-                bc.setup(fd, g.du, g.dv);
-                float gK[12];
-                float gA[3][NCH];
+            int qh = 0, qn = 0;
+            for (int base = 0; base < n_e; base += NB) {
+                const int nb = min(NB, n_e - base);
+                stage_batch(a, sh, beg, base, nb, live, ck.s, g, tc, false);
+                for (int e = 0; e < nb; ++e) {
+                    const FaceRec &r = sh.rec[e];
+                    const uint32_t msk = __builtin_amdgcn_readfirstlane(r.msk) & bgbits;
+                    if (!msk) continue;
+                    uint32_t bits = 0;
 #pragma unroll
-                for (int q = 0; q < 12; ++q) gK[q] = 0.0f;
-                bool hit = false;
-#pragma unroll
-                for (int j = 0; j < T; ++j) {
-                    if (!((msk >> j) & 1u)) continue;
-                    if (!(vid[j] <= -1 && vid[j] >= -3)) continue;
-                    float N[3];
-                    bc.eval(fd, tau[j], N);
-                    const float D = N[0] + N[1] + N[2];
-                    if (!(fabsf(D) > kTauDet)) continue;
-                    const float invD = 1.0f / D;
-                    const int X = (xbits >> j) & 1u;
-                    const EdgeSet &es = X ? es1 : es0;
-                    BgEval be;
-                    bg_eval(fd, es, tau[j], N, invD, g.du, g.dv, be);
-                    if (!(be.d <= a.dmax)) continue;
-                    const float A = exp2f(be.d * a.neg_log2e_over_delta);
-                    const float om = one_minus_exp_neg(be.d * a.inv_delta, A);
-                    const int nzc = -1 - vid[j];
-                    const float Pe = nzc == 0 ? vp[j] / om : (nzc == 1 ? (om > 0.0f ? 0.0f : vp[j]) : 0.0f);
-                    const float gd = -galpha * Pe * A * a.inv_delta;
-                    if (gd == 0.0f) continue;
-                    hit = true;
-                    // d = |p* - p|^2, p* = (1 - sg) v_a(tau) + sg v_b(tau)
-                    const float gpx = 2.0f * gd * (be.psx - g.du), gpy = 2.0f * gd * (be.psy - g.dv);
-                    float xt[3], yt[3];
-                    pos_at(fd, tau[j], xt, yt);
-                    // per-vertex gradient at tau (gt) and at keyframe X (gk)
-                    float gtx[3], gty[3], gkx[3], gky[3];
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) {
-                        const float wq = be.be == q ? 1.0f - be.sg : (be.be == (q + 2) % 3 ? be.sg : 0.0f);
-                        gtx[q] = wq * gpx;
-                        gty[q] = wq * gpy;
-                        gkx[q] = 0.0f;
-                        gky[q] = 0.0f;
+                    for (int j = 0; j < T; ++j) {
+                        if (!((msk >> j) & 1u)) continue;
+                        if (vid[j] <= -1 && vid[j] >= -3 && gI[NCH] != 0.0f &&
+                            box_dist2(r, tau[j] - tc, g.du, g.dv) <= a.dmax)
+                            bits |= 1u << j;
                     }
-                    const bool interior = !(be.sr < 0.0f) && !(be.sr > 1.0f);
-                    if (interior) {
-                        const int ea = be.be;
-                        const float exs = ea == 0 ? es.ex[0] : (ea == 1 ? es.ex[1] : es.ex[2]);
-                        const float eys = ea == 0 ? es.ey[0] : (ea == 1 ? es.ey[1] : es.ey[2]);
-                        const float iee = ea == 0 ? es.inv_ee[0] : (ea == 1 ? es.inv_ee[1] : es.inv_ee[2]);
-                        const float axs = ea == 0 ? es.ax[0] : (ea == 1 ? es.ax[1] : es.ax[2]);
-                        const float ays = ea == 0 ? es.ay[0] : (ea == 1 ? es.ay[1] : es.ay[2]);
-                        const float xa = ea == 0 ? xt[0] : (ea == 1 ? xt[1] : xt[2]);
-                        const float ya = ea == 0 ? yt[0] : (ea == 1 ? yt[1] : yt[2]);
-                        const float xb = ea == 0 ? xt[1] : (ea == 1 ? xt[2] : xt[0]);
-                        const float yb = ea == 0 ? yt[1] : (ea == 1 ? yt[2] : yt[0]);
-                        const float gsig = fmaf(gpx, xb - xa, gpy * (yb - ya));
-                        const float rx = be.qx - axs, ry = be.qy - ays;
-                        const float grx = gsig * exs * iee, gry = gsig * eys * iee;
-                        const float gex = gsig * fmaf(-2.0f * be.sr, exs, rx) * iee;
-                        const float gey = gsig * fmaf(-2.0f * be.sr, eys, ry) * iee;
-                        float gwq[3];
-#pragma unroll
-                        for (int q = 0; q < 3; ++q) {
-                            const bool isa = ea == q, isb = ea == (q + 2) % 3;
-                            gkx[q] = fmaf(be.w[q], grx, isa ? -grx - gex : (isb ? gex : 0.0f));
-                            gky[q] = fmaf(be.w[q], gry, isa ? -gry - gey : (isb ? gey : 0.0f));
-                            gwq[q] = fmaf(grx, es.ax[q], gry * es.ay[q]);
-                        }
-                        const float gxs =
-                            fmaf(gwq[0], yt[1] - yt[2], fmaf(gwq[1], yt[2] - yt[0], gwq[2] * (yt[0] - yt[1]))) * invD;
-                        const float gys =
-                            fmaf(gwq[0], xt[2] - xt[1], fmaf(gwq[1], xt[0] - xt[2], gwq[2] * (xt[1] - xt[0]))) * invD;
-#pragma unroll
-                        for (int q = 0; q < 3; ++q) {
-                            gtx[q] = fmaf(-be.w[q], gxs, gtx[q]);
-                            gty[q] = fmaf(-be.w[q], gys, gty[q]);
-                        }
-                    }
-                    const float t1 = tau[j], t0 = 1.0f - tau[j];
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) {
-                        gK[q * 4 + 0] += fmaf(t0, gtx[q], X ? 0.0f : gkx[q]);
-                        gK[q * 4 + 1] += fmaf(t0, gty[q], X ? 0.0f : gky[q]);
-                        gK[q * 4 + 2] += fmaf(t1, gtx[q], X ? gkx[q] : 0.0f);
-                        gK[q * 4 + 3] += fmaf(t1, gty[q], X ? gky[q] : 0.0f);
+                    const uint64_t bal = __ballot(bits != 0);
+                    if (!bal) continue;
+                    const int pos = qn + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
+                    if (bits) sh.q[pos & (2 * kWave - 1)] = (uint32_t)e | ((uint32_t)lane << 8) | (bits << 16);
+                    qn += __popcll(bal);
+                    if (qn - qh >= kWave) {
+                        bg_process_bwd<T, SOLVER>(a, sh, qh, kWave, tau, xbits, tc);
+                        qh += kWave;
                     }
                 }
-                flush_face<false>(hit, gK, gA, fd, ck.s, a, ga);
+                if (qn > qh) bg_process_bwd<T, SOLVER>(a, sh, qh, qn - qh, tau, xbits, tc);
+                qh = qn;
+                flush_slots<T>(sh, nb, ck.s, a, ga, false);
             }
         }
+        lds_sync();
     }
 }
 

@@ -40,7 +40,7 @@ def image_errors(gpu, orc, flags, rows=None):
         gpu = gpu[:, rows[0]:rows[1]:rows[2]]
         orc = orc[:, rows[0]:rows[1]:rows[2]]
         flags = flags[rows[0]:rows[1]:rows[2]]
-    ok = flags == 0
+    ok = (flags & 1) == 0          # bit 0: value within rounding distance of a flip
     errs = []
     for c in range(orc.shape[0]):
         scale = max(np.abs(orc[c]).max(), 1e-30)

@@ -1,8 +1,10 @@
 """Gradient parity of the HIP adjoint (through the C ABI) with the FP64
 oracle's adjoint and with central finite differences of the oracle's
 frozen-decision surrogate.  Bar: relative L2 error <= 1e-3, separately for
-vertex positions and attributes.  Pixels the oracle flags as within rounding
-distance of a decision flip get zero upstream gradient."""
+vertex positions and attributes.  Pixels the oracle flags (either bit: a
+decision within rounding distance of flipping that moves the value, or that
+changes which vertices receive gradient, e.g. the closest point's edge
+parameter at a clamp bound) get zero upstream gradient."""
 import numpy as np
 import pytest
 
@@ -18,7 +20,7 @@ pytestmark = pytest.mark.gpu
 def _grad_case(sc, solver="fast", chunk_len=4, seed=0):
     ref = oracle.render(sc, flags=True)
     G = np.random.default_rng(seed).normal(size=ref.image.shape)
-    G[:, ref.flags > 0] = 0.0
+    G[:, ref.flags != 0] = 0.0
     og = oracle.render(sc, grad_image=G)
     img, state, st = gpu_forward(sc, solver=solver, chunk_len=chunk_len)
     gv, ga = gpu_backward(st, state, G)
@@ -61,7 +63,7 @@ def test_medium_gradient_vs_frozen_fd_64_vertices():
     base = oracle.render(sc, rows=rows, flags=True, record=True)
     G = np.zeros_like(base.image)
     G[:, rows[0]:rows[1]:rows[2]] = np.random.default_rng(7).normal(size=G[:, ::rows[2]].shape)
-    G[:, base.flags > 0] = 0.0
+    G[:, base.flags != 0] = 0.0
     og = oracle.render(sc, rows=rows, grad_image=G)
     img, state, st = gpu_forward(sc)
     gv, _ = gpu_backward(st, state, G)

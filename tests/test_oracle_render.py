@@ -260,7 +260,8 @@ def test_counters_and_invariants_on_small_workload():
     # a closed surface: every foreground pixel-subframe is covered by an even
     # number of faces (front and back), >= 2
     assert c["cover_pairs"] >= 2 * c["fg_pixsub"]
-    assert (r.flags > 0).sum() <= 0.01 * sc.width * sc.height
+    assert ((r.flags & 1) > 0).sum() <= 0.01 * sc.width * sc.height
+    assert (r.flags > 0).sum() <= 0.03 * sc.width * sc.height
     assert 0.0 <= r.image.min() and r.image[3].max() <= 1.0
 
 
@@ -274,4 +275,4 @@ def test_guard_band_flags_edge_on_pixel_centres():
     #  a centre on the diagonal is ambiguous: both faces sit on their edge)
     sc2 = wl.square_scene(center_px=(0.0, 0.25), half_px=3.3, shift_px=0.0, width=W, height=H, k=1)
     r2 = oracle.render(sc2, flags=True)
-    assert r2.flags.sum() == 0
+    assert (r2.flags & 1).sum() == 0
