@@ -336,25 +336,34 @@ __global__ void k_scan3(int64_t *__restrict__ off, const int64_t *__restrict__ b
 
 // ----------------------------------------------------------------- raster
 //
-// One 64-lane wave per (8x8 tile, group of chunks), lane = pixel.  For each
-// chunk the wave walks its two lists in batches of NB entries.  A batch is
-// staged in LDS by the whole wave at once, one entry per lane: the entry's
-// face indices and double keyframes are gathered in parallel and turned into
-// a FaceRec of float32 anchor-local coordinates, so the per-face setup costs
-// one lane instead of every lane, and one round of memory latency per batch
-// instead of one per entry.
+// One 64-lane wave per (8x8 tile, group of chunks).  For each chunk the wave
+// walks its foreground list, then its background list, NB entries at a time.
 //
-//  * foreground: every lane tests every staged face against its pixel for
-//    each sub-frame of the entry's mask (z-buffer in registers, eq 9);
-//  * background: a cheap lower bound of the squared distance (pixel to the
-//    face's box at the sub-frame) selects the (pixel, face, sub-frame mask)
-//    triples that can reach d <= d_max; they are appended to an LDS queue and
-//    evaluated 64 at a time with every lane busy.  The soft product of eq 15
-//    is accumulated as sum log2(1 - A) with LDS atomics (zero factors counted
-//    apart).
-//  * backward: same walks; per-entry gradient slots in LDS gather the
-//    contributions of all lanes, and are flushed to global memory with one
-//    atomic per non-zero value and batch.
+//  * staging: lane e gathers entry e's face indices and double keyframes and
+//    forms a FaceRec of float32 coordinates relative to the tile anchor at the
+//    chunk's middle time.  It also forms, per sub-frame of the chunk, the
+//    64-bit mask of tile pixels the entry can reach (its box at that
+//    sub-frame, grown by the influence radius for the background, restricted
+//    to the pixels still in question) and their union U_e.
+//  * items: a batch's work is the set of (entry, pixel) pairs with the pixel
+//    in U_e.  An exclusive scan over the entries numbers them and they are
+//    dealt out 64 at a time, one per lane, so a face that reaches 3 pixels of
+//    the tile costs 3 lane-evaluations instead of 64.  An item carries the
+//    sub-frames where its pixel is in the entry's mask; the fast solver's
+//    coefficients are formed once per item and evaluated per sub-frame.
+//  * foreground (eq 9): items update an LDS z-buffer by a 64-bit atomic min
+//    of (depth bits, face index), which keeps the lowest face index on exact
+//    depth ties.  Afterwards each (pixel, sub-frame) shades its winner from
+//    the face's keyframes.
+//  * background (eqs 10, 13-15): items on uncovered pixels accumulate
+//    sum log2(1 - A) per (pixel, sub-frame) with LDS float atomics, zero
+//    factors counted apart.
+//  * backward: the same item walk over the background list.  The foreground
+//    goes the other way round: each (pixel, sub-frame) knows its winning face
+//    from the forward, finds it among the staged entries through a small LDS
+//    hash table and is queued for that entry.  Per-entry LDS gradient slots
+//    collect the items' contributions and are added to global memory with
+//    one atomic per non-zero value and batch.
 
 struct RasterArgs {
     const double2 *kf;
@@ -369,13 +378,16 @@ struct RasterArgs {
     float *part;
     const DevHeader *hdr;
     int V, F, C, S, K, W, H, tiles_x, ntiles, CPS, NC, G, NG;
-    float dmax, neg_log2e_over_delta, inv_delta;
+    float dmax, halo, neg_log2e_over_delta, inv_delta;
     int64_t cap;
 };
 
 constexpr int NCH = RB_MAX_CHANNELS;
-constexpr int NB = 32;        // list entries staged per batch
+constexpr int NB = 32;              // list entries staged per batch
 constexpr int NGA = 12 + 3 * NCH;   // per-entry gradient slot: 3 vertices x 2 keyframes x (x, y), attributes
+constexpr int kHash = 128;          // face -> staged entry table (NB keys at most)
+
+enum { kRecFg = 0, kRecBg = 1, kRecGeom = 2 };
 
 // One list entry staged in LDS.  Edge i runs from vertex (i+1)%3 to (i+2)%3.
 struct __align__(16) FaceRec {
@@ -383,14 +395,12 @@ struct __align__(16) FaceRec {
     float dx[3], dy[3];       // segment displacement
     float e0x[3], e0y[3];     // edge i at the segment start
     float e1x[3], e1y[3];     // edge i at the segment end
-    float iee0[3], iee1[3];   // 1 / |edge i|^2 at start / end (0 for a degenerate edge)
-    float z0[3], dz[3];       // camera depth at the start and its change
-    float at[3][NCH];         // vertex attributes
-    int v[3];
+    float aux0[3], aux1[3];   // foreground: camera depth at the start and its change;
+                              // background: 1/|edge i|^2 at the start and the end (0 if degenerate)
     int f;
     uint32_t msk;             // sub-frames of the chunk this entry touches
-    int pad[3];
 };
+static_assert(sizeof(FaceRec) == 128, "FaceRec layout");
 
 __device__ __forceinline__ void lds_sync()
 {
@@ -400,17 +410,15 @@ __device__ __forceinline__ void lds_sync()
     __asm__ volatile("" ::: "memory");
 }
 
-__device__ __forceinline__ void stage_rec(const RasterArgs &a, uint32_t ent, uint32_t live, int s, double ua,
-                                          double va, float tc, bool with_attr, FaceRec &r)
+__device__ __forceinline__ void stage_rec(const RasterArgs &a, int f, int s, double ua, double va, float tc, int kind,
+                                          FaceRec &r, int vid[3])
 {
-    const int f = (int)(ent >> 8);
     r.f = f;
-    r.msk = ent & live;
     double X0[3], Y0[3], X1[3], Y1[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
         const int v = clampi(a.faces[3 * f + q], 0, a.V - 1);
-        r.v[q] = v;
+        vid[q] = v;
         const double2 p = a.kf[(size_t)s * a.V + v];
         const double2 e = a.kf[(size_t)(s + 1) * a.V + v];
         X0[q] = p.x;
@@ -421,11 +429,11 @@ __device__ __forceinline__ void stage_rec(const RasterArgs &a, uint32_t ent, uin
         r.yc[q] = (float)(fma((double)tc, e.y - p.y, p.y) - va);
         r.dx[q] = (float)(e.x - p.x);
         r.dy[q] = (float)(e.y - p.y);
-        const float z0 = a.kfz[(size_t)s * a.V + v], z1 = a.kfz[(size_t)(s + 1) * a.V + v];
-        r.z0[q] = z0;
-        r.dz[q] = z1 - z0;
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) r.at[q][c] = (with_attr && c < a.C) ? a.attrs[(size_t)v * a.C + c] : 0.0f;
+        if (kind == kRecFg) {
+            const float z0 = a.kfz[(size_t)s * a.V + v], z1 = a.kfz[(size_t)(s + 1) * a.V + v];
+            r.aux0[q] = z0;
+            r.aux1[q] = z1 - z0;
+        }
     }
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -435,9 +443,15 @@ __device__ __forceinline__ void stage_rec(const RasterArgs &a, uint32_t ent, uin
         r.e0y[i] = (float)ay;
         r.e1x[i] = (float)bx;
         r.e1y[i] = (float)by;
-        const double ea = ax * ax + ay * ay, eb = bx * bx + by * by;
-        r.iee0[i] = ea > 0.0 ? (float)(1.0 / ea) : 0.0f;
-        r.iee1[i] = eb > 0.0 ? (float)(1.0 / eb) : 0.0f;
+        if (kind == kRecBg) {
+            const double ea = ax * ax + ay * ay, eb = bx * bx + by * by;
+            r.aux0[i] = ea > 0.0 ? (float)(1.0 / ea) : 0.0f;
+            r.aux1[i] = eb > 0.0 ? (float)(1.0 / eb) : 0.0f;
+        }
+    }
+    if (kind == kRecGeom) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) r.aux0[i] = r.aux1[i] = 0.0f;
     }
 }
 
@@ -536,7 +550,7 @@ __device__ __forceinline__ void kedges(const FaceRec &r, int X, float tc, float 
         const int i = (e + 2) % 3, b = (e + 1) % 3;
         Ex[e] = kx[b] - kx[e];
         Ey[e] = ky[b] - ky[e];
-        iee[e] = X ? r.iee1[i] : r.iee0[i];
+        iee[e] = X ? r.aux1[i] : r.aux0[i];
     }
 }
 
@@ -601,22 +615,6 @@ __device__ __forceinline__ float log2_one_minus(float A, float om)
     return __log2f(om);
 }
 
-// squared distance from the pixel to the face's box at local time t (lower
-// bound of d of eq 14, since the closest point lies in the triangle)
-__device__ __forceinline__ float box_dist2(const FaceRec &r, float t, float du, float dv)
-{
-    float xt[3], yt[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        xt[q] = fmaf(t, r.dx[q], r.xc[q]);
-        yt[q] = fmaf(t, r.dy[q], r.yc[q]);
-    }
-    const float x0 = fminf(xt[0], fminf(xt[1], xt[2])), x1 = fmaxf(xt[0], fmaxf(xt[1], xt[2]));
-    const float y0 = fminf(yt[0], fminf(yt[1], yt[2])), y1 = fmaxf(yt[0], fmaxf(yt[1], yt[2]));
-    const float ex = fmaxf(fmaxf(x0 - du, du - x1), 0.0f), ey = fmaxf(fmaxf(y0 - dv, dv - y1), 0.0f);
-    return fmaf(ex, ex, ey * ey);
-}
-
 struct TileGeom {
     int tile, grp, px, py;
     bool inimg;
@@ -646,15 +644,24 @@ __device__ __forceinline__ bool tile_geom(const RasterArgs &a, TileGeom &g)
     return true;
 }
 
+// local time of sub-frame j of a chunk and whether eq 13 takes the segment's
+// end keyframe (tau > 1/2, decided in integers)
+__device__ __forceinline__ float chunk_tau(const RasterArgs &a, const Chunk &ch, int j, int &X)
+{
+    const int rem = (ch.k0 + j) * a.S - ch.s * (a.K - 1);
+    X = 2 * rem > a.K - 1 ? 1 : 0;
+    return a.K > 1 ? (float)rem / (float)(a.K - 1) : 0.0f;
+}
+
 template <int T>
 __device__ __forceinline__ void chunk_taus(const RasterArgs &a, const Chunk &ch, float tau[T], uint32_t &xbits)
 {
     xbits = 0;
 #pragma unroll
     for (int j = 0; j < T; ++j) {
-        int rem = (ch.k0 + j) * a.S - ch.s * (a.K - 1);
-        tau[j] = a.K > 1 ? (float)rem / (float)(a.K - 1) : 0.0f;
-        if (j < ch.n && 2 * rem > a.K - 1) xbits |= 1u << j;
+        int X;
+        tau[j] = chunk_tau(a, ch, j, X);
+        if (j < ch.n && X) xbits |= 1u << j;
     }
 }
 
@@ -669,75 +676,273 @@ __device__ __forceinline__ float chunk_centre(const float tau[T], int n)
     return 0.5f * (tau[0] + last);
 }
 
-template <int T>
-struct FwdShared {
-    FaceRec rec[NB];
-    float lsum[T][kWave];   // sum of log2(1 - A) over non-zero factors
-    int nz[T][kWave];       // number of zero factors (A == 1)
-    uint32_t q[2 * kWave];  // background work queue: entry | pixel << 8 | sub-frame mask << 16
-};
+// ------------------------------------------------------------ item machinery
 
-template <int T>
-struct BwdShared {
-    FaceRec rec[NB];
-    float P[T][kWave];      // forward product over non-zero factors
-    int nz[T][kWave];
-    float ga[kWave];        // dL/dalpha of the pixel (already divided by K)
-    uint32_t q[2 * kWave];
-    float gacc[NB][NGA];    // per-entry gradient slots
-};
-
-// Stage entries [base, base + nb) of a list into LDS, one per lane.
-template <class SH>
-__device__ __forceinline__ void stage_batch(const RasterArgs &a, SH &sh, int64_t beg, int base, int nb, uint32_t live,
-                                            int s, const TileGeom &g, float tc, bool with_attr)
+// mask of the tile pixels whose centres lie in [x0 - g, x1 + g] x [y0 - g, y1 + g]
+// (anchor-local; bit = 8 * row + column), with a margin of 0.05 pixel so that
+// the box never cuts off a pixel the exact test below would accept
+__device__ __forceinline__ uint64_t rect_mask(float x0, float x1, float y0, float y1, float g, float W, float H)
 {
-    const int lane = threadIdx.x & 63;
-    lds_sync();
-    if (lane < nb) {
-        const uint32_t ent = a.list[beg + base + lane];
-        FaceRec r;
-        stage_rec(a, ent, live, s, g.ua, g.va, tc, with_attr, r);
-        sh.rec[lane] = r;
-    }
-    lds_sync();
+    // column c has centre du = (2c - 7)/W, row r has dv = (7 - 2r)/H
+    const float ca = fmaf(x0 - g, W, 7.0f) * 0.5f - 0.05f, cb = fmaf(x1 + g, W, 7.0f) * 0.5f + 0.05f;
+    const float ra = (7.0f - (y1 + g) * H) * 0.5f - 0.05f, rb = (7.0f - (y0 - g) * H) * 0.5f + 0.05f;
+    const int c0 = max((int)ceilf(fmaxf(ca, -1.0f)), 0), c1 = min((int)floorf(fminf(cb, 8.0f)), 7);
+    const int r0 = max((int)ceilf(fmaxf(ra, -1.0f)), 0), r1 = min((int)floorf(fminf(rb, 8.0f)), 7);
+    if (c0 > c1 || r0 > r1) return 0ull;
+    const uint64_t row = (uint64_t)((0xffu >> (7 - c1 + c0)) << c0);
+    const uint64_t hi = r1 == 7 ? ~0ull : ((1ull << (8 * (r1 + 1))) - 1ull);
+    const uint64_t lo = (1ull << (8 * r0)) - 1ull;
+    return (row * 0x0101010101010101ull) & hi & ~lo;
 }
 
-// Background queue item evaluation (forward): accumulate log2(1 - A) into
-// the pixel's slot.
-template <int T, int SOLVER>
-__device__ __forceinline__ void bg_process_fwd(const RasterArgs &a, FwdShared<T> &sh, int qh, int cnt,
-                                               const float tau[T], uint32_t xbits, float tc)
+// position of the r-th set bit (r < popcount(m))
+__device__ __forceinline__ int select64(uint64_t m, int r)
+{
+    uint32_t x = (uint32_t)m;
+    int base = 0;
+    int c = __popc(x);
+    if (r >= c) {
+        r -= c;
+        x = (uint32_t)(m >> 32);
+        base = 32;
+    }
+    c = __popc(x & 0xffffu);
+    if (r >= c) {
+        r -= c;
+        x >>= 16;
+        base += 16;
+    }
+    c = __popc(x & 0xffu);
+    if (r >= c) {
+        r -= c;
+        x >>= 8;
+        base += 8;
+    }
+    c = __popc(x & 0xfu);
+    if (r >= c) {
+        r -= c;
+        x >>= 4;
+        base += 4;
+    }
+    c = __popc(x & 0x3u);
+    if (r >= c) {
+        r -= c;
+        x >>= 2;
+        base += 2;
+    }
+    return base + (r >= (int)(x & 1u) ? 1 : 0);
+}
+
+__device__ __forceinline__ int wave_incl_scan(int x)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ int lane_rank(uint64_t bal)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
+}
+
+// Item bookkeeping shared by the forward and backward walks.
+template <int T>
+struct ItemShared {
+    FaceRec rec[NB];
+    uint64_t m[NB][T];   // per entry and sub-frame: pixels to evaluate
+    uint64_t U[NB];      // union over the sub-frames
+    int pre[NB];         // number of the entry's first item
+    int ne[NB];          // entries with at least one item, in order
+    uint8_t flag[kWave];
+};
+
+// Stage entries [first, first + nb) of a list (one per lane) with their
+// per-sub-frame pixel masks; allow[j] is the set of pixels in question at
+// sub-frame j (0 for sub-frames outside the chunk).  Returns the number of
+// items; cnt / pre are the lane's entry's item count and first item.
+template <int T>
+__device__ __forceinline__ int stage_items(const RasterArgs &a, ItemShared<T> &sh, int64_t first, int nb, int s,
+                                           const TileGeom &g, float tc, const float tau[T], int kind, float grow,
+                                           const uint64_t allow[T], float (*at)[3][NCH], int (*vids)[3], int &cnt,
+                                           int &pre)
 {
     const int lane = threadIdx.x & 63;
     lds_sync();
-    if (lane < cnt) {
-        const uint32_t it = sh.q[(qh + lane) & (2 * kWave - 1)];
-        const int e = (int)(it & 0xff), pl = (int)((it >> 8) & 0xff);
-        const uint32_t bits = it >> 16;
-        const FaceRec &r = sh.rec[e];
-        const float du = lane_du(pl, a.W), dv = lane_dv(pl, a.H);
-        Bary<SOLVER> bc;
-        bc.setup(r, tc, du, dv);
+    cnt = 0;
+    if (lane < nb) {
+        const uint32_t ent = a.list[first + lane];
+        FaceRec r;
+        int vid[3];
+        stage_rec(a, (int)(ent >> 8), s, g.ua, g.va, tc, kind, r, vid);
+        uint32_t msk = 0;
+        uint64_t U = 0;
 #pragma unroll
         for (int j = 0; j < T; ++j) {
-            if (!((bits >> j) & 1u)) continue;
-            float N[3];
-            bc.eval(r, tau[j] - tc, N);
-            const float D = N[0] + N[1] + N[2];
-            if (!(fabsf(D) > kTauDet)) continue;
-            BgEval b;
-            bg_eval(r, tc, tau[j], (xbits >> j) & 1u, N, 1.0f / D, du, dv, b);
-            if (!(b.d <= a.dmax)) continue;
-            const float A = exp2f(b.d * a.neg_log2e_over_delta);
-            const float om = one_minus_exp_neg(b.d * a.inv_delta, A);
-            if (om > 0.0f)
-                atomicAdd(&sh.lsum[j][pl], log2_one_minus(A, om));
-            else
-                atomicAdd(&sh.nz[j][pl], 1);
+            uint64_t mj = 0;
+            if (((ent >> j) & 1u) && allow[j]) {
+                const float t = tau[j] - tc;
+                float x0 = FLT_MAX, x1 = -FLT_MAX, y0 = FLT_MAX, y1 = -FLT_MAX;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    const float xt = fmaf(t, r.dx[q], r.xc[q]), yt = fmaf(t, r.dy[q], r.yc[q]);
+                    x0 = fminf(x0, xt);
+                    x1 = fmaxf(x1, xt);
+                    y0 = fminf(y0, yt);
+                    y1 = fmaxf(y1, yt);
+                }
+                mj = rect_mask(x0, x1, y0, y1, grow, (float)a.W, (float)a.H) & allow[j];
+            }
+            sh.m[lane][j] = mj;
+            if (mj) msk |= 1u << j;
+            U |= mj;
         }
+        r.msk = msk;
+        sh.rec[lane] = r;
+        sh.U[lane] = U;
+        if (at) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) at[lane][q][c] = c < a.C ? a.attrs[(size_t)vid[q] * a.C + c] : 0.0f;
+        }
+        if (vids) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) vids[lane][q] = vid[q];
+        }
+        cnt = __popcll(U);
+    }
+    const int incl = wave_incl_scan(cnt);
+    pre = incl - cnt;
+    const uint64_t bal = __ballot(cnt > 0);
+    if (cnt > 0) {
+        sh.pre[lane] = pre;
+        sh.ne[lane_rank(bal)] = lane;
     }
     lds_sync();
+    return __shfl(incl, 63, 64);
+}
+
+// Deal the batch's items out 64 at a time: fn(entry, pixel) on one lane each.
+template <int T, class Fn>
+__device__ __forceinline__ void for_items(ItemShared<T> &sh, int total, int cnt, int pre, Fn &&fn)
+{
+    const int lane = threadIdx.x & 63;
+    const uint64_t upto = lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1ull);
+    for (int rb = 0; rb < total; rb += kWave) {
+        sh.flag[lane] = 0;
+        lds_sync();
+        // entries whose first item falls in this round (distinct positions)
+        if (cnt > 0 && pre >= rb && pre < rb + kWave) sh.flag[pre - rb] = 1;
+        const int c0 = __popcll(__ballot(cnt > 0 && pre <= rb)) - 1;
+        lds_sync();
+        const uint64_t B = __ballot(sh.flag[lane] != 0);
+        if (rb + lane < total) {
+            const int e = sh.ne[c0 + __popcll(B & upto & ~1ull)];
+            const int p = select64(sh.U[e], rb + lane - sh.pre[e]);
+            fn(e, p);
+        }
+        lds_sync();
+    }
+}
+
+// ------------------------------------------------------------------ forward
+
+template <int T>
+struct FwdShared {
+    ItemShared<T> it;
+    union {
+        unsigned long long zb[T][kWave];   // foreground: depth bits << 32 | face
+        struct {
+            float lsum[T][kWave];          // sum of log2(1 - A) over non-zero factors
+            int nz[T][kWave];              // number of zero factors (A == 1)
+        } bg;
+    } u;
+};
+
+// foreground item: coverage (eqs 1-3 / 8) and depth test (eq 9) per sub-frame
+template <int T, int SOLVER>
+__device__ __forceinline__ void fg_item(const RasterArgs &a, FwdShared<T> &sh, int e, int p, const float tau[T],
+                                        float tc)
+{
+    const FaceRec &r = sh.it.rec[e];
+    const float du = lane_du(p, a.W), dv = lane_dv(p, a.H);
+    Bary<SOLVER> bc;
+    bc.setup(r, tc, du, dv);
+    const unsigned long long f = (uint32_t)r.f;
+#pragma unroll
+    for (int j = 0; j < T; ++j) {
+        if (!((sh.it.m[e][j] >> p) & 1ull)) continue;
+        float N[3];
+        bc.eval(r, tau[j] - tc, N);
+        const float D = N[0] + N[1] + N[2];
+        if (!(fabsf(D) > kTauDet)) continue;
+        const bool cov = D > 0.0f ? fminf(N[0], fminf(N[1], N[2])) >= 0.0f : fmaxf(N[0], fmaxf(N[1], N[2])) <= 0.0f;
+        if (!cov) continue;
+        const float invD = 1.0f / D;
+        float zt[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) zt[q] = fmaf(tau[j], r.aux1[q], r.aux0[q]);
+        const float z = fmaf(N[0], zt[0], fmaf(N[1], zt[1], N[2] * zt[2])) * invD;
+        // z > 0 (all vertices in front of the camera), so its bits order like its value
+        atomicMin(&sh.u.zb[j][p], ((unsigned long long)__float_as_uint(z) << 32) | f);
+    }
+}
+
+// background item: eqs 10, 13-15, accumulated as log2(1 - A)
+template <int T, int SOLVER>
+__device__ __forceinline__ void bg_item_fwd(const RasterArgs &a, FwdShared<T> &sh, int e, int p, const float tau[T],
+                                            uint32_t xbits, float tc)
+{
+    const FaceRec &r = sh.it.rec[e];
+    const float du = lane_du(p, a.W), dv = lane_dv(p, a.H);
+    Bary<SOLVER> bc;
+    bc.setup(r, tc, du, dv);
+#pragma unroll
+    for (int j = 0; j < T; ++j) {
+        if (!((sh.it.m[e][j] >> p) & 1ull)) continue;
+        float N[3];
+        bc.eval(r, tau[j] - tc, N);
+        const float D = N[0] + N[1] + N[2];
+        if (!(fabsf(D) > kTauDet)) continue;
+        BgEval b;
+        bg_eval(r, tc, tau[j], (xbits >> j) & 1u, N, 1.0f / D, du, dv, b);
+        if (!(b.d <= a.dmax)) continue;
+        const float A = exp2f(b.d * a.neg_log2e_over_delta);
+        const float om = one_minus_exp_neg(b.d * a.inv_delta, A);
+        if (om > 0.0f)
+            atomicAdd(&sh.u.bg.lsum[j][p], log2_one_minus(A, om));
+        else
+            atomicAdd(&sh.u.bg.nz[j][p], 1);
+    }
+}
+
+// colour of the winning face at this lane's pixel: barycentric interpolation
+// of the vertex attributes (eq 9), from the same float32 record the depth
+// test used
+template <int SOLVER>
+__device__ __forceinline__ void shade_winner(const RasterArgs &a, int f, int s, const TileGeom &g, float tc, float tau,
+                                             float rgb[NCH])
+{
+    FaceRec r;
+    int vid[3];
+    stage_rec(a, f, s, g.ua, g.va, tc, kRecGeom, r, vid);
+    Bary<SOLVER> bc;
+    bc.setup(r, tc, g.du, g.dv);
+    float N[3];
+    bc.eval(r, tau - tc, N);
+    const float invD = 1.0f / (N[0] + N[1] + N[2]);
+    const float w0 = N[0] * invD, w1 = N[1] * invD, w2 = N[2] * invD;
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+        float at[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) at[q] = ch < a.C ? a.attrs[(size_t)vid[q] * a.C + ch] : 0.0f;
+        rgb[ch] = fmaf(w0, at[0], fmaf(w1, at[1], w2 * at[2]));
+    }
 }
 
 template <int T, int SOLVER>
@@ -749,6 +954,7 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a)
     if (a.hdr->error_bits & kHdrOverflow) return;
     const int lane = threadIdx.x & 63;
     FwdShared<T> &sh = shm[threadIdx.x >> 6];
+    const uint64_t inimg = __ballot(g.inimg);
     float acc[NCH + 1];
 #pragma unroll
     for (int ch = 0; ch <= NCH; ++ch) acc[ch] = 0.0f;
@@ -757,105 +963,60 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a)
     for (int c = g.grp * a.G; c < c_end; ++c) {
         const Chunk ck = chunk_info(c, a.K, a.S, a.CPS);
         if (ck.n <= 0) continue;
-        const uint32_t live = (1u << ck.n) - 1u;
         float tau[T];
         uint32_t xbits;
         chunk_taus<T>(a, ck, tau, xbits);
         const float tc = chunk_centre<T>(tau, ck.n);
-        float zb[T], rgb[T][NCH];
-        int zid[T];
+        uint64_t allow[T];
 #pragma unroll
-        for (int j = 0; j < T; ++j) {
-            zb[j] = FLT_MAX;
-            zid[j] = -1;
-#pragma unroll
-            for (int ch = 0; ch < NCH; ++ch) rgb[j][ch] = 0.0f;
-        }
+        for (int j = 0; j < T; ++j) allow[j] = j < ck.n ? inimg : 0ull;
 
         // ---- foreground: z-buffer over the tile's foreground list (eq 9)
+        lds_sync();
+#pragma unroll
+        for (int j = 0; j < T; ++j) sh.u.zb[j][lane] = ~0ull;
         {
             const int64_t idx = (int64_t)c * a.ntiles + g.tile;
             const int64_t beg = a.off[idx];
             const int n_e = a.cnt[idx];
             for (int base = 0; base < n_e; base += NB) {
                 const int nb = min(NB, n_e - base);
-                stage_batch(a, sh, beg, base, nb, live, ck.s, g, tc, true);
-                for (int e = 0; e < nb; ++e) {
-                    const FaceRec &r = sh.rec[e];
-                    const uint32_t msk = __builtin_amdgcn_readfirstlane(r.msk);
-                    if (!msk) continue;
-                    const int f = __builtin_amdgcn_readfirstlane(r.f);
-                    Bary<SOLVER> bc;
-                    bc.setup(r, tc, g.du, g.dv);
-#pragma unroll
-                    for (int j = 0; j < T; ++j) {
-                        if (!((msk >> j) & 1u)) continue;
-                        float N[3];
-                        bc.eval(r, tau[j] - tc, N);
-                        const float D = N[0] + N[1] + N[2];
-                        if (!(fabsf(D) > kTauDet)) continue;
-                        const bool cov = D > 0.0f ? fminf(N[0], fminf(N[1], N[2])) >= 0.0f
-                                                  : fmaxf(N[0], fmaxf(N[1], N[2])) <= 0.0f;
-                        if (!cov) continue;
-                        const float invD = 1.0f / D;
-                        float zt[3];
-#pragma unroll
-                        for (int q = 0; q < 3; ++q) zt[q] = fmaf(tau[j], r.dz[q], r.z0[q]);
-                        const float z = fmaf(N[0], zt[0], fmaf(N[1], zt[1], N[2] * zt[2])) * invD;
-                        if (z < zb[j] || (z == zb[j] && f < zid[j])) {
-                            zb[j] = z;
-                            zid[j] = f;
-                            const float w0 = N[0] * invD, w1 = N[1] * invD, w2 = N[2] * invD;
-#pragma unroll
-                            for (int ch = 0; ch < NCH; ++ch)
-                                rgb[j][ch] = fmaf(w0, r.at[0][ch], fmaf(w1, r.at[1][ch], w2 * r.at[2][ch]));
-                        }
-                    }
-                }
+                int cnt, pre;
+                const int total = stage_items<T>(a, sh.it, beg + base, nb, ck.s, g, tc, tau, kRecFg, 0.0f, allow,
+                                                 nullptr, nullptr, cnt, pre);
+                for_items<T>(sh.it, total, cnt, pre, [&](int e, int p) { fg_item<T, SOLVER>(a, sh, e, p, tau, tc); });
             }
+        }
+        lds_sync();
+        int zid[T];
+        uint64_t unc[T];
+        bool anybg = false;
+#pragma unroll
+        for (int j = 0; j < T; ++j) {
+            const unsigned long long key = sh.u.zb[j][lane];
+            zid[j] = key == ~0ull ? -1 : (int)(uint32_t)key;
+            unc[j] = __ballot(zid[j] < 0) & allow[j];
+            anybg = anybg || unc[j] != 0ull;
+        }
+        lds_sync();
+#pragma unroll
+        for (int j = 0; j < T; ++j) {
+            sh.u.bg.lsum[j][lane] = 0.0f;
+            sh.u.bg.nz[j][lane] = 0;
         }
 
         // ---- background: soft aggregation (eqs 10, 13-15) where uncovered
-        uint32_t bgbits = 0;
-#pragma unroll
-        for (int j = 0; j < T; ++j) {
-            sh.lsum[j][lane] = 0.0f;
-            sh.nz[j][lane] = 0;
-            if (__ballot(g.inimg && zid[j] < 0)) bgbits |= 1u << j;
-        }
-        bgbits &= live;
-        if (bgbits) {
+        if (anybg) {
             const int64_t idx = ((int64_t)a.NC + c) * a.ntiles + g.tile;
             const int64_t beg = a.off[idx];
             const int n_e = a.cnt[idx];
-            int qh = 0, qn = 0;
             for (int base = 0; base < n_e; base += NB) {
                 const int nb = min(NB, n_e - base);
-                stage_batch(a, sh, beg, base, nb, live, ck.s, g, tc, false);
-                for (int e = 0; e < nb; ++e) {
-                    const FaceRec &r = sh.rec[e];
-                    const uint32_t msk = __builtin_amdgcn_readfirstlane(r.msk) & bgbits;
-                    if (!msk) continue;
-                    uint32_t bits = 0;
-#pragma unroll
-                    for (int j = 0; j < T; ++j) {
-                        if (!((msk >> j) & 1u)) continue;
-                        if (g.inimg && zid[j] < 0 && box_dist2(r, tau[j] - tc, g.du, g.dv) <= a.dmax)
-                            bits |= 1u << j;
-                    }
-                    const uint64_t bal = __ballot(bits != 0);
-                    if (!bal) continue;
-                    const int pos = qn + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
-                    if (bits) sh.q[pos & (2 * kWave - 1)] = (uint32_t)e | ((uint32_t)lane << 8) | (bits << 16);
-                    qn += __popcll(bal);
-                    if (qn - qh >= kWave) {
-                        bg_process_fwd<T, SOLVER>(a, sh, qh, kWave, tau, xbits, tc);
-                        qh += kWave;
-                    }
-                }
-                if (qn > qh) bg_process_fwd<T, SOLVER>(a, sh, qh, qn - qh, tau, xbits, tc);
-                qh = qn;
+                int cnt, pre;
+                const int total = stage_items<T>(a, sh.it, beg + base, nb, ck.s, g, tc, tau, kRecBg, a.halo, unc,
+                                                 nullptr, nullptr, cnt, pre);
+                for_items<T>(sh.it, total, cnt, pre,
+                             [&](int e, int p) { bg_item_fwd<T, SOLVER>(a, sh, e, p, tau, xbits, tc); });
             }
         }
 
@@ -869,14 +1030,16 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a)
                 a.vis_id[vi] = -4;
                 a.vis_p[vi] = 0.0f;
             } else if (zid[j] >= 0) {
+                float rgb[NCH];
+                shade_winner<SOLVER>(a, zid[j], ck.s, g, tc, tau[j], rgb);
 #pragma unroll
-                for (int ch = 0; ch < NCH; ++ch) acc[ch] += rgb[j][ch];
+                for (int ch = 0; ch < NCH; ++ch) acc[ch] += rgb[ch];
                 acc[NCH] += 1.0f;
                 a.vis_id[vi] = zid[j];
                 a.vis_p[vi] = 0.0f;
             } else {
-                const int nz = sh.nz[j][lane];
-                const float P = exp2f(sh.lsum[j][lane]);
+                const int nz = sh.u.bg.nz[j][lane];
+                const float P = exp2f(sh.u.bg.lsum[j][lane]);
                 acc[NCH] += nz > 0 ? 1.0f : 1.0f - P;
                 a.vis_id[vi] = -1 - min(nz, 2);
                 a.vis_p[vi] = P;
@@ -913,6 +1076,22 @@ struct GradArgs {
     float invK;
 };
 
+template <int T>
+struct BwdShared {
+    ItemShared<T> it;
+    float at[NB][3][NCH];     // staged entries' vertex attributes (foreground)
+    int vid[NB][3];           // staged entries' vertex indices
+    float gacc[NB][NGA];      // per-entry gradient slots
+    float P[T][kWave];        // forward product over non-zero factors
+    int nz[T][kWave];
+    float gI[NCH + 1][kWave]; // dL/d(colour, alpha) of each pixel, already divided by K
+    int hkey[kHash];          // face -> staged entry (open addressing, -1 = empty)
+    int hval[kHash];
+    uint32_t q[T * kWave];    // foreground items: entry | pixel << 8 | sub-frame << 16
+};
+
+__device__ __forceinline__ int hash_face(int f) { return (int)(((uint32_t)f * 2654435761u) >> 25); }
+
 // Add a lane's per-entry contribution to the entry's LDS slot.
 __device__ __forceinline__ void slot_add(float *slot, int i, float v)
 {
@@ -927,13 +1106,13 @@ __device__ __forceinline__ void flush_slots(BwdShared<T> &sh, int nb, int s, con
     const int lane = threadIdx.x & 63;
     lds_sync();
     if (lane < nb) {
-        const FaceRec &r = sh.rec[lane];
         float *slot = sh.gacc[lane];
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
+            const int v = sh.vid[lane][q];
 #pragma unroll
             for (int sl = 0; sl < 2; ++sl) {
-                float *p = ga.gkf + ((size_t)(s + sl) * a.V + r.v[q]) * 2;
+                float *p = ga.gkf + ((size_t)(s + sl) * a.V + v) * 2;
                 const float gx = slot[q * 4 + sl * 2], gy = slot[q * 4 + sl * 2 + 1];
                 if (gx != 0.0f) unsafeAtomicAdd(p, gx);
                 if (gy != 0.0f) unsafeAtomicAdd(p + 1, gy);
@@ -941,7 +1120,7 @@ __device__ __forceinline__ void flush_slots(BwdShared<T> &sh, int nb, int s, con
             if (with_attr)
                 for (int c = 0; c < a.C; ++c) {
                     const float gv = slot[12 + q * NCH + c];
-                    if (gv != 0.0f) unsafeAtomicAdd(ga.gattr + (size_t)r.v[q] * a.C + c, gv);
+                    if (gv != 0.0f) unsafeAtomicAdd(ga.gattr + (size_t)v * a.C + c, gv);
                 }
         }
 #pragma unroll
@@ -950,118 +1129,154 @@ __device__ __forceinline__ void flush_slots(BwdShared<T> &sh, int nb, int s, con
     lds_sync();
 }
 
-// Background adjoint of one queue item: dalpha/dA_j = prod_{m != j}(1 - A_m),
+// Foreground adjoint of one (pixel, sub-frame) whose winner is staged entry e:
+// colour = sum_i w_i c_i, dL/dw through the static solve (dw = -F^-1 dF w),
+// dL/dc_i = w_i dL/dcolour.
+template <int T, int SOLVER>
+__device__ __forceinline__ void fg_item_bwd(const RasterArgs &a, BwdShared<T> &sh, int e, int p, float tau, float tc)
+{
+    const FaceRec &r = sh.it.rec[e];
+    const float du = lane_du(p, a.W), dv = lane_dv(p, a.H);
+    float gI[NCH], gw[3];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) gI[ch] = sh.gI[ch][p];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        gw[q] = 0.0f;
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) gw[q] = fmaf(gI[ch], sh.at[e][q][ch], gw[q]);
+    }
+    Bary<SOLVER> bc;
+    bc.setup(r, tc, du, dv);
+    const float t = tau - tc;
+    float N[3];
+    bc.eval(r, t, N);
+    const float invD = 1.0f / (N[0] + N[1] + N[2]);
+    const float w[3] = {N[0] * invD, N[1] * invD, N[2] * invD};
+    float xt[3], yt[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        xt[q] = fmaf(t, r.dx[q], r.xc[q]);
+        yt[q] = fmaf(t, r.dy[q], r.yc[q]);
+    }
+    const float gxs = fmaf(gw[0], yt[1] - yt[2], fmaf(gw[1], yt[2] - yt[0], gw[2] * (yt[0] - yt[1]))) * invD;
+    const float gys = fmaf(gw[0], xt[2] - xt[1], fmaf(gw[1], xt[0] - xt[2], gw[2] * (xt[1] - xt[0]))) * invD;
+    const float t1 = tau, t0 = 1.0f - tau;
+    float *slot = sh.gacc[e];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const float gx = -w[q] * gxs, gy = -w[q] * gys;
+        slot_add(slot, q * 4 + 0, t0 * gx);
+        slot_add(slot, q * 4 + 1, t0 * gy);
+        slot_add(slot, q * 4 + 2, t1 * gx);
+        slot_add(slot, q * 4 + 3, t1 * gy);
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) slot_add(slot, 12 + q * NCH + ch, w[q] * gI[ch]);
+    }
+}
+
+// Background adjoint of one item: dalpha/dA_j = prod_{m != j}(1 - A_m),
 // dA/dd = -A/delta, then the chain through d = |p - p*|^2, the closest point
 // (edge parameter where unclamped), q = F(X) w and w(tau) (dw = -F^-1 dF w).
 template <int T, int SOLVER>
-__device__ __forceinline__ void bg_process_bwd(const RasterArgs &a, BwdShared<T> &sh, int qh, int cnt,
-                                               const float tau[T], uint32_t xbits, float tc)
+__device__ __forceinline__ void bg_item_bwd(const RasterArgs &a, BwdShared<T> &sh, int e, int p, const float tau[T],
+                                            uint32_t xbits, float tc)
 {
-    const int lane = threadIdx.x & 63;
-    lds_sync();
-    if (lane < cnt) {
-        const uint32_t it = sh.q[(qh + lane) & (2 * kWave - 1)];
-        const int e = (int)(it & 0xff), pl = (int)((it >> 8) & 0xff);
-        const uint32_t bits = it >> 16;
-        const FaceRec &r = sh.rec[e];
-        const float du = lane_du(pl, a.W), dv = lane_dv(pl, a.H);
-        const float galpha = sh.ga[pl];
-        Bary<SOLVER> bc;
-        bc.setup(r, tc, du, dv);
-        float gK[12];
+    const FaceRec &r = sh.it.rec[e];
+    const float du = lane_du(p, a.W), dv = lane_dv(p, a.H);
+    const float galpha = sh.gI[NCH][p];
+    Bary<SOLVER> bc;
+    bc.setup(r, tc, du, dv);
+    float gK[12];
 #pragma unroll
-        for (int q = 0; q < 12; ++q) gK[q] = 0.0f;
+    for (int q = 0; q < 12; ++q) gK[q] = 0.0f;
 #pragma unroll
-        for (int j = 0; j < T; ++j) {
-            if (!((bits >> j) & 1u)) continue;
-            const float t = tau[j] - tc;
-            float N[3];
-            bc.eval(r, t, N);
-            const float D = N[0] + N[1] + N[2];
-            if (!(fabsf(D) > kTauDet)) continue;
-            const float invD = 1.0f / D;
-            const int X = (xbits >> j) & 1u;
-            BgEval b;
-            bg_eval(r, tc, tau[j], X, N, invD, du, dv, b);
-            if (!(b.d <= a.dmax)) continue;
-            const float A = exp2f(b.d * a.neg_log2e_over_delta);
-            const float om = one_minus_exp_neg(b.d * a.inv_delta, A);
-            const int nzc = sh.nz[j][pl];
-            const float P = sh.P[j][pl];
-            const float Pe = nzc == 0 ? P / om : (nzc == 1 ? (om > 0.0f ? 0.0f : P) : 0.0f);
-            const float gd = -galpha * Pe * A * a.inv_delta;
-            if (gd == 0.0f) continue;
-            const float gpx = 2.0f * gd * (b.psx - du), gpy = 2.0f * gd * (b.psy - dv);
-            float xt[3], yt[3];
+    for (int j = 0; j < T; ++j) {
+        if (!((sh.it.m[e][j] >> p) & 1ull)) continue;
+        const float t = tau[j] - tc;
+        float N[3];
+        bc.eval(r, t, N);
+        const float D = N[0] + N[1] + N[2];
+        if (!(fabsf(D) > kTauDet)) continue;
+        const float invD = 1.0f / D;
+        const int X = (xbits >> j) & 1u;
+        BgEval b;
+        bg_eval(r, tc, tau[j], X, N, invD, du, dv, b);
+        if (!(b.d <= a.dmax)) continue;
+        const float A = exp2f(b.d * a.neg_log2e_over_delta);
+        const float om = one_minus_exp_neg(b.d * a.inv_delta, A);
+        const int nzc = sh.nz[j][p];
+        const float P = sh.P[j][p];
+        const float Pe = nzc == 0 ? P / om : (nzc == 1 ? (om > 0.0f ? 0.0f : P) : 0.0f);
+        const float gd = -galpha * Pe * A * a.inv_delta;
+        if (gd == 0.0f) continue;
+        const float gpx = 2.0f * gd * (b.psx - du), gpy = 2.0f * gd * (b.psy - dv);
+        float xt[3], yt[3];
 #pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                xt[q] = fmaf(t, r.dx[q], r.xc[q]);
-                yt[q] = fmaf(t, r.dy[q], r.yc[q]);
-            }
-            // per-vertex gradient at tau (gt) and at keyframe X (gk)
-            float gtx[3], gty[3], gkx[3], gky[3];
+        for (int q = 0; q < 3; ++q) {
+            xt[q] = fmaf(t, r.dx[q], r.xc[q]);
+            yt[q] = fmaf(t, r.dy[q], r.yc[q]);
+        }
+        // per-vertex gradient at tau (gt) and at keyframe X (gk)
+        float gtx[3], gty[3], gkx[3], gky[3];
 #pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                const float wq = b.be == q ? 1.0f - b.sg : (b.be == (q + 2) % 3 ? b.sg : 0.0f);
-                gtx[q] = wq * gpx;
-                gty[q] = wq * gpy;
-                gkx[q] = 0.0f;
-                gky[q] = 0.0f;
-            }
-            const bool interior = !(b.sr < 0.0f) && !(b.sr > 1.0f);
-            if (interior) {
-                const int ea = b.be;
-                float Ex[3], Ey[3], iee3[3];
-                kedges(r, X, tc, Ex, Ey, iee3);
-                const float exs = ea == 0 ? Ex[0] : (ea == 1 ? Ex[1] : Ex[2]);
-                const float eys = ea == 0 ? Ey[0] : (ea == 1 ? Ey[1] : Ey[2]);
-                const float iee = ea == 0 ? iee3[0] : (ea == 1 ? iee3[1] : iee3[2]);
-                // edge ea+2 (from vertex ea+2 back to ea): v_{ea+2} - v_ea = -E_{ea+2}
-                const float e2x = ea == 0 ? Ex[2] : (ea == 1 ? Ex[0] : Ex[1]);
-                const float e2y = ea == 0 ? Ey[2] : (ea == 1 ? Ey[0] : Ey[1]);
-                const float xa = ea == 0 ? xt[0] : (ea == 1 ? xt[1] : xt[2]);
-                const float ya = ea == 0 ? yt[0] : (ea == 1 ? yt[1] : yt[2]);
-                const float xb = ea == 0 ? xt[1] : (ea == 1 ? xt[2] : xt[0]);
-                const float yb = ea == 0 ? yt[1] : (ea == 1 ? yt[2] : yt[0]);
-                const float gsig = fmaf(gpx, xb - xa, gpy * (yb - ya));
-                const float rx = b.rx, ry = b.ry;
-                const float grx = gsig * exs * iee, gry = gsig * eys * iee;
-                const float gex = gsig * fmaf(-2.0f * b.sr, exs, rx) * iee;
-                const float gey = gsig * fmaf(-2.0f * b.sr, eys, ry) * iee;
-                // dL/dw_i = g_r . (v_i - v_ea): 0, E_ea, -E_{ea+2} for i = ea, ea+1, ea+2
-                const float g1 = fmaf(grx, exs, gry * eys), g2 = -fmaf(grx, e2x, gry * e2y);
-                float gwq[3];
-#pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    const bool isa = ea == q, isb = ea == (q + 2) % 3;
-                    gkx[q] = fmaf(b.w[q], grx, isa ? -grx - gex : (isb ? gex : 0.0f));
-                    gky[q] = fmaf(b.w[q], gry, isa ? -gry - gey : (isb ? gey : 0.0f));
-                    gwq[q] = isa ? 0.0f : (isb ? g1 : g2);
-                }
-                const float gxs =
-                    fmaf(gwq[0], yt[1] - yt[2], fmaf(gwq[1], yt[2] - yt[0], gwq[2] * (yt[0] - yt[1]))) * invD;
-                const float gys =
-                    fmaf(gwq[0], xt[2] - xt[1], fmaf(gwq[1], xt[0] - xt[2], gwq[2] * (xt[1] - xt[0]))) * invD;
-#pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    gtx[q] = fmaf(-b.w[q], gxs, gtx[q]);
-                    gty[q] = fmaf(-b.w[q], gys, gty[q]);
-                }
-            }
-            const float t1 = tau[j], t0 = 1.0f - tau[j];
+        for (int q = 0; q < 3; ++q) {
+            const float wq = b.be == q ? 1.0f - b.sg : (b.be == (q + 2) % 3 ? b.sg : 0.0f);
+            gtx[q] = wq * gpx;
+            gty[q] = wq * gpy;
+            gkx[q] = 0.0f;
+            gky[q] = 0.0f;
+        }
+        const bool interior = !(b.sr < 0.0f) && !(b.sr > 1.0f);
+        if (interior) {
+            const int ea = b.be;
+            float Ex[3], Ey[3], iee3[3];
+            kedges(r, X, tc, Ex, Ey, iee3);
+            const float exs = ea == 0 ? Ex[0] : (ea == 1 ? Ex[1] : Ex[2]);
+            const float eys = ea == 0 ? Ey[0] : (ea == 1 ? Ey[1] : Ey[2]);
+            const float iee = ea == 0 ? iee3[0] : (ea == 1 ? iee3[1] : iee3[2]);
+            // edge ea+2 (from vertex ea+2 back to ea): v_{ea+2} - v_ea = -E_{ea+2}
+            const float e2x = ea == 0 ? Ex[2] : (ea == 1 ? Ex[0] : Ex[1]);
+            const float e2y = ea == 0 ? Ey[2] : (ea == 1 ? Ey[0] : Ey[1]);
+            const float xa = ea == 0 ? xt[0] : (ea == 1 ? xt[1] : xt[2]);
+            const float ya = ea == 0 ? yt[0] : (ea == 1 ? yt[1] : yt[2]);
+            const float xb = ea == 0 ? xt[1] : (ea == 1 ? xt[2] : xt[0]);
+            const float yb = ea == 0 ? yt[1] : (ea == 1 ? yt[2] : yt[0]);
+            const float gsig = fmaf(gpx, xb - xa, gpy * (yb - ya));
+            const float rx = b.rx, ry = b.ry;
+            const float grx = gsig * exs * iee, gry = gsig * eys * iee;
+            const float gex = gsig * fmaf(-2.0f * b.sr, exs, rx) * iee;
+            const float gey = gsig * fmaf(-2.0f * b.sr, eys, ry) * iee;
+            // dL/dw_i = g_r . (v_i - v_ea): 0, E_ea, -E_{ea+2} for i = ea, ea+1, ea+2
+            const float g1 = fmaf(grx, exs, gry * eys), g2 = -fmaf(grx, e2x, gry * e2y);
+            float gwq[3];
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
-                gK[q * 4 + 0] += fmaf(t0, gtx[q], X ? 0.0f : gkx[q]);
-                gK[q * 4 + 1] += fmaf(t0, gty[q], X ? 0.0f : gky[q]);
-                gK[q * 4 + 2] += fmaf(t1, gtx[q], X ? gkx[q] : 0.0f);
-                gK[q * 4 + 3] += fmaf(t1, gty[q], X ? gky[q] : 0.0f);
+                const bool isa = ea == q, isb = ea == (q + 2) % 3;
+                gkx[q] = fmaf(b.w[q], grx, isa ? -grx - gex : (isb ? gex : 0.0f));
+                gky[q] = fmaf(b.w[q], gry, isa ? -gry - gey : (isb ? gey : 0.0f));
+                gwq[q] = isa ? 0.0f : (isb ? g1 : g2);
+            }
+            const float gxs = fmaf(gwq[0], yt[1] - yt[2], fmaf(gwq[1], yt[2] - yt[0], gwq[2] * (yt[0] - yt[1]))) * invD;
+            const float gys = fmaf(gwq[0], xt[2] - xt[1], fmaf(gwq[1], xt[0] - xt[2], gwq[2] * (xt[1] - xt[0]))) * invD;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                gtx[q] = fmaf(-b.w[q], gxs, gtx[q]);
+                gty[q] = fmaf(-b.w[q], gys, gty[q]);
             }
         }
-        float *slot = sh.gacc[e];
+        const float t1 = tau[j], t0 = 1.0f - tau[j];
 #pragma unroll
-        for (int q = 0; q < 12; ++q) slot_add(slot, q, gK[q]);
+        for (int q = 0; q < 3; ++q) {
+            gK[q * 4 + 0] += fmaf(t0, gtx[q], X ? 0.0f : gkx[q]);
+            gK[q * 4 + 1] += fmaf(t0, gty[q], X ? 0.0f : gky[q]);
+            gK[q * 4 + 2] += fmaf(t1, gtx[q], X ? gkx[q] : 0.0f);
+            gK[q * 4 + 3] += fmaf(t1, gty[q], X ? gky[q] : 0.0f);
+        }
     }
-    lds_sync();
+    float *slot = sh.gacc[e];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) slot_add(slot, q, gK[q]);
 }
 
 template <int T, int SOLVER>
@@ -1073,27 +1288,32 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a, GradArgs ga)
     if (a.hdr->error_bits & kHdrOverflow) return;
     const int lane = threadIdx.x & 63;
     BwdShared<T> &sh = shm[threadIdx.x >> 6];
-    float gI[NCH + 1];
+    bool gcol = false;
+    float gal = 0.0f;
 #pragma unroll
-    for (int ch = 0; ch <= NCH; ++ch) gI[ch] = 0.0f;
-    if (g.inimg) {
-        for (int ch = 0; ch < a.C; ++ch) gI[ch] = ga.grad_image[((size_t)ch * a.H + g.py) * a.W + g.px] * ga.invK;
-        gI[NCH] = ga.grad_image[((size_t)a.C * a.H + g.py) * a.W + g.px] * ga.invK;
+    for (int ch = 0; ch < NCH; ++ch) {
+        float v = 0.0f;
+        if (g.inimg && ch < a.C) v = ga.grad_image[((size_t)ch * a.H + g.py) * a.W + g.px] * ga.invK;
+        sh.gI[ch][lane] = v;
+        gcol = gcol || v != 0.0f;
     }
-    sh.ga[lane] = gI[NCH];
+    if (g.inimg) gal = ga.grad_image[((size_t)a.C * a.H + g.py) * a.W + g.px] * ga.invK;
+    sh.gI[NCH][lane] = gal;
     if (lane < NB)
         for (int i = 0; i < NGA; ++i) sh.gacc[lane][i] = 0.0f;
+    sh.hkey[lane] = -1;
+    sh.hkey[lane + kWave] = -1;
 
     const int c_end = min((g.grp + 1) * a.G, a.NC);
     for (int c = g.grp * a.G; c < c_end; ++c) {
         const Chunk ck = chunk_info(c, a.K, a.S, a.CPS);
         if (ck.n <= 0) continue;
-        const uint32_t live = (1u << ck.n) - 1u;
         float tau[T];
         uint32_t xbits;
         chunk_taus<T>(a, ck, tau, xbits);
         const float tc = chunk_centre<T>(tau, ck.n);
         int vid[T];
+        lds_sync();
 #pragma unroll
         for (int j = 0; j < T; ++j) {
             vid[j] = -4;
@@ -1107,133 +1327,105 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a, GradArgs ga)
             sh.nz[j][lane] = vid[j] <= -1 && vid[j] >= -3 ? -1 - vid[j] : 0;
         }
 
-        // ---- foreground: dL/dw through the static solve (dw = -F^-1 dF w)
-        uint32_t fgbits = 0;
+        // ---- foreground: each (pixel, sub-frame) finds its winner among the
+        //      staged entries through the hash table
+        bool anyfg = false;
 #pragma unroll
-        for (int j = 0; j < T; ++j)
-            if (__ballot(vid[j] >= 0)) fgbits |= 1u << j;
-        if (fgbits) {
+        for (int j = 0; j < T; ++j) anyfg = anyfg || __ballot(gcol && vid[j] >= 0) != 0ull;
+        if (anyfg) {
             const int64_t idx = (int64_t)c * a.ntiles + g.tile;
             const int64_t beg = a.off[idx];
             const int n_e = a.cnt[idx];
             for (int base = 0; base < n_e; base += NB) {
                 const int nb = min(NB, n_e - base);
-                stage_batch(a, sh, beg, base, nb, live, ck.s, g, tc, true);
-                for (int e = 0; e < nb; ++e) {
-                    const FaceRec &r = sh.rec[e];
-                    const int f = __builtin_amdgcn_readfirstlane(r.f);
-                    uint32_t hits = 0;
-#pragma unroll
-                    for (int j = 0; j < T; ++j)
-                        if (vid[j] == f) hits |= 1u << j;
-                    const uint32_t msk = wave_or(hits) & __builtin_amdgcn_readfirstlane(r.msk) & fgbits;
-                    if (!msk) continue;
-                    float gw[3];
+                lds_sync();
+                int hb = -1;
+                if (lane < nb) {
+                    const uint32_t ent = a.list[beg + base + lane];
+                    const int f = (int)(ent >> 8);
+                    FaceRec r;
+                    int vq[3];
+                    stage_rec(a, f, ck.s, g.ua, g.va, tc, kRecGeom, r, vq);
+                    r.msk = ent & 0xffu;
+                    sh.it.rec[lane] = r;
 #pragma unroll
                     for (int q = 0; q < 3; ++q) {
-                        gw[q] = 0.0f;
+                        sh.vid[lane][q] = vq[q];
 #pragma unroll
-                        for (int ch = 0; ch < NCH; ++ch) gw[q] = fmaf(gI[ch], r.at[q][ch], gw[q]);
+                        for (int ch = 0; ch < NCH; ++ch)
+                            sh.at[lane][q][ch] = ch < a.C ? a.attrs[(size_t)vq[q] * a.C + ch] : 0.0f;
                     }
-                    Bary<SOLVER> bc;
-                    bc.setup(r, tc, g.du, g.dv);
-                    float gK[12], gA[3][NCH];
-#pragma unroll
-                    for (int q = 0; q < 12; ++q) gK[q] = 0.0f;
-#pragma unroll
-                    for (int q = 0; q < 3; ++q)
-#pragma unroll
-                        for (int ch = 0; ch < NCH; ++ch) gA[q][ch] = 0.0f;
-                    bool hit = false;
-#pragma unroll
-                    for (int j = 0; j < T; ++j) {
-                        if (!((msk >> j) & 1u)) continue;
-                        if (vid[j] != f) continue;
-                        const float t = tau[j] - tc;
-                        float N[3];
-                        bc.eval(r, t, N);
-                        const float invD = 1.0f / (N[0] + N[1] + N[2]);
-                        const float w[3] = {N[0] * invD, N[1] * invD, N[2] * invD};
-                        float xt[3], yt[3];
-#pragma unroll
-                        for (int q = 0; q < 3; ++q) {
-                            xt[q] = fmaf(t, r.dx[q], r.xc[q]);
-                            yt[q] = fmaf(t, r.dy[q], r.yc[q]);
+                    // faces are unique within a list and NB < kHash: an empty
+                    // bucket is always found
+                    int h = hash_face(f);
+                    for (int probe = 0; probe < kHash; ++probe) {
+                        if (atomicCAS(&sh.hkey[h], -1, f) == -1) {
+                            hb = h;
+                            break;
                         }
-                        const float gxs =
-                            fmaf(gw[0], yt[1] - yt[2], fmaf(gw[1], yt[2] - yt[0], gw[2] * (yt[0] - yt[1]))) * invD;
-                        const float gys =
-                            fmaf(gw[0], xt[2] - xt[1], fmaf(gw[1], xt[0] - xt[2], gw[2] * (xt[1] - xt[0]))) * invD;
-                        const float t1 = tau[j], t0 = 1.0f - tau[j];
-#pragma unroll
-                        for (int q = 0; q < 3; ++q) {
-                            const float gx = -w[q] * gxs, gy = -w[q] * gys;
-                            gK[q * 4 + 0] = fmaf(t0, gx, gK[q * 4 + 0]);
-                            gK[q * 4 + 1] = fmaf(t0, gy, gK[q * 4 + 1]);
-                            gK[q * 4 + 2] = fmaf(t1, gx, gK[q * 4 + 2]);
-                            gK[q * 4 + 3] = fmaf(t1, gy, gK[q * 4 + 3]);
-#pragma unroll
-                            for (int ch = 0; ch < NCH; ++ch) gA[q][ch] = fmaf(w[q], gI[ch], gA[q][ch]);
-                        }
-                        hit = true;
+                        h = (h + 1) & (kHash - 1);
                     }
-                    if (hit) {
-                        float *slot = sh.gacc[e];
+                    if (hb >= 0) sh.hval[hb] = lane;
+                }
+                lds_sync();
+                int qn = 0;
 #pragma unroll
-                        for (int q = 0; q < 12; ++q) slot_add(slot, q, gK[q]);
-#pragma unroll
-                        for (int q = 0; q < 3; ++q)
-#pragma unroll
-                            for (int ch = 0; ch < NCH; ++ch) slot_add(slot, 12 + q * NCH + ch, gA[q][ch]);
+                for (int j = 0; j < T; ++j) {
+                    int sl = -1;
+                    if (gcol && vid[j] >= 0) {
+                        int h = hash_face(vid[j]);
+                        for (int probe = 0; probe < kHash; ++probe) {
+                            const int k = sh.hkey[h];
+                            if (k == vid[j]) {
+                                sl = sh.hval[h];
+                                break;
+                            }
+                            if (k == -1) break;
+                            h = (h + 1) & (kHash - 1);
+                        }
+                    }
+                    const uint64_t bal = __ballot(sl >= 0);
+                    if (sl >= 0) sh.q[qn + lane_rank(bal)] = (uint32_t)sl | ((uint32_t)lane << 8) | ((uint32_t)j << 16);
+                    qn += __popcll(bal);
+                }
+                lds_sync();
+                for (int rb = 0; rb < qn; rb += kWave) {
+                    if (rb + lane < qn) {
+                        const uint32_t item = sh.q[rb + lane];
+                        const int jj = (int)(item >> 16);
+                        int X;
+                        const float tj = chunk_tau(a, ck, jj, X);
+                        fg_item_bwd<T, SOLVER>(a, sh, (int)(item & 0xffu), (int)((item >> 8) & 0xffu), tj, tc);
                     }
                 }
+                lds_sync();
+                if (hb >= 0) sh.hkey[hb] = -1;
                 flush_slots<T>(sh, nb, ck.s, a, ga, true);
             }
         }
 
         // ---- background
-        uint32_t bgbits = 0;
+        uint64_t bgm[T];
+        bool anybg = false;
 #pragma unroll
-        for (int j = 0; j < T; ++j)
-            if (__ballot(vid[j] <= -1 && vid[j] >= -3 && gI[NCH] != 0.0f)) bgbits |= 1u << j;
-        bgbits &= live;
-        if (bgbits) {
+        for (int j = 0; j < T; ++j) {
+            bgm[j] = __ballot(vid[j] <= -1 && vid[j] >= -3 && gal != 0.0f);
+            anybg = anybg || bgm[j] != 0ull;
+        }
+        if (anybg) {
             const int64_t idx = ((int64_t)a.NC + c) * a.ntiles + g.tile;
             const int64_t beg = a.off[idx];
             const int n_e = a.cnt[idx];
-            int qh = 0, qn = 0;
             for (int base = 0; base < n_e; base += NB) {
                 const int nb = min(NB, n_e - base);
-                stage_batch(a, sh, beg, base, nb, live, ck.s, g, tc, false);
-                for (int e = 0; e < nb; ++e) {
-                    const FaceRec &r = sh.rec[e];
-                    const uint32_t msk = __builtin_amdgcn_readfirstlane(r.msk) & bgbits;
-                    if (!msk) continue;
-                    uint32_t bits = 0;
-#pragma unroll
-                    for (int j = 0; j < T; ++j) {
-                        if (!((msk >> j) & 1u)) continue;
-                        if (vid[j] <= -1 && vid[j] >= -3 && gI[NCH] != 0.0f &&
-                            box_dist2(r, tau[j] - tc, g.du, g.dv) <= a.dmax)
-                            bits |= 1u << j;
-                    }
-                    const uint64_t bal = __ballot(bits != 0);
-                    if (!bal) continue;
-                    const int pos = qn + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
-                    if (bits) sh.q[pos & (2 * kWave - 1)] = (uint32_t)e | ((uint32_t)lane << 8) | (bits << 16);
-                    qn += __popcll(bal);
-                    if (qn - qh >= kWave) {
-                        bg_process_bwd<T, SOLVER>(a, sh, qh, kWave, tau, xbits, tc);
-                        qh += kWave;
-                    }
-                }
-                if (qn > qh) bg_process_bwd<T, SOLVER>(a, sh, qh, qn - qh, tau, xbits, tc);
-                qh = qn;
+                int cnt, pre;
+                const int total = stage_items<T>(a, sh.it, beg + base, nb, ck.s, g, tc, tau, kRecBg, a.halo, bgm,
+                                                 nullptr, sh.vid, cnt, pre);
+                for_items<T>(sh.it, total, cnt, pre,
+                             [&](int e, int p) { bg_item_bwd<T, SOLVER>(a, sh, e, p, tau, xbits, tc); });
                 flush_slots<T>(sh, nb, ck.s, a, ga, false);
             }
         }
-        lds_sync();
     }
 }
 
@@ -1304,6 +1496,7 @@ static RasterArgs raster_args(const Plan &p, const Inputs &in, const Bufs &b)
     a.G = p.G;
     a.NG = p.NG;
     a.dmax = p.dmax;
+    a.halo = p.halo;
     a.neg_log2e_over_delta = (float)(-1.4426950408889634 / (double)p.delta);
     a.inv_delta = (float)(1.0 / (double)p.delta);
     a.cap = p.cap;
