@@ -56,7 +56,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--chunk-len", type=int, default=4)
-    ap.add_argument("--chunks-per-wave", type=int, default=0)
+    ap.add_argument("--slice-len", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     args = ap.parse_args()
@@ -84,7 +84,7 @@ def main():
 
     def opts(solver, check=True):
         return R.RenderOptions(K, solver=solver, chunk_len=args.chunk_len,
-                               chunks_per_wave=args.chunks_per_wave, check=check)
+                               slice_len=args.slice_len, check=check)
 
     target, _ = R.render_forward(tt.verts, tt.faces, tt.attrs, tt.model, tt.camera, opts("fast"))
 

@@ -35,7 +35,7 @@ class rb_options(ctypes.Structure):
     _fields_ = [("num_subframes", ctypes.c_int32), ("delta", ctypes.c_float),
                 ("eps_cutoff", ctypes.c_float), ("solver", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("chunk_len", ctypes.c_int32),
-                ("chunks_per_wave", ctypes.c_int32), ("list_capacity", ctypes.c_int64)]
+                ("slice_len", ctypes.c_int32), ("list_capacity", ctypes.c_int64)]
 
 
 class rb_header(ctypes.Structure):

@@ -27,7 +27,7 @@ static rb_status make_plan(int32_t V, int32_t F, int32_t C, const rb_motion *mot
     for (int i = 0; i < 12; ++i)
         if (!std::isfinite(cam->view[i])) return RB_EINVAL;
     if (opt->solver != RB_SOLVER_FAST && opt->solver != RB_SOLVER_RECOMPUTE) return RB_EINVAL;
-    if (opt->chunk_len < 0 || opt->chunks_per_wave < 0 || opt->list_capacity < 0) return RB_EINVAL;
+    if (opt->chunk_len < 0 || opt->slice_len < 0 || opt->list_capacity < 0) return RB_EINVAL;
     if (C > RB_MAX_CHANNELS) return RB_EUNSUPPORTED;
     if (F >= RB_MAX_FACES) return RB_EUNSUPPORTED;
     const int T = opt->chunk_len == 0 ? 4 : opt->chunk_len;
@@ -61,19 +61,20 @@ static rb_status make_plan(int32_t V, int32_t F, int32_t C, const rb_motion *mot
     }
     p.CPS = std::max(1, (nmax + T - 1) / T);
     p.NC = S * p.CPS;
-    if (opt->chunks_per_wave > 0) {
-        p.G = opt->chunks_per_wave;
-    } else {
-        // enough waves to fill 256 CUs several times over
-        const int64_t target_groups = std::max<int64_t>(1, 16384 / p.ntiles);
-        p.G = (int)std::max<int64_t>(1, (p.NC + target_groups - 1) / target_groups);
-    }
-    p.G = std::min(p.G, p.NC);
-    p.NG = (p.NC + p.G - 1) / p.G;
+    // background list entries per task: small enough that the longest lists
+    // (silhouette tiles) spread over many waves, large enough to amortize a
+    // task's set-up
+    p.SL = opt->slice_len > 0 ? opt->slice_len : 64;
+    p.NS = std::max(C, 2);
     p.cap = opt->list_capacity > 0 ? opt->list_capacity
                                    : std::max<int64_t>(1 << 20, (int64_t)64 * F * std::min(p.NC, 64));
     p.ncounts = (int64_t)2 * p.NC * p.ntiles;
     p.nblocks_scan = std::max<int64_t>(1, (p.ncounts + 4095) / 4096);
+    p.ntct = (int64_t)p.NC * p.ntiles;
+    p.nblocks_tscan = std::max<int64_t>(1, (p.ntct + 4095) / 4096);
+    // every (chunk, tile) contributes at most ceil(n_bg / SL) <= n_bg / SL + 1 tasks
+    p.maxtasks = p.ntct + p.cap / p.SL + 1;
+    p.persist = 256 * 12;
 
     size_t o = 0;
     p.o_hdr = o;
@@ -94,10 +95,16 @@ static rb_status make_plan(int32_t V, int32_t F, int32_t C, const rb_motion *mot
     o = align256(o + (size_t)p.cap * 4);
     p.o_vis_id = o;
     o = align256(o + (size_t)p.ntiles * K * kWave * 4);
-    p.o_vis_p = o;
-    o = align256(o + (size_t)p.ntiles * K * kWave * 4);
-    p.o_part = o;
-    o = align256(o + (size_t)p.NG * p.ntiles * (C + 1) * kWave * 4);
+    p.o_pix = o;
+    o = align256(o + (size_t)p.ntiles * K * p.NS * kWave * 4);
+    p.o_tsl = o;
+    o = align256(o + (size_t)p.ntct * 4);
+    p.o_toff = o;
+    o = align256(o + (size_t)p.ntct * 8);
+    p.o_tbsum = o;
+    o = align256(o + (size_t)p.nblocks_tscan * 8);
+    p.o_tasks = o;
+    o = align256(o + (size_t)p.maxtasks * 8);
     p.o_gkf = o;
     o = align256(o + (size_t)(S + 1) * V * 2 * 4);
     p.total = o;
@@ -117,8 +124,11 @@ static Bufs carve(const Plan &p, void *ws)
     r.bsum = (int64_t *)(b + p.o_bsum);
     r.list = (uint32_t *)(b + p.o_list);
     r.vis_id = (int32_t *)(b + p.o_vis_id);
-    r.vis_p = (float *)(b + p.o_vis_p);
-    r.part = (float *)(b + p.o_part);
+    r.pix = (float *)(b + p.o_pix);
+    r.tsl = (int32_t *)(b + p.o_tsl);
+    r.toff = (int64_t *)(b + p.o_toff);
+    r.tbsum = (int64_t *)(b + p.o_tbsum);
+    r.tasks = (uint64_t *)(b + p.o_tasks);
     r.gkf = (float *)(b + p.o_gkf);
     return r;
 }

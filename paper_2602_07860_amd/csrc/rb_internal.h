@@ -50,7 +50,9 @@ struct DevHeader {
     int32_t reserved;
     int64_t list_entries;
     int64_t list_capacity;
-    int64_t pad[5];
+    int64_t ntasks;                  // background tasks of the current forward
+    unsigned long long task_ctr[2];  // next task (forward, backward)
+    int64_t pad[2];
 };
 
 // Everything a launch needs, derived on the host from sizes and options.
@@ -65,13 +67,17 @@ struct Plan {
     int T;          // chunk length (template)
     int CPS;        // chunks per segment
     int NC;         // chunks = S * CPS
-    int G;          // chunks per wave
-    int NG;         // chunk groups = ceil(NC / G)
+    int SL;         // background list entries per task
+    int NS;         // per (pixel, sub-frame) value slots: colour, or log-sum and zero count
     int64_t cap;    // list capacity (entries)
+    int64_t ntct;   // (chunk, tile) pairs = NC * ntiles
+    int64_t maxtasks;
+    int persist;    // waves of the persistent background kernels
     // workspace byte offsets
-    size_t o_hdr, o_kf, o_kfz, o_cnt, o_off, o_cur, o_bsum, o_list, o_vis_id, o_vis_p, o_part, o_gkf, total;
+    size_t o_hdr, o_kf, o_kfz, o_cnt, o_off, o_cur, o_bsum, o_list, o_vis_id, o_pix, o_tsl, o_toff, o_tbsum,
+        o_tasks, o_gkf, total;
     int64_t ncounts;  // 2 * NC * ntiles
-    int64_t nblocks_scan;
+    int64_t nblocks_scan, nblocks_tscan;
 };
 
 // Pointers into a workspace for one call.
@@ -85,9 +91,12 @@ struct Bufs {
     int32_t *cur;        // [2][NC][ntiles] fill cursors
     int64_t *bsum;       // scan block sums
     uint32_t *list;      // entries: face << 8 | sub-frame mask
-    int32_t *vis_id;     // [ntiles][K][64] winner face, or -1 - (#zero factors, max 2) for background
-    float *vis_p;        // [ntiles][K][64] background product over non-zero factors
-    float *part;         // [NG][ntiles][C+1][64] partial sums
+    int32_t *vis_id;     // [ntiles][K][64] winner face; -1 uncovered; -4 outside the image
+    float *pix;          // [ntiles][K][NS][64] winner colour, or (sum log2(1 - A), #zero factors)
+    int32_t *tsl;        // [NC][ntiles] background tasks (list slices) per (chunk, tile)
+    int64_t *toff;       // [NC][ntiles] first task
+    int64_t *tbsum;      // task scan block sums
+    uint64_t *tasks;     // (chunk * ntiles + tile) << 32 | slice
     float *gkf;          // [S+1][V][2] keyframe gradient
 };
 

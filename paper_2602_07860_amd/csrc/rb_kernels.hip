@@ -85,6 +85,9 @@ __global__ void k_init(DevHeader *hdr, int64_t cap, int32_t *cnt, int32_t *cur, 
         hdr->reserved = 0;
         hdr->list_entries = 0;
         hdr->list_capacity = cap;
+        hdr->ntasks = 0;
+        hdr->task_ctr[0] = 0;
+        hdr->task_ctr[1] = 0;
     }
     for (; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         cnt[i] = 0;
@@ -92,10 +95,17 @@ __global__ void k_init(DevHeader *hdr, int64_t cap, int32_t *cnt, int32_t *cur, 
     }
 }
 
-__global__ void k_zero(float *p, int64_t n)
+// clear the keyframe and attribute gradients and the backward task counter
+__global__ void k_bwd_init(float *gkf, int64_t n1, float *gattr, int64_t n2, DevHeader *hdr)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = 0.0f;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) hdr->task_ctr[1] = 0;
+    for (; i < n1 + n2; i += (int64_t)gridDim.x * blockDim.x) {
+        if (i < n1)
+            gkf[i] = 0.0f;
+        else
+            gattr[i - n1] = 0.0f;
+    }
 }
 
 struct ViewArgs {
@@ -253,7 +263,6 @@ __global__ __launch_bounds__(256) void k_bin(BinArgs a, int pass)
         }
     }
 }
-
 // ------------------------------------------------------------------- scan
 // exclusive prefix sum of n int32 counts into int64 offsets, 3 phases
 
@@ -309,8 +318,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan1(const int32_t *__restric
     if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan2(int64_t *__restrict__ bsum, int64_t nb, DevHeader *hdr,
-                                                        int64_t cap)
+// block sums -> block offsets; the grand total goes to *total, and the error
+// bit is raised in *err (if given) when it exceeds cap
+__global__ __launch_bounds__(kScanThreads) void k_scan2(int64_t *__restrict__ bsum, int64_t nb, int64_t *total,
+                                                        int32_t *err, int64_t cap)
 {
     __shared__ int64_t tot;
     int64_t carry = 0;
@@ -323,8 +334,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan2(int64_t *__restrict__ bs
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        hdr->list_entries = carry;
-        if (carry > cap) atomicOr(&hdr->error_bits, kHdrOverflow);
+        *total = carry;
+        if (err && carry > cap) atomicOr(err, kHdrOverflow);
     }
 }
 
@@ -336,34 +347,44 @@ __global__ void k_scan3(int64_t *__restrict__ off, const int64_t *__restrict__ b
 
 // ----------------------------------------------------------------- raster
 //
-// One 64-lane wave per (8x8 tile, group of chunks).  For each chunk the wave
-// walks its foreground list, then its background list, NB entries at a time.
+// Forward, three kernels:
+//  * k_fg, one 64-lane wave per (chunk, 8x8 tile), lane = pixel: z-buffer
+//    over the tile's foreground list (eq 9), shading of the winners, and the
+//    per-(pixel, sub-frame) records the rest reads: winner (or uncovered),
+//    colour, zeroed background accumulators.  It also counts the background
+//    tasks of its (chunk, tile): slices of SL background-list entries, none
+//    if every in-image pixel is covered at every sub-frame of the chunk.
+//  * k_bg, persistent waves taking background tasks from a counter: soft
+//    aggregation (eqs 10, 13-15) of the slice's faces on the uncovered pixels,
+//    accumulated in LDS as sum log2(1 - A) (zero factors counted apart) and
+//    added to the pixel records.  Splitting the long lists of silhouette tiles
+//    into slices keeps every wave's work bounded.
+//  * k_resolve, one wave per tile: the average over the K sub-frames.
 //
+// Inside a wave, a list is walked NB entries at a time:
 //  * staging: lane e gathers entry e's face indices and double keyframes and
-//    forms a FaceRec of float32 coordinates relative to the tile anchor at the
-//    chunk's middle time.  It also forms, per sub-frame of the chunk, the
-//    64-bit mask of tile pixels the entry can reach (its box at that
+//    forms the entry's float32 coordinates relative to the tile anchor at the
+//    chunk's middle time (stored in LDS field-major, so lanes reading different
+//    entries hit different banks).  It also forms, per sub-frame of the chunk,
+//    the 64-bit mask of tile pixels the entry can reach (its box at that
 //    sub-frame, grown by the influence radius for the background, restricted
 //    to the pixels still in question) and their union U_e.
-//  * items: a batch's work is the set of (entry, pixel) pairs with the pixel
+//  * items: the batch's work is the set of (entry, pixel) pairs with the pixel
 //    in U_e.  An exclusive scan over the entries numbers them and they are
 //    dealt out 64 at a time, one per lane, so a face that reaches 3 pixels of
 //    the tile costs 3 lane-evaluations instead of 64.  An item carries the
 //    sub-frames where its pixel is in the entry's mask; the fast solver's
 //    coefficients are formed once per item and evaluated per sub-frame.
-//  * foreground (eq 9): items update an LDS z-buffer by a 64-bit atomic min
-//    of (depth bits, face index), which keeps the lowest face index on exact
-//    depth ties.  Afterwards each (pixel, sub-frame) shades its winner from
-//    the face's keyframes.
-//  * background (eqs 10, 13-15): items on uncovered pixels accumulate
-//    sum log2(1 - A) per (pixel, sub-frame) with LDS float atomics, zero
-//    factors counted apart.
-//  * backward: the same item walk over the background list.  The foreground
-//    goes the other way round: each (pixel, sub-frame) knows its winning face
-//    from the forward, finds it among the staged entries through a small LDS
-//    hash table and is queued for that entry.  Per-entry LDS gradient slots
-//    collect the items' contributions and are added to global memory with
-//    one atomic per non-zero value and batch.
+//  * foreground items update the LDS z-buffer by a 64-bit atomic min of
+//    (depth bits, face index), which keeps the lowest face index on exact
+//    depth ties; background items add log2(1 - A) with LDS float atomics.
+//
+// Backward, two kernels: k_fg_bwd per (chunk, tile): each (pixel, sub-frame)
+// finds its winning face among the staged entries through a small LDS hash
+// table and is queued for that entry; k_bg_bwd over the same background tasks
+// as the forward.  Per-entry LDS gradient slots collect the items'
+// contributions and are added to global memory with one atomic per non-zero
+// value and batch.
 
 struct RasterArgs {
     const double2 *kf;
@@ -374,33 +395,53 @@ struct RasterArgs {
     const int64_t *off;
     const uint32_t *list;
     int32_t *vis_id;
-    float *vis_p;
-    float *part;
-    const DevHeader *hdr;
-    int V, F, C, S, K, W, H, tiles_x, ntiles, CPS, NC, G, NG;
-    float dmax, halo, neg_log2e_over_delta, inv_delta;
-    int64_t cap;
+    float *pix;
+    int32_t *tsl;
+    const uint64_t *tasks;
+    DevHeader *hdr;
+    int64_t maxtasks;
+    int V, F, C, S, K, W, H, tiles_x, ntiles, CPS, NC, SL, NS;
+    float inv_w, inv_h, dmax, halo, neg_log2e_over_delta, inv_delta;
 };
 
 constexpr int NCH = RB_MAX_CHANNELS;
 constexpr int NB = 32;              // list entries staged per batch
 constexpr int NGA = 12 + 3 * NCH;   // per-entry gradient slot: 3 vertices x 2 keyframes x (x, y), attributes
 constexpr int kHash = 128;          // face -> staged entry table (NB keys at most)
+constexpr int kVisOut = -4;         // vis_id of a pixel outside the image
+
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 enum { kRecFg = 0, kRecBg = 1, kRecGeom = 2 };
 
-// One list entry staged in LDS.  Edge i runs from vertex (i+1)%3 to (i+2)%3.
-struct __align__(16) FaceRec {
-    float xc[3], yc[3];       // positions at the chunk's middle time tc, minus the tile anchor
-    float dx[3], dy[3];       // segment displacement
-    float e0x[3], e0y[3];     // edge i at the segment start
-    float e1x[3], e1y[3];     // edge i at the segment end
-    float aux0[3], aux1[3];   // foreground: camera depth at the start and its change;
-                              // background: 1/|edge i|^2 at the start and the end (0 if degenerate)
-    int f;
-    uint32_t msk;             // sub-frames of the chunk this entry touches
+// field offsets of a staged entry (edge i runs from vertex (i+1)%3 to (i+2)%3)
+enum {
+    R_XC = 0,     // positions at the chunk's middle time tc, minus the tile anchor
+    R_YC = 3,
+    R_DX = 6,     // segment displacement
+    R_DY = 9,
+    R_E0X = 12,   // edge i at the segment start
+    R_E0Y = 15,
+    R_E1X = 18,   // edge i at the segment end
+    R_E1Y = 21,
+    R_A0 = 24,    // foreground: camera depth at the start; background: 1/|edge i|^2 at the start (0 if degenerate)
+    R_A1 = 27,    // foreground: its change over the segment; background: 1/|edge i|^2 at the end
+    R_F = 30,     // face index (int bits)
+    R_N = 31
 };
-static_assert(sizeof(FaceRec) == 128, "FaceRec layout");
+
+// An entry in registers.
+struct FaceRec {
+    float v[R_N - 1];
+    int f;
+    __device__ float at(int k) const { return v[k]; }
+};
+
+// An entry staged in LDS, field-major: field k of entry e at rec[k][e].
+struct LdsRec {
+    const float *p;
+    __device__ float at(int k) const { return p[k * NB]; }
+};
 
 __device__ __forceinline__ void lds_sync()
 {
@@ -425,33 +466,33 @@ __device__ __forceinline__ void stage_rec(const RasterArgs &a, int f, int s, dou
         Y0[q] = p.y;
         X1[q] = e.x;
         Y1[q] = e.y;
-        r.xc[q] = (float)(fma((double)tc, e.x - p.x, p.x) - ua);
-        r.yc[q] = (float)(fma((double)tc, e.y - p.y, p.y) - va);
-        r.dx[q] = (float)(e.x - p.x);
-        r.dy[q] = (float)(e.y - p.y);
+        r.v[R_XC + q] = (float)(fma((double)tc, e.x - p.x, p.x) - ua);
+        r.v[R_YC + q] = (float)(fma((double)tc, e.y - p.y, p.y) - va);
+        r.v[R_DX + q] = (float)(e.x - p.x);
+        r.v[R_DY + q] = (float)(e.y - p.y);
         if (kind == kRecFg) {
             const float z0 = a.kfz[(size_t)s * a.V + v], z1 = a.kfz[(size_t)(s + 1) * a.V + v];
-            r.aux0[q] = z0;
-            r.aux1[q] = z1 - z0;
+            r.v[R_A0 + q] = z0;
+            r.v[R_A1 + q] = z1 - z0;
         }
     }
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         const int j = (i + 1) % 3, k = (i + 2) % 3;
         const double ax = X0[k] - X0[j], ay = Y0[k] - Y0[j], bx = X1[k] - X1[j], by = Y1[k] - Y1[j];
-        r.e0x[i] = (float)ax;
-        r.e0y[i] = (float)ay;
-        r.e1x[i] = (float)bx;
-        r.e1y[i] = (float)by;
+        r.v[R_E0X + i] = (float)ax;
+        r.v[R_E0Y + i] = (float)ay;
+        r.v[R_E1X + i] = (float)bx;
+        r.v[R_E1Y + i] = (float)by;
         if (kind == kRecBg) {
-            const double ea = ax * ax + ay * ay, eb = bx * bx + by * by;
-            r.aux0[i] = ea > 0.0 ? (float)(1.0 / ea) : 0.0f;
-            r.aux1[i] = eb > 0.0 ? (float)(1.0 / eb) : 0.0f;
+            const float ea = (float)(ax * ax + ay * ay), eb = (float)(bx * bx + by * by);
+            r.v[R_A0 + i] = ea > 0.0f ? rcp(ea) : 0.0f;
+            r.v[R_A1 + i] = eb > 0.0f ? rcp(eb) : 0.0f;
         }
     }
     if (kind == kRecGeom) {
 #pragma unroll
-        for (int i = 0; i < 3; ++i) r.aux0[i] = r.aux1[i] = 0.0f;
+        for (int i = 0; i < 3; ++i) r.v[R_A0 + i] = r.v[R_A1 + i] = 0.0f;
     }
 }
 
@@ -470,34 +511,38 @@ __device__ __forceinline__ void stage_rec(const RasterArgs &a, int f, int s, dou
 template <int SOLVER>
 struct Bary {
     float c1[3], c2[3], c3[3];
-    __device__ __forceinline__ void setup(const FaceRec &r, float tc, float du, float dv)
+    template <class R>
+    __device__ __forceinline__ void setup(const R &r, float tc, float du, float dv)
     {
         if (SOLVER == RB_SOLVER_FAST) {
             float ax[3], ay[3];
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
-                ax[q] = r.xc[q] - du;
-                ay[q] = r.yc[q] - dv;
+                ax[q] = r.at(R_XC + q) - du;
+                ay[q] = r.at(R_YC + q) - dv;
             }
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
                 const int j = (i + 1) % 3;
-                const float dex = r.e1x[i] - r.e0x[i], dey = r.e1y[i] - r.e0y[i];
-                const float ecx = fmaf(tc, dex, r.e0x[i]), ecy = fmaf(tc, dey, r.e0y[i]);
-                c1[i] = fmaf(r.dx[j], dey, -r.dy[j] * dex);
-                c2[i] = fmaf(ax[j], dey, -ay[j] * dex) + fmaf(r.dx[j], ecy, -r.dy[j] * ecx);
+                const float e0x = r.at(R_E0X + i), e0y = r.at(R_E0Y + i);
+                const float dex = r.at(R_E1X + i) - e0x, dey = r.at(R_E1Y + i) - e0y;
+                const float ecx = fmaf(tc, dex, e0x), ecy = fmaf(tc, dey, e0y);
+                const float djx = r.at(R_DX + j), djy = r.at(R_DY + j);
+                c1[i] = fmaf(djx, dey, -djy * dex);
+                c2[i] = fmaf(ax[j], dey, -ay[j] * dex) + fmaf(djx, ecy, -djy * ecx);
                 c3[i] = fmaf(ax[j], ecy, -ay[j] * ecx);
             }
         } else {
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                c1[i] = r.xc[i] - du;
-                c2[i] = r.yc[i] - dv;
+                c1[i] = r.at(R_XC + i) - du;
+                c2[i] = r.at(R_YC + i) - dv;
                 c3[i] = 0.0f;
             }
         }
     }
-    __device__ __forceinline__ void eval(const FaceRec &r, float t, float N[3]) const
+    template <class R>
+    __device__ __forceinline__ void eval(const R &r, float t, float N[3]) const
     {
         // t = tau - tc
         if (SOLVER == RB_SOLVER_FAST) {
@@ -507,8 +552,8 @@ struct Bary {
             float xt[3], yt[3];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                xt[i] = fmaf(t, r.dx[i], c1[i]);
-                yt[i] = fmaf(t, r.dy[i], c2[i]);
+                xt[i] = fmaf(t, r.at(R_DX + i), c1[i]);
+                yt[i] = fmaf(t, r.at(R_DY + i), c2[i]);
             }
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
@@ -522,11 +567,7 @@ struct Bary {
 // Background term of one (pixel, face, sub-frame): closest point of the
 // keyframe triangle F(X) to q = F(X) w by the three clamped edge projections
 // of App. B (edges (0,1), (1,2), (2,0), first wins ties; eq 13), mapped to
-// the sub-frame (eq 14): d = |p - F(tau) w*|^2.  q itself is never formed:
-// outside a nearly edge-on face |w| is large and q = sum w_i v_i would
-// amplify position rounding; the edge search only needs q - v_e, which is
-// w_{e+1} E_e - w_{e+2} E_{e+2} with the (double-derived) edge vectors
-// E_e = v_{e+1} - v_e.
+// the sub-frame (eq 14): d = |p - F(tau) w*|^2.
 struct BgEval {
     float w[3];
     float rx, ry;             // q - v_be in F(X)
@@ -535,32 +576,44 @@ struct BgEval {
     int be;                   // chosen edge: vertices be and (be+1)%3
 };
 
-// closest-point edge e of F(X) (from vertex e to e+1) is FaceRec edge (e+2)%3
-__device__ __forceinline__ void kedges(const FaceRec &r, int X, float tc, float Ex[3], float Ey[3], float iee[3])
+// keyframe X positions (anchor-local) and edges; closest-point edge e of
+// F(X) (from vertex e to e+1) is the entry's edge (e+2)%3
+template <class R>
+__device__ __forceinline__ void kedges(const R &r, int X, float tc, float Ex[3], float Ey[3], float iee[3], float kx[3],
+                                       float ky[3])
 {
     const float tx = (X ? 1.0f : 0.0f) - tc;
-    float kx[3], ky[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-        kx[q] = fmaf(tx, r.dx[q], r.xc[q]);
-        ky[q] = fmaf(tx, r.dy[q], r.yc[q]);
+        kx[q] = fmaf(tx, r.at(R_DX + q), r.at(R_XC + q));
+        ky[q] = fmaf(tx, r.at(R_DY + q), r.at(R_YC + q));
     }
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
         const int i = (e + 2) % 3, b = (e + 1) % 3;
         Ex[e] = kx[b] - kx[e];
         Ey[e] = ky[b] - ky[e];
-        iee[e] = X ? r.aux1[i] : r.aux0[i];
+        iee[e] = X ? r.at(R_A1 + i) : r.at(R_A0 + i);
     }
 }
 
-__device__ __forceinline__ void bg_eval(const FaceRec &r, float tc, float tau, int X, const float N[3], float invD,
-                                        float du, float dv, BgEval &b)
+template <class R>
+__device__ __forceinline__ void bg_eval(const R &r, float tc, float tau, int X, const float N[3], float invD, float du,
+                                        float dv, BgEval &b)
 {
 #pragma unroll
     for (int i = 0; i < 3; ++i) b.w[i] = N[i] * invD;
-    float Ex[3], Ey[3], iee[3];
-    kedges(r, X, tc, Ex, Ey, iee);
+    float Ex[3], Ey[3], iee[3], kx[3], ky[3];
+    kedges(r, X, tc, Ex, Ey, iee, kx, ky);
+    // q = F(X) w = p + (X - tau) sum_i w_i dv_i (linear motion, sum w = 1):
+    // exact at the keyframes and under translation, and free of the
+    // |w| * |edge| rounding of sum_i w_i v_i(X) when the face is nearly
+    // edge-on at tau (|w| large)
+    const float mX = (X ? 1.0f : 0.0f) - tau;
+    const float d0x = r.at(R_DX), d0y = r.at(R_DY);
+    const float sx = fmaf(b.w[1], r.at(R_DX + 1) - d0x, fmaf(b.w[2], r.at(R_DX + 2) - d0x, d0x));
+    const float sy = fmaf(b.w[1], r.at(R_DY + 1) - d0y, fmaf(b.w[2], r.at(R_DY + 2) - d0y, d0y));
+    const float qx = fmaf(mX, sx, du), qy = fmaf(mX, sy, dv);
     float best = FLT_MAX;
     b.be = 0;
     b.sr = 0.0f;
@@ -569,9 +622,7 @@ __device__ __forceinline__ void bg_eval(const FaceRec &r, float tc, float tau, i
     b.ry = 0.0f;
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
-        const int e1 = (e + 1) % 3, e2 = (e + 2) % 3;
-        const float rx = fmaf(b.w[e1], Ex[e], -b.w[e2] * Ex[e2]);
-        const float ry = fmaf(b.w[e1], Ey[e], -b.w[e2] * Ey[e2]);
+        const float rx = qx - kx[e], ry = qy - ky[e];
         const float sr = fmaf(rx, Ex[e], ry * Ey[e]) * iee[e];
         const float sg = __builtin_amdgcn_fmed3f(sr, 0.0f, 1.0f);
         const float hx = fmaf(-sg, Ex[e], rx), hy = fmaf(-sg, Ey[e], ry);
@@ -588,8 +639,8 @@ __device__ __forceinline__ void bg_eval(const FaceRec &r, float tc, float tau, i
     float xt[3], yt[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-        xt[q] = fmaf(t, r.dx[q], r.xc[q]);
-        yt[q] = fmaf(t, r.dy[q], r.yc[q]);
+        xt[q] = fmaf(t, r.at(R_DX + q), r.at(R_XC + q));
+        yt[q] = fmaf(t, r.at(R_DY + q), r.at(R_YC + q));
     }
     const float xa = b.be == 0 ? xt[0] : (b.be == 1 ? xt[1] : xt[2]);
     const float ya = b.be == 0 ? yt[0] : (b.be == 1 ? yt[1] : yt[2]);
@@ -615,33 +666,33 @@ __device__ __forceinline__ float log2_one_minus(float A, float om)
     return __log2f(om);
 }
 
-struct TileGeom {
-    int tile, grp, px, py;
+// pixel p of a tile (bit 8 * row + column) relative to the tile anchor, which
+// lies between the 4 centre pixels; exact for W, H powers of 2
+__device__ __forceinline__ float pix_du(int p, float inv_w) { return (float)(2 * (p & 7) - 7) * inv_w; }
+__device__ __forceinline__ float pix_dv(int p, float inv_h) { return (float)(7 - 2 * (p >> 3)) * inv_h; }
+
+struct TileCtx {
+    int c, tile, px, py;
     bool inimg;
-    double ua, va;   // tile anchor (between the 4 centre pixels) in normalized coordinates
-    float du, dv;    // this lane's pixel centre relative to the anchor (exact for W, H powers of 2)
+    double ua, va;   // tile anchor in normalized coordinates
+    float du, dv;    // this lane's pixel centre relative to the anchor
+    Chunk ck;
 };
 
-__device__ __forceinline__ float lane_du(int lane, int W) { return (float)(2 * (lane & 7) - 7) / (float)W; }
-__device__ __forceinline__ float lane_dv(int lane, int H) { return (float)(7 - 2 * (lane >> 3)) / (float)H; }
-
-__device__ __forceinline__ bool tile_geom(const RasterArgs &a, TileGeom &g)
+__device__ __forceinline__ void tile_ctx(const RasterArgs &a, int64_t ct, TileCtx &g)
 {
     const int lane = threadIdx.x & 63;
-    int lb = xcd_remap(blockIdx.x, gridDim.x);
-    int wave = lb * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (wave >= a.ntiles * a.NG) return false;
-    g.tile = wave % a.ntiles;
-    g.grp = wave / a.ntiles;
-    int tx = g.tile % a.tiles_x, ty = g.tile / a.tiles_x;
+    g.c = (int)(ct / a.ntiles);
+    g.tile = (int)(ct - (int64_t)g.c * a.ntiles);
+    const int tx = g.tile % a.tiles_x, ty = g.tile / a.tiles_x;
     g.px = tx * kTile + (lane & 7);
     g.py = ty * kTile + (lane >> 3);
     g.inimg = g.px < a.W && g.py < a.H;
     g.ua = (double)(16 * tx + 8 - a.W) / (double)a.W;
     g.va = (double)(a.H - 16 * ty - 8) / (double)a.H;
-    g.du = lane_du(lane, a.W);
-    g.dv = lane_dv(lane, a.H);
-    return true;
+    g.du = pix_du(lane, a.inv_w);
+    g.dv = pix_dv(lane, a.inv_h);
+    g.ck = chunk_info(g.c, a.K, a.S, a.CPS);
 }
 
 // local time of sub-frame j of a chunk and whether eq 13 takes the segment's
@@ -676,11 +727,21 @@ __device__ __forceinline__ float chunk_centre(const float tau[T], int n)
     return 0.5f * (tau[0] + last);
 }
 
+// record index of pixel lane, sub-frame k of a tile
+__device__ __forceinline__ size_t vis_index(const RasterArgs &a, int tile, int k, int lane)
+{
+    return ((size_t)tile * a.K + k) * kWave + lane;
+}
+__device__ __forceinline__ size_t pix_index(const RasterArgs &a, int tile, int k, int slot, int lane)
+{
+    return (((size_t)tile * a.K + k) * a.NS + slot) * kWave + lane;
+}
+
 // ------------------------------------------------------------ item machinery
 
 // mask of the tile pixels whose centres lie in [x0 - g, x1 + g] x [y0 - g, y1 + g]
 // (anchor-local; bit = 8 * row + column), with a margin of 0.05 pixel so that
-// the box never cuts off a pixel the exact test below would accept
+// the box never cuts off a pixel the exact test would accept
 __device__ __forceinline__ uint64_t rect_mask(float x0, float x1, float y0, float y1, float g, float W, float H)
 {
     // column c has centre du = (2c - 7)/W, row r has dv = (7 - 2r)/H
@@ -752,13 +813,27 @@ __device__ __forceinline__ int lane_rank(uint64_t bal)
 // Item bookkeeping shared by the forward and backward walks.
 template <int T>
 struct ItemShared {
-    FaceRec rec[NB];
-    uint64_t m[NB][T];   // per entry and sub-frame: pixels to evaluate
+    float rec[R_N][NB];  // staged entries, field-major
+    uint64_t m[T][NB];   // per sub-frame and entry: pixels to evaluate
     uint64_t U[NB];      // union over the sub-frames
     int pre[NB];         // number of the entry's first item
     int ne[NB];          // entries with at least one item, in order
     uint8_t flag[kWave];
 };
+
+template <int T>
+__device__ __forceinline__ LdsRec lds_rec(ItemShared<T> &sh, int e)
+{
+    return LdsRec{&sh.rec[0][e]};
+}
+
+template <int T>
+__device__ __forceinline__ void store_rec(ItemShared<T> &sh, int e, const FaceRec &r)
+{
+#pragma unroll
+    for (int k = 0; k < R_N - 1; ++k) sh.rec[k][e] = r.v[k];
+    sh.rec[R_F][e] = __int_as_float(r.f);
+}
 
 // Stage entries [first, first + nb) of a list (one per lane) with their
 // per-sub-frame pixel masks; allow[j] is the set of pixels in question at
@@ -766,9 +841,8 @@ struct ItemShared {
 // items; cnt / pre are the lane's entry's item count and first item.
 template <int T>
 __device__ __forceinline__ int stage_items(const RasterArgs &a, ItemShared<T> &sh, int64_t first, int nb, int s,
-                                           const TileGeom &g, float tc, const float tau[T], int kind, float grow,
-                                           const uint64_t allow[T], float (*at)[3][NCH], int (*vids)[3], int &cnt,
-                                           int &pre)
+                                           const TileCtx &g, float tc, const float tau[T], int kind, float grow,
+                                           const uint64_t allow[T], int (*vids)[3], int &cnt, int &pre)
 {
     const int lane = threadIdx.x & 63;
     lds_sync();
@@ -778,7 +852,6 @@ __device__ __forceinline__ int stage_items(const RasterArgs &a, ItemShared<T> &s
         FaceRec r;
         int vid[3];
         stage_rec(a, (int)(ent >> 8), s, g.ua, g.va, tc, kind, r, vid);
-        uint32_t msk = 0;
         uint64_t U = 0;
 #pragma unroll
         for (int j = 0; j < T; ++j) {
@@ -788,7 +861,8 @@ __device__ __forceinline__ int stage_items(const RasterArgs &a, ItemShared<T> &s
                 float x0 = FLT_MAX, x1 = -FLT_MAX, y0 = FLT_MAX, y1 = -FLT_MAX;
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
-                    const float xt = fmaf(t, r.dx[q], r.xc[q]), yt = fmaf(t, r.dy[q], r.yc[q]);
+                    const float xt = fmaf(t, r.v[R_DX + q], r.v[R_XC + q]);
+                    const float yt = fmaf(t, r.v[R_DY + q], r.v[R_YC + q]);
                     x0 = fminf(x0, xt);
                     x1 = fmaxf(x1, xt);
                     y0 = fminf(y0, yt);
@@ -796,19 +870,11 @@ __device__ __forceinline__ int stage_items(const RasterArgs &a, ItemShared<T> &s
                 }
                 mj = rect_mask(x0, x1, y0, y1, grow, (float)a.W, (float)a.H) & allow[j];
             }
-            sh.m[lane][j] = mj;
-            if (mj) msk |= 1u << j;
+            sh.m[j][lane] = mj;
             U |= mj;
         }
-        r.msk = msk;
-        sh.rec[lane] = r;
+        store_rec(sh, lane, r);
         sh.U[lane] = U;
-        if (at) {
-#pragma unroll
-            for (int q = 0; q < 3; ++q)
-#pragma unroll
-                for (int c = 0; c < NCH; ++c) at[lane][q][c] = c < a.C ? a.attrs[(size_t)vid[q] * a.C + c] : 0.0f;
-        }
         if (vids) {
 #pragma unroll
             for (int q = 0; q < 3; ++q) vids[lane][q] = vid[q];
@@ -849,74 +915,49 @@ __device__ __forceinline__ void for_items(ItemShared<T> &sh, int total, int cnt,
     }
 }
 
-// ------------------------------------------------------------------ forward
+// next task of a persistent kernel (wave-uniform); tasks >= n end the loop
+__device__ __forceinline__ int64_t next_task(unsigned long long *ctr)
+{
+    unsigned long long t = 0;
+    if ((threadIdx.x & 63) == 0) t = atomicAdd(ctr, 1ull);
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)t, 0, 64);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(t >> 32), 0, 64);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// --------------------------------------------------------- forward: k_fg
 
 template <int T>
-struct FwdShared {
+struct FgShared {
     ItemShared<T> it;
-    union {
-        unsigned long long zb[T][kWave];   // foreground: depth bits << 32 | face
-        struct {
-            float lsum[T][kWave];          // sum of log2(1 - A) over non-zero factors
-            int nz[T][kWave];              // number of zero factors (A == 1)
-        } bg;
-    } u;
+    unsigned long long zb[T][kWave];   // depth bits << 32 | face
 };
 
 // foreground item: coverage (eqs 1-3 / 8) and depth test (eq 9) per sub-frame
 template <int T, int SOLVER>
-__device__ __forceinline__ void fg_item(const RasterArgs &a, FwdShared<T> &sh, int e, int p, const float tau[T],
+__device__ __forceinline__ void fg_item(const RasterArgs &a, FgShared<T> &sh, int e, int p, const float tau[T],
                                         float tc)
 {
-    const FaceRec &r = sh.it.rec[e];
-    const float du = lane_du(p, a.W), dv = lane_dv(p, a.H);
+    const LdsRec r = lds_rec(sh.it, e);
+    const float du = pix_du(p, a.inv_w), dv = pix_dv(p, a.inv_h);
     Bary<SOLVER> bc;
     bc.setup(r, tc, du, dv);
-    const unsigned long long f = (uint32_t)r.f;
+    const unsigned long long f = (uint32_t)__float_as_int(r.at(R_F));
 #pragma unroll
     for (int j = 0; j < T; ++j) {
-        if (!((sh.it.m[e][j] >> p) & 1ull)) continue;
+        if (!((sh.it.m[j][e] >> p) & 1ull)) continue;
         float N[3];
         bc.eval(r, tau[j] - tc, N);
         const float D = N[0] + N[1] + N[2];
         if (!(fabsf(D) > kTauDet)) continue;
         const bool cov = D > 0.0f ? fminf(N[0], fminf(N[1], N[2])) >= 0.0f : fmaxf(N[0], fmaxf(N[1], N[2])) <= 0.0f;
         if (!cov) continue;
-        const float invD = 1.0f / D;
         float zt[3];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) zt[q] = fmaf(tau[j], r.aux1[q], r.aux0[q]);
-        const float z = fmaf(N[0], zt[0], fmaf(N[1], zt[1], N[2] * zt[2])) * invD;
+        for (int q = 0; q < 3; ++q) zt[q] = fmaf(tau[j], r.at(R_A1 + q), r.at(R_A0 + q));
+        const float z = fmaf(N[0], zt[0], fmaf(N[1], zt[1], N[2] * zt[2])) * rcp(D);
         // z > 0 (all vertices in front of the camera), so its bits order like its value
-        atomicMin(&sh.u.zb[j][p], ((unsigned long long)__float_as_uint(z) << 32) | f);
-    }
-}
-
-// background item: eqs 10, 13-15, accumulated as log2(1 - A)
-template <int T, int SOLVER>
-__device__ __forceinline__ void bg_item_fwd(const RasterArgs &a, FwdShared<T> &sh, int e, int p, const float tau[T],
-                                            uint32_t xbits, float tc)
-{
-    const FaceRec &r = sh.it.rec[e];
-    const float du = lane_du(p, a.W), dv = lane_dv(p, a.H);
-    Bary<SOLVER> bc;
-    bc.setup(r, tc, du, dv);
-#pragma unroll
-    for (int j = 0; j < T; ++j) {
-        if (!((sh.it.m[e][j] >> p) & 1ull)) continue;
-        float N[3];
-        bc.eval(r, tau[j] - tc, N);
-        const float D = N[0] + N[1] + N[2];
-        if (!(fabsf(D) > kTauDet)) continue;
-        BgEval b;
-        bg_eval(r, tc, tau[j], (xbits >> j) & 1u, N, 1.0f / D, du, dv, b);
-        if (!(b.d <= a.dmax)) continue;
-        const float A = exp2f(b.d * a.neg_log2e_over_delta);
-        const float om = one_minus_exp_neg(b.d * a.inv_delta, A);
-        if (om > 0.0f)
-            atomicAdd(&sh.u.bg.lsum[j][p], log2_one_minus(A, om));
-        else
-            atomicAdd(&sh.u.bg.nz[j][p], 1);
+        atomicMin(&sh.zb[j][p], ((unsigned long long)__float_as_uint(z) << 32) | f);
     }
 }
 
@@ -924,7 +965,7 @@ __device__ __forceinline__ void bg_item_fwd(const RasterArgs &a, FwdShared<T> &s
 // of the vertex attributes (eq 9), from the same float32 record the depth
 // test used
 template <int SOLVER>
-__device__ __forceinline__ void shade_winner(const RasterArgs &a, int f, int s, const TileGeom &g, float tc, float tau,
+__device__ __forceinline__ void shade_winner(const RasterArgs &a, int f, int s, const TileCtx &g, float tc, float tau,
                                              float rgb[NCH])
 {
     FaceRec r;
@@ -934,7 +975,7 @@ __device__ __forceinline__ void shade_winner(const RasterArgs &a, int f, int s, 
     bc.setup(r, tc, g.du, g.dv);
     float N[3];
     bc.eval(r, tau - tc, N);
-    const float invD = 1.0f / (N[0] + N[1] + N[2]);
+    const float invD = rcp(N[0] + N[1] + N[2]);
     const float w0 = N[0] * invD, w1 = N[1] * invD, w2 = N[2] * invD;
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) {
@@ -946,125 +987,210 @@ __device__ __forceinline__ void shade_winner(const RasterArgs &a, int f, int s, 
 }
 
 template <int T, int SOLVER>
-__global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a)
+__global__ __launch_bounds__(64) void k_fg(RasterArgs a)
 {
-    __shared__ FwdShared<T> shm[4];
-    TileGeom g;
-    if (!tile_geom(a, g)) return;
-    if (a.hdr->error_bits & kHdrOverflow) return;
+    __shared__ FgShared<T> sh;
+    const int64_t ct = xcd_remap(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x & 63;
-    FwdShared<T> &sh = shm[threadIdx.x >> 6];
+    TileCtx g;
+    tile_ctx(a, ct, g);
+    const Chunk &ck = g.ck;
+    if (a.hdr->error_bits & kHdrOverflow) {
+        if (lane == 0) a.tsl[ct] = 0;
+        return;
+    }
+    if (ck.n <= 0) {
+        if (lane == 0) a.tsl[ct] = 0;
+        return;
+    }
     const uint64_t inimg = __ballot(g.inimg);
-    float acc[NCH + 1];
+    float tau[T];
+    uint32_t xbits;
+    chunk_taus<T>(a, ck, tau, xbits);
+    const float tc = chunk_centre<T>(tau, ck.n);
+    uint64_t allow[T];
 #pragma unroll
-    for (int ch = 0; ch <= NCH; ++ch) acc[ch] = 0.0f;
+    for (int j = 0; j < T; ++j) {
+        allow[j] = j < ck.n ? inimg : 0ull;
+        sh.zb[j][lane] = ~0ull;
+    }
+    {
+        const int64_t idx = ct;   // foreground list of (chunk, tile)
+        const int64_t beg = a.off[idx];
+        const int n_e = a.cnt[idx];
+        for (int base = 0; base < n_e; base += NB) {
+            const int nb = min(NB, n_e - base);
+            int cnt, pre;
+            const int total =
+                stage_items<T>(a, sh.it, beg + base, nb, ck.s, g, tc, tau, kRecFg, 0.0f, allow, nullptr, cnt, pre);
+            for_items<T>(sh.it, total, cnt, pre, [&](int e, int p) { fg_item<T, SOLVER>(a, sh, e, p, tau, tc); });
+        }
+    }
+    lds_sync();
+    bool anyunc = false;
+#pragma unroll
+    for (int j = 0; j < T; ++j) {
+        if (j >= ck.n) continue;
+        const int k = ck.k0 + j;
+        const unsigned long long key = sh.zb[j][lane];
+        const int zid = key == ~0ull ? -1 : (int)(uint32_t)key;
+        anyunc = anyunc || __ballot(g.inimg && zid < 0) != 0ull;
+        float rgb[NCH];
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) rgb[ch] = 0.0f;
+        if (g.inimg && zid >= 0) shade_winner<SOLVER>(a, zid, ck.s, g, tc, tau[j], rgb);
+        a.vis_id[vis_index(a, g.tile, k, lane)] = g.inimg ? zid : kVisOut;
+        // colour of a covered pixel; the background accumulators start at 0
+        for (int sl = 0; sl < a.NS; ++sl) {
+            float v = 0.0f;
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch)
+                if (ch == sl) v = rgb[ch];
+            a.pix[pix_index(a, g.tile, k, sl, lane)] = v;
+        }
+    }
+    if (lane == 0) {
+        const int n_bg = a.cnt[(int64_t)a.NC * a.ntiles + ct];
+        a.tsl[ct] = anyunc ? (n_bg + a.SL - 1) / a.SL : 0;
+    }
+}
 
-    const int c_end = min((g.grp + 1) * a.G, a.NC);
-    for (int c = g.grp * a.G; c < c_end; ++c) {
-        const Chunk ck = chunk_info(c, a.K, a.S, a.CPS);
-        if (ck.n <= 0) continue;
+// write the task list: tasks[toff[ct] + i] = (ct, i), i < tsl[ct]
+__global__ void k_tasks(const int32_t *__restrict__ tsl, const int64_t *__restrict__ toff, int64_t ntct,
+                        uint64_t *__restrict__ tasks, int64_t maxtasks)
+{
+    const int64_t ct = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (ct >= ntct) return;
+    const int n = tsl[ct];
+    const int64_t o = toff[ct];
+    for (int i = 0; i < n; ++i)
+        if (o + i < maxtasks) tasks[o + i] = ((uint64_t)ct << 32) | (uint32_t)i;
+}
+
+// --------------------------------------------------------- forward: k_bg
+
+template <int T>
+struct BgShared {
+    ItemShared<T> it;
+    float lsum[T][kWave];   // sum of log2(1 - A) over non-zero factors
+    int nz[T][kWave];       // number of zero factors (A == 1)
+};
+
+// background item: eqs 10, 13-15, accumulated as log2(1 - A)
+template <int T, int SOLVER>
+__device__ __forceinline__ void bg_item_fwd(const RasterArgs &a, BgShared<T> &sh, int e, int p, const float tau[T],
+                                            uint32_t xbits, float tc)
+{
+    const LdsRec r = lds_rec(sh.it, e);
+    const float du = pix_du(p, a.inv_w), dv = pix_dv(p, a.inv_h);
+    Bary<SOLVER> bc;
+    bc.setup(r, tc, du, dv);
+#pragma unroll
+    for (int j = 0; j < T; ++j) {
+        if (!((sh.it.m[j][e] >> p) & 1ull)) continue;
+        float N[3];
+        bc.eval(r, tau[j] - tc, N);
+        const float D = N[0] + N[1] + N[2];
+        if (!(fabsf(D) > kTauDet)) continue;
+        BgEval b;
+        bg_eval(r, tc, tau[j], (xbits >> j) & 1u, N, rcp(D), du, dv, b);
+        if (!(b.d <= a.dmax)) continue;
+        const float A = exp2f(b.d * a.neg_log2e_over_delta);
+        const float om = one_minus_exp_neg(b.d * a.inv_delta, A);
+        if (om > 0.0f)
+            atomicAdd(&sh.lsum[j][p], log2_one_minus(A, om));
+        else
+            atomicAdd(&sh.nz[j][p], 1);
+    }
+}
+
+template <int T, int SOLVER>
+__global__ __launch_bounds__(64) void k_bg(RasterArgs a)
+{
+    __shared__ BgShared<T> sh;
+    const int lane = threadIdx.x & 63;
+    if (a.hdr->error_bits & kHdrOverflow) return;
+    const int64_t ntasks = a.hdr->ntasks;
+    for (;;) {
+        const int64_t t = next_task(&a.hdr->task_ctr[0]);
+        if (t >= ntasks || t >= a.maxtasks) break;
+        const uint64_t task = a.tasks[t];
+        const int64_t ct = (int64_t)(task >> 32);
+        const int slice = (int)(uint32_t)task;
+        TileCtx g;
+        tile_ctx(a, ct, g);
+        const Chunk &ck = g.ck;
         float tau[T];
         uint32_t xbits;
         chunk_taus<T>(a, ck, tau, xbits);
         const float tc = chunk_centre<T>(tau, ck.n);
-        uint64_t allow[T];
-#pragma unroll
-        for (int j = 0; j < T; ++j) allow[j] = j < ck.n ? inimg : 0ull;
-
-        // ---- foreground: z-buffer over the tile's foreground list (eq 9)
-        lds_sync();
-#pragma unroll
-        for (int j = 0; j < T; ++j) sh.u.zb[j][lane] = ~0ull;
-        {
-            const int64_t idx = (int64_t)c * a.ntiles + g.tile;
-            const int64_t beg = a.off[idx];
-            const int n_e = a.cnt[idx];
-            for (int base = 0; base < n_e; base += NB) {
-                const int nb = min(NB, n_e - base);
-                int cnt, pre;
-                const int total = stage_items<T>(a, sh.it, beg + base, nb, ck.s, g, tc, tau, kRecFg, 0.0f, allow,
-                                                 nullptr, nullptr, cnt, pre);
-                for_items<T>(sh.it, total, cnt, pre, [&](int e, int p) { fg_item<T, SOLVER>(a, sh, e, p, tau, tc); });
-            }
-        }
-        lds_sync();
-        int zid[T];
         uint64_t unc[T];
-        bool anybg = false;
+        lds_sync();
 #pragma unroll
         for (int j = 0; j < T; ++j) {
-            const unsigned long long key = sh.u.zb[j][lane];
-            zid[j] = key == ~0ull ? -1 : (int)(uint32_t)key;
-            unc[j] = __ballot(zid[j] < 0) & allow[j];
-            anybg = anybg || unc[j] != 0ull;
+            const int vid = j < ck.n ? a.vis_id[vis_index(a, g.tile, ck.k0 + j, lane)] : kVisOut;
+            unc[j] = __ballot(vid == -1);
+            sh.lsum[j][lane] = 0.0f;
+            sh.nz[j][lane] = 0;
+        }
+        const int64_t idx = (int64_t)a.NC * a.ntiles + ct;
+        const int64_t beg = a.off[idx];
+        const int n_e = a.cnt[idx];
+        const int e0 = slice * a.SL, e1 = min(n_e, e0 + a.SL);
+        for (int base = e0; base < e1; base += NB) {
+            const int nb = min(NB, e1 - base);
+            int cnt, pre;
+            const int total =
+                stage_items<T>(a, sh.it, beg + base, nb, ck.s, g, tc, tau, kRecBg, a.halo, unc, nullptr, cnt, pre);
+            for_items<T>(sh.it, total, cnt, pre,
+                         [&](int e, int p) { bg_item_fwd<T, SOLVER>(a, sh, e, p, tau, xbits, tc); });
         }
         lds_sync();
 #pragma unroll
         for (int j = 0; j < T; ++j) {
-            sh.u.bg.lsum[j][lane] = 0.0f;
-            sh.u.bg.nz[j][lane] = 0;
-        }
-
-        // ---- background: soft aggregation (eqs 10, 13-15) where uncovered
-        if (anybg) {
-            const int64_t idx = ((int64_t)a.NC + c) * a.ntiles + g.tile;
-            const int64_t beg = a.off[idx];
-            const int n_e = a.cnt[idx];
-            for (int base = 0; base < n_e; base += NB) {
-                const int nb = min(NB, n_e - base);
-                int cnt, pre;
-                const int total = stage_items<T>(a, sh.it, beg + base, nb, ck.s, g, tc, tau, kRecBg, a.halo, unc,
-                                                 nullptr, nullptr, cnt, pre);
-                for_items<T>(sh.it, total, cnt, pre,
-                             [&](int e, int p) { bg_item_fwd<T, SOLVER>(a, sh, e, p, tau, xbits, tc); });
-            }
-        }
-
-        // ---- shade, store visibility, accumulate the sub-frame average
-        lds_sync();
-#pragma unroll
-        for (int j = 0; j < T; ++j) {
-            if (j >= ck.n) continue;
-            const size_t vi = ((size_t)g.tile * a.K + (ck.k0 + j)) * kWave + lane;
-            if (!g.inimg) {
-                a.vis_id[vi] = -4;
-                a.vis_p[vi] = 0.0f;
-            } else if (zid[j] >= 0) {
-                float rgb[NCH];
-                shade_winner<SOLVER>(a, zid[j], ck.s, g, tc, tau[j], rgb);
-#pragma unroll
-                for (int ch = 0; ch < NCH; ++ch) acc[ch] += rgb[ch];
-                acc[NCH] += 1.0f;
-                a.vis_id[vi] = zid[j];
-                a.vis_p[vi] = 0.0f;
-            } else {
-                const int nz = sh.u.bg.nz[j][lane];
-                const float P = exp2f(sh.u.bg.lsum[j][lane]);
-                acc[NCH] += nz > 0 ? 1.0f : 1.0f - P;
-                a.vis_id[vi] = -1 - min(nz, 2);
-                a.vis_p[vi] = P;
-            }
+            if (!((unc[j] >> lane) & 1ull)) continue;
+            const float ls = sh.lsum[j][lane];
+            const int nz = sh.nz[j][lane];
+            if (ls != 0.0f) unsafeAtomicAdd(&a.pix[pix_index(a, g.tile, ck.k0 + j, 0, lane)], ls);
+            if (nz) atomicAdd((int *)&a.pix[pix_index(a, g.tile, ck.k0 + j, 1, lane)], nz);
         }
     }
-    float *out = a.part + ((size_t)g.grp * a.ntiles + g.tile) * (a.C + 1) * kWave + lane;
-    for (int ch = 0; ch < a.C; ++ch) out[(size_t)ch * kWave] = acc[ch];
-    out[(size_t)a.C * kWave] = acc[NCH];
 }
 
-__global__ void k_reduce_image(const float *__restrict__ part, float *__restrict__ image, int C, int W, int H,
-                               int tiles_x, int ntiles, int NG, float invK, const DevHeader *hdr)
+// ---------------------------------------------------- forward: k_resolve
+
+// image = mean over the K sub-frames of the winner's colour (premultiplied,
+// alpha 1) or, where uncovered, alpha = 1 - prod (1 - A) (eq 15)
+__global__ __launch_bounds__(64) void k_resolve(RasterArgs a, float *__restrict__ image)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t n = (int64_t)(C + 1) * W * H;
-    if (i >= n) return;
-    int ch = (int)(i / ((int64_t)W * H));
-    int rem = (int)(i - (int64_t)ch * W * H);
-    int y = rem / W, x = rem - y * W;
-    int tile = (y / kTile) * tiles_x + x / kTile;
-    int lane = (y % kTile) * kTile + (x % kTile);
-    double s = 0.0;
-    for (int gq = 0; gq < NG; ++gq) s += part[(((size_t)gq * ntiles + tile) * (C + 1) + ch) * kWave + lane];
-    image[i] = (hdr->error_bits & kHdrOverflow) ? __builtin_nanf("") : (float)(s * (double)invK);
+    const int lane = threadIdx.x & 63;
+    const int tile = blockIdx.x;
+    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+    const int px = tx * kTile + (lane & 7), py = ty * kTile + (lane >> 3);
+    if (px >= a.W || py >= a.H) return;
+    double acc[NCH + 1];
+#pragma unroll
+    for (int ch = 0; ch <= NCH; ++ch) acc[ch] = 0.0;
+    for (int k = 0; k < a.K; ++k) {
+        const int vid = a.vis_id[vis_index(a, tile, k, lane)];
+        if (vid >= 0) {
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch)
+                if (ch < a.C) acc[ch] += (double)a.pix[pix_index(a, tile, k, ch, lane)];
+            acc[NCH] += 1.0;
+        } else {
+            const float ls = a.pix[pix_index(a, tile, k, 0, lane)];
+            const int nz = __float_as_int(a.pix[pix_index(a, tile, k, 1, lane)]);
+            acc[NCH] += nz > 0 ? 1.0 : (double)(1.0f - exp2f(ls));
+        }
+    }
+    const bool bad = (a.hdr->error_bits & kHdrOverflow) != 0;
+    const double invK = 1.0 / (double)a.K;
+    const size_t plane = (size_t)a.H * a.W, at = (size_t)py * a.W + px;
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+        if (ch < a.C) image[ch * plane + at] = bad ? __builtin_nanf("") : (float)(acc[ch] * invK);
+    image[a.C * plane + at] = bad ? __builtin_nanf("") : (float)(acc[NCH] * invK);
 }
 
 // ---------------------------------------------------------------- adjoint
@@ -1076,67 +1202,65 @@ struct GradArgs {
     float invK;
 };
 
-template <int T>
-struct BwdShared {
-    ItemShared<T> it;
-    float at[NB][3][NCH];     // staged entries' vertex attributes (foreground)
-    int vid[NB][3];           // staged entries' vertex indices
-    float gacc[NB][NGA];      // per-entry gradient slots
-    float P[T][kWave];        // forward product over non-zero factors
-    int nz[T][kWave];
-    float gI[NCH + 1][kWave]; // dL/d(colour, alpha) of each pixel, already divided by K
-    int hkey[kHash];          // face -> staged entry (open addressing, -1 = empty)
-    int hval[kHash];
-    uint32_t q[T * kWave];    // foreground items: entry | pixel << 8 | sub-frame << 16
-};
-
 __device__ __forceinline__ int hash_face(int f) { return (int)(((uint32_t)f * 2654435761u) >> 25); }
 
 // Add a lane's per-entry contribution to the entry's LDS slot.
-__device__ __forceinline__ void slot_add(float *slot, int i, float v)
+__device__ __forceinline__ void slot_add(float (*gacc)[NB], int e, int i, float v)
 {
-    if (v != 0.0f) atomicAdd(&slot[i], v);
+    if (v != 0.0f) atomicAdd(&gacc[i][e], v);
 }
 
 // Flush the staged entries' gradient slots to global memory and clear them.
-template <int T>
-__device__ __forceinline__ void flush_slots(BwdShared<T> &sh, int nb, int s, const RasterArgs &a, const GradArgs &ga,
-                                            bool with_attr)
+__device__ __forceinline__ void flush_slots(float (*gacc)[NB], const int (*vids)[3], int nb, int s,
+                                            const RasterArgs &a, const GradArgs &ga, bool with_attr)
 {
     const int lane = threadIdx.x & 63;
     lds_sync();
     if (lane < nb) {
-        float *slot = sh.gacc[lane];
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            const int v = sh.vid[lane][q];
+            const int v = vids[lane][q];
 #pragma unroll
             for (int sl = 0; sl < 2; ++sl) {
                 float *p = ga.gkf + ((size_t)(s + sl) * a.V + v) * 2;
-                const float gx = slot[q * 4 + sl * 2], gy = slot[q * 4 + sl * 2 + 1];
+                const float gx = gacc[q * 4 + sl * 2][lane], gy = gacc[q * 4 + sl * 2 + 1][lane];
                 if (gx != 0.0f) unsafeAtomicAdd(p, gx);
                 if (gy != 0.0f) unsafeAtomicAdd(p + 1, gy);
             }
             if (with_attr)
                 for (int c = 0; c < a.C; ++c) {
-                    const float gv = slot[12 + q * NCH + c];
+                    const float gv = gacc[12 + q * NCH + c][lane];
                     if (gv != 0.0f) unsafeAtomicAdd(ga.gattr + (size_t)v * a.C + c, gv);
                 }
         }
 #pragma unroll
-        for (int i = 0; i < NGA; ++i) slot[i] = 0.0f;
+        for (int i = 0; i < NGA; ++i) gacc[i][lane] = 0.0f;
     }
     lds_sync();
 }
+
+// ------------------------------------------------------- backward: k_fg_bwd
+
+template <int T>
+struct FgBwdShared {
+    ItemShared<T> it;
+    float at[3 * NCH][NB];    // staged entries' vertex attributes
+    int vid[NB][3];           // staged entries' vertex indices
+    float gacc[NGA][NB];      // per-entry gradient slots
+    float gI[NCH][kWave];     // dL/dcolour of each pixel, already divided by K
+    int hkey[kHash];          // face -> staged entry (open addressing, -1 = empty)
+    int hval[kHash];
+    uint32_t q[T * kWave];    // items: entry | pixel << 8 | sub-frame << 16
+};
 
 // Foreground adjoint of one (pixel, sub-frame) whose winner is staged entry e:
 // colour = sum_i w_i c_i, dL/dw through the static solve (dw = -F^-1 dF w),
 // dL/dc_i = w_i dL/dcolour.
 template <int T, int SOLVER>
-__device__ __forceinline__ void fg_item_bwd(const RasterArgs &a, BwdShared<T> &sh, int e, int p, float tau, float tc)
+__device__ __forceinline__ void fg_item_bwd(const RasterArgs &a, FgBwdShared<T> &sh, int e, int p, float tau, float tc)
 {
-    const FaceRec &r = sh.it.rec[e];
-    const float du = lane_du(p, a.W), dv = lane_dv(p, a.H);
+    const LdsRec r = lds_rec(sh.it, e);
+    const float du = pix_du(p, a.inv_w), dv = pix_dv(p, a.inv_h);
     float gI[NCH], gw[3];
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) gI[ch] = sh.gI[ch][p];
@@ -1144,47 +1268,162 @@ __device__ __forceinline__ void fg_item_bwd(const RasterArgs &a, BwdShared<T> &s
     for (int q = 0; q < 3; ++q) {
         gw[q] = 0.0f;
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) gw[q] = fmaf(gI[ch], sh.at[e][q][ch], gw[q]);
+        for (int ch = 0; ch < NCH; ++ch) gw[q] = fmaf(gI[ch], sh.at[q * NCH + ch][e], gw[q]);
     }
     Bary<SOLVER> bc;
     bc.setup(r, tc, du, dv);
     const float t = tau - tc;
     float N[3];
     bc.eval(r, t, N);
-    const float invD = 1.0f / (N[0] + N[1] + N[2]);
+    const float invD = rcp(N[0] + N[1] + N[2]);
     const float w[3] = {N[0] * invD, N[1] * invD, N[2] * invD};
     float xt[3], yt[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-        xt[q] = fmaf(t, r.dx[q], r.xc[q]);
-        yt[q] = fmaf(t, r.dy[q], r.yc[q]);
+        xt[q] = fmaf(t, r.at(R_DX + q), r.at(R_XC + q));
+        yt[q] = fmaf(t, r.at(R_DY + q), r.at(R_YC + q));
     }
     const float gxs = fmaf(gw[0], yt[1] - yt[2], fmaf(gw[1], yt[2] - yt[0], gw[2] * (yt[0] - yt[1]))) * invD;
     const float gys = fmaf(gw[0], xt[2] - xt[1], fmaf(gw[1], xt[0] - xt[2], gw[2] * (xt[1] - xt[0]))) * invD;
     const float t1 = tau, t0 = 1.0f - tau;
-    float *slot = sh.gacc[e];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
         const float gx = -w[q] * gxs, gy = -w[q] * gys;
-        slot_add(slot, q * 4 + 0, t0 * gx);
-        slot_add(slot, q * 4 + 1, t0 * gy);
-        slot_add(slot, q * 4 + 2, t1 * gx);
-        slot_add(slot, q * 4 + 3, t1 * gy);
+        slot_add(sh.gacc, e, q * 4 + 0, t0 * gx);
+        slot_add(sh.gacc, e, q * 4 + 1, t0 * gy);
+        slot_add(sh.gacc, e, q * 4 + 2, t1 * gx);
+        slot_add(sh.gacc, e, q * 4 + 3, t1 * gy);
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) slot_add(slot, 12 + q * NCH + ch, w[q] * gI[ch]);
+        for (int ch = 0; ch < NCH; ++ch) slot_add(sh.gacc, e, 12 + q * NCH + ch, w[q] * gI[ch]);
     }
 }
+
+template <int T, int SOLVER>
+__global__ __launch_bounds__(64) void k_fg_bwd(RasterArgs a, GradArgs ga)
+{
+    __shared__ FgBwdShared<T> sh;
+    const int64_t ct = xcd_remap(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x & 63;
+    if (a.hdr->error_bits & kHdrOverflow) return;
+    TileCtx g;
+    tile_ctx(a, ct, g);
+    const Chunk &ck = g.ck;
+    if (ck.n <= 0) return;
+    bool gcol = false;
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+        float v = 0.0f;
+        if (g.inimg && ch < a.C) v = ga.grad_image[((size_t)ch * a.H + g.py) * a.W + g.px] * ga.invK;
+        sh.gI[ch][lane] = v;
+        gcol = gcol || v != 0.0f;
+    }
+    int vid[T];
+    bool anyfg = false;
+#pragma unroll
+    for (int j = 0; j < T; ++j) {
+        vid[j] = j < ck.n ? a.vis_id[vis_index(a, g.tile, ck.k0 + j, lane)] : kVisOut;
+        anyfg = anyfg || __ballot(gcol && vid[j] >= 0) != 0ull;
+    }
+    if (!anyfg) return;
+    if (lane < NB)
+        for (int i = 0; i < NGA; ++i) sh.gacc[i][lane] = 0.0f;
+    sh.hkey[lane] = -1;
+    sh.hkey[lane + kWave] = -1;
+    float tau[T];
+    uint32_t xbits;
+    chunk_taus<T>(a, ck, tau, xbits);
+    const float tc = chunk_centre<T>(tau, ck.n);
+
+    const int64_t beg = a.off[ct];
+    const int n_e = a.cnt[ct];
+    for (int base = 0; base < n_e; base += NB) {
+        const int nb = min(NB, n_e - base);
+        lds_sync();
+        int hb = -1;
+        if (lane < nb) {
+            const uint32_t ent = a.list[beg + base + lane];
+            const int f = (int)(ent >> 8);
+            FaceRec r;
+            int vq[3];
+            stage_rec(a, f, ck.s, g.ua, g.va, tc, kRecGeom, r, vq);
+            store_rec(sh.it, lane, r);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                sh.vid[lane][q] = vq[q];
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch)
+                    sh.at[q * NCH + ch][lane] = ch < a.C ? a.attrs[(size_t)vq[q] * a.C + ch] : 0.0f;
+            }
+            // faces are unique within a list and NB < kHash: an empty
+            // bucket is always found
+            int h = hash_face(f);
+            for (int probe = 0; probe < kHash; ++probe) {
+                if (atomicCAS(&sh.hkey[h], -1, f) == -1) {
+                    hb = h;
+                    break;
+                }
+                h = (h + 1) & (kHash - 1);
+            }
+            if (hb >= 0) sh.hval[hb] = lane;
+        }
+        lds_sync();
+        int qn = 0;
+#pragma unroll
+        for (int j = 0; j < T; ++j) {
+            int sl = -1;
+            if (gcol && vid[j] >= 0) {
+                int h = hash_face(vid[j]);
+                for (int probe = 0; probe < kHash; ++probe) {
+                    const int k = sh.hkey[h];
+                    if (k == vid[j]) {
+                        sl = sh.hval[h];
+                        break;
+                    }
+                    if (k == -1) break;
+                    h = (h + 1) & (kHash - 1);
+                }
+            }
+            const uint64_t bal = __ballot(sl >= 0);
+            if (sl >= 0) sh.q[qn + lane_rank(bal)] = (uint32_t)sl | ((uint32_t)lane << 8) | ((uint32_t)j << 16);
+            qn += __popcll(bal);
+        }
+        lds_sync();
+        for (int rb = 0; rb < qn; rb += kWave) {
+            if (rb + lane < qn) {
+                const uint32_t item = sh.q[rb + lane];
+                int X;
+                const float tj = chunk_tau(a, ck, (int)(item >> 16), X);
+                fg_item_bwd<T, SOLVER>(a, sh, (int)(item & 0xffu), (int)((item >> 8) & 0xffu), tj, tc);
+            }
+        }
+        lds_sync();
+        if (hb >= 0) sh.hkey[hb] = -1;
+        flush_slots(sh.gacc, sh.vid, nb, ck.s, a, ga, true);
+    }
+}
+
+// ------------------------------------------------------- backward: k_bg_bwd
+
+template <int T>
+struct BgBwdShared {
+    ItemShared<T> it;
+    int vid[NB][3];
+    float gacc[NGA][NB];
+    float P[T][kWave];        // forward product over non-zero factors
+    int nz[T][kWave];
+    float gal[kWave];         // dL/dalpha of each pixel, already divided by K
+};
 
 // Background adjoint of one item: dalpha/dA_j = prod_{m != j}(1 - A_m),
 // dA/dd = -A/delta, then the chain through d = |p - p*|^2, the closest point
 // (edge parameter where unclamped), q = F(X) w and w(tau) (dw = -F^-1 dF w).
 template <int T, int SOLVER>
-__device__ __forceinline__ void bg_item_bwd(const RasterArgs &a, BwdShared<T> &sh, int e, int p, const float tau[T],
-                                            uint32_t xbits, float tc)
+__device__ __forceinline__ void bg_item_bwd(const RasterArgs &a, BgBwdShared<T> &sh, int e, int p,
+                                            const float tau[T], uint32_t xbits, float tc)
 {
-    const FaceRec &r = sh.it.rec[e];
-    const float du = lane_du(p, a.W), dv = lane_dv(p, a.H);
-    const float galpha = sh.gI[NCH][p];
+    const LdsRec r = lds_rec(sh.it, e);
+    const float du = pix_du(p, a.inv_w), dv = pix_dv(p, a.inv_h);
+    const float galpha = sh.gal[p];
     Bary<SOLVER> bc;
     bc.setup(r, tc, du, dv);
     float gK[12];
@@ -1192,13 +1431,13 @@ __device__ __forceinline__ void bg_item_bwd(const RasterArgs &a, BwdShared<T> &s
     for (int q = 0; q < 12; ++q) gK[q] = 0.0f;
 #pragma unroll
     for (int j = 0; j < T; ++j) {
-        if (!((sh.it.m[e][j] >> p) & 1ull)) continue;
+        if (!((sh.it.m[j][e] >> p) & 1ull)) continue;
         const float t = tau[j] - tc;
         float N[3];
         bc.eval(r, t, N);
         const float D = N[0] + N[1] + N[2];
         if (!(fabsf(D) > kTauDet)) continue;
-        const float invD = 1.0f / D;
+        const float invD = rcp(D);
         const int X = (xbits >> j) & 1u;
         BgEval b;
         bg_eval(r, tc, tau[j], X, N, invD, du, dv, b);
@@ -1214,8 +1453,8 @@ __device__ __forceinline__ void bg_item_bwd(const RasterArgs &a, BwdShared<T> &s
         float xt[3], yt[3];
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            xt[q] = fmaf(t, r.dx[q], r.xc[q]);
-            yt[q] = fmaf(t, r.dy[q], r.yc[q]);
+            xt[q] = fmaf(t, r.at(R_DX + q), r.at(R_XC + q));
+            yt[q] = fmaf(t, r.at(R_DY + q), r.at(R_YC + q));
         }
         // per-vertex gradient at tau (gt) and at keyframe X (gk)
         float gtx[3], gty[3], gkx[3], gky[3];
@@ -1230,8 +1469,8 @@ __device__ __forceinline__ void bg_item_bwd(const RasterArgs &a, BwdShared<T> &s
         const bool interior = !(b.sr < 0.0f) && !(b.sr > 1.0f);
         if (interior) {
             const int ea = b.be;
-            float Ex[3], Ey[3], iee3[3];
-            kedges(r, X, tc, Ex, Ey, iee3);
+            float Ex[3], Ey[3], iee3[3], kx[3], ky[3];
+            kedges(r, X, tc, Ex, Ey, iee3, kx, ky);
             const float exs = ea == 0 ? Ex[0] : (ea == 1 ? Ex[1] : Ex[2]);
             const float eys = ea == 0 ? Ey[0] : (ea == 1 ? Ey[1] : Ey[2]);
             const float iee = ea == 0 ? iee3[0] : (ea == 1 ? iee3[1] : iee3[2]);
@@ -1274,157 +1513,68 @@ __device__ __forceinline__ void bg_item_bwd(const RasterArgs &a, BwdShared<T> &s
             gK[q * 4 + 3] += fmaf(t1, gty[q], X ? gky[q] : 0.0f);
         }
     }
-    float *slot = sh.gacc[e];
 #pragma unroll
-    for (int q = 0; q < 12; ++q) slot_add(slot, q, gK[q]);
+    for (int q = 0; q < 12; ++q) slot_add(sh.gacc, e, q, gK[q]);
 }
 
 template <int T, int SOLVER>
-__global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a, GradArgs ga)
+__global__ __launch_bounds__(64) void k_bg_bwd(RasterArgs a, GradArgs ga)
 {
-    __shared__ BwdShared<T> shm[4];
-    TileGeom g;
-    if (!tile_geom(a, g)) return;
-    if (a.hdr->error_bits & kHdrOverflow) return;
+    __shared__ BgBwdShared<T> sh;
     const int lane = threadIdx.x & 63;
-    BwdShared<T> &sh = shm[threadIdx.x >> 6];
-    bool gcol = false;
-    float gal = 0.0f;
-#pragma unroll
-    for (int ch = 0; ch < NCH; ++ch) {
-        float v = 0.0f;
-        if (g.inimg && ch < a.C) v = ga.grad_image[((size_t)ch * a.H + g.py) * a.W + g.px] * ga.invK;
-        sh.gI[ch][lane] = v;
-        gcol = gcol || v != 0.0f;
-    }
-    if (g.inimg) gal = ga.grad_image[((size_t)a.C * a.H + g.py) * a.W + g.px] * ga.invK;
-    sh.gI[NCH][lane] = gal;
+    if (a.hdr->error_bits & kHdrOverflow) return;
     if (lane < NB)
-        for (int i = 0; i < NGA; ++i) sh.gacc[lane][i] = 0.0f;
-    sh.hkey[lane] = -1;
-    sh.hkey[lane + kWave] = -1;
-
-    const int c_end = min((g.grp + 1) * a.G, a.NC);
-    for (int c = g.grp * a.G; c < c_end; ++c) {
-        const Chunk ck = chunk_info(c, a.K, a.S, a.CPS);
-        if (ck.n <= 0) continue;
+        for (int i = 0; i < NGA; ++i) sh.gacc[i][lane] = 0.0f;
+    const int64_t ntasks = a.hdr->ntasks;
+    for (;;) {
+        const int64_t t = next_task(&a.hdr->task_ctr[1]);
+        if (t >= ntasks || t >= a.maxtasks) break;
+        const uint64_t task = a.tasks[t];
+        const int64_t ct = (int64_t)(task >> 32);
+        const int slice = (int)(uint32_t)task;
+        TileCtx g;
+        tile_ctx(a, ct, g);
+        const Chunk &ck = g.ck;
+        const float gal = g.inimg ? ga.grad_image[((size_t)a.C * a.H + g.py) * a.W + g.px] * ga.invK : 0.0f;
         float tau[T];
         uint32_t xbits;
         chunk_taus<T>(a, ck, tau, xbits);
         const float tc = chunk_centre<T>(tau, ck.n);
-        int vid[T];
-        lds_sync();
-#pragma unroll
-        for (int j = 0; j < T; ++j) {
-            vid[j] = -4;
-            float vp = 0.0f;
-            if (j < ck.n) {
-                const size_t vi = ((size_t)g.tile * a.K + (ck.k0 + j)) * kWave + lane;
-                vid[j] = a.vis_id[vi];
-                vp = a.vis_p[vi];
-            }
-            sh.P[j][lane] = vp;
-            sh.nz[j][lane] = vid[j] <= -1 && vid[j] >= -3 ? -1 - vid[j] : 0;
-        }
-
-        // ---- foreground: each (pixel, sub-frame) finds its winner among the
-        //      staged entries through the hash table
-        bool anyfg = false;
-#pragma unroll
-        for (int j = 0; j < T; ++j) anyfg = anyfg || __ballot(gcol && vid[j] >= 0) != 0ull;
-        if (anyfg) {
-            const int64_t idx = (int64_t)c * a.ntiles + g.tile;
-            const int64_t beg = a.off[idx];
-            const int n_e = a.cnt[idx];
-            for (int base = 0; base < n_e; base += NB) {
-                const int nb = min(NB, n_e - base);
-                lds_sync();
-                int hb = -1;
-                if (lane < nb) {
-                    const uint32_t ent = a.list[beg + base + lane];
-                    const int f = (int)(ent >> 8);
-                    FaceRec r;
-                    int vq[3];
-                    stage_rec(a, f, ck.s, g.ua, g.va, tc, kRecGeom, r, vq);
-                    r.msk = ent & 0xffu;
-                    sh.it.rec[lane] = r;
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) {
-                        sh.vid[lane][q] = vq[q];
-#pragma unroll
-                        for (int ch = 0; ch < NCH; ++ch)
-                            sh.at[lane][q][ch] = ch < a.C ? a.attrs[(size_t)vq[q] * a.C + ch] : 0.0f;
-                    }
-                    // faces are unique within a list and NB < kHash: an empty
-                    // bucket is always found
-                    int h = hash_face(f);
-                    for (int probe = 0; probe < kHash; ++probe) {
-                        if (atomicCAS(&sh.hkey[h], -1, f) == -1) {
-                            hb = h;
-                            break;
-                        }
-                        h = (h + 1) & (kHash - 1);
-                    }
-                    if (hb >= 0) sh.hval[hb] = lane;
-                }
-                lds_sync();
-                int qn = 0;
-#pragma unroll
-                for (int j = 0; j < T; ++j) {
-                    int sl = -1;
-                    if (gcol && vid[j] >= 0) {
-                        int h = hash_face(vid[j]);
-                        for (int probe = 0; probe < kHash; ++probe) {
-                            const int k = sh.hkey[h];
-                            if (k == vid[j]) {
-                                sl = sh.hval[h];
-                                break;
-                            }
-                            if (k == -1) break;
-                            h = (h + 1) & (kHash - 1);
-                        }
-                    }
-                    const uint64_t bal = __ballot(sl >= 0);
-                    if (sl >= 0) sh.q[qn + lane_rank(bal)] = (uint32_t)sl | ((uint32_t)lane << 8) | ((uint32_t)j << 16);
-                    qn += __popcll(bal);
-                }
-                lds_sync();
-                for (int rb = 0; rb < qn; rb += kWave) {
-                    if (rb + lane < qn) {
-                        const uint32_t item = sh.q[rb + lane];
-                        const int jj = (int)(item >> 16);
-                        int X;
-                        const float tj = chunk_tau(a, ck, jj, X);
-                        fg_item_bwd<T, SOLVER>(a, sh, (int)(item & 0xffu), (int)((item >> 8) & 0xffu), tj, tc);
-                    }
-                }
-                lds_sync();
-                if (hb >= 0) sh.hkey[hb] = -1;
-                flush_slots<T>(sh, nb, ck.s, a, ga, true);
-            }
-        }
-
-        // ---- background
         uint64_t bgm[T];
         bool anybg = false;
+        lds_sync();
+        sh.gal[lane] = gal;
 #pragma unroll
         for (int j = 0; j < T; ++j) {
-            bgm[j] = __ballot(vid[j] <= -1 && vid[j] >= -3 && gal != 0.0f);
+            int vid = kVisOut;
+            float P = 0.0f;
+            int nz = 0;
+            if (j < ck.n) {
+                const int k = ck.k0 + j;
+                vid = a.vis_id[vis_index(a, g.tile, k, lane)];
+                if (vid == -1) {
+                    P = exp2f(a.pix[pix_index(a, g.tile, k, 0, lane)]);
+                    nz = __float_as_int(a.pix[pix_index(a, g.tile, k, 1, lane)]);
+                }
+            }
+            sh.P[j][lane] = P;
+            sh.nz[j][lane] = nz;
+            bgm[j] = __ballot(vid == -1 && gal != 0.0f);
             anybg = anybg || bgm[j] != 0ull;
         }
-        if (anybg) {
-            const int64_t idx = ((int64_t)a.NC + c) * a.ntiles + g.tile;
-            const int64_t beg = a.off[idx];
-            const int n_e = a.cnt[idx];
-            for (int base = 0; base < n_e; base += NB) {
-                const int nb = min(NB, n_e - base);
-                int cnt, pre;
-                const int total = stage_items<T>(a, sh.it, beg + base, nb, ck.s, g, tc, tau, kRecBg, a.halo, bgm,
-                                                 nullptr, sh.vid, cnt, pre);
-                for_items<T>(sh.it, total, cnt, pre,
-                             [&](int e, int p) { bg_item_bwd<T, SOLVER>(a, sh, e, p, tau, xbits, tc); });
-                flush_slots<T>(sh, nb, ck.s, a, ga, false);
-            }
+        if (!anybg) continue;
+        const int64_t idx = (int64_t)a.NC * a.ntiles + ct;
+        const int64_t beg = a.off[idx];
+        const int n_e = a.cnt[idx];
+        const int e0 = slice * a.SL, e1 = min(n_e, e0 + a.SL);
+        for (int base = e0; base < e1; base += NB) {
+            const int nb = min(NB, e1 - base);
+            int cnt, pre;
+            const int total =
+                stage_items<T>(a, sh.it, beg + base, nb, ck.s, g, tc, tau, kRecBg, a.halo, bgm, sh.vid, cnt, pre);
+            for_items<T>(sh.it, total, cnt, pre,
+                         [&](int e, int p) { bg_item_bwd<T, SOLVER>(a, sh, e, p, tau, xbits, tc); });
+            flush_slots(sh.gacc, sh.vid, nb, ck.s, a, ga, false);
         }
     }
 }
@@ -1479,9 +1629,11 @@ static RasterArgs raster_args(const Plan &p, const Inputs &in, const Bufs &b)
     a.off = b.off;
     a.list = b.list;
     a.vis_id = b.vis_id;
-    a.vis_p = b.vis_p;
-    a.part = b.part;
+    a.pix = b.pix;
+    a.tsl = b.tsl;
+    a.tasks = b.tasks;
     a.hdr = b.hdr;
+    a.maxtasks = p.maxtasks;
     a.V = p.V;
     a.F = p.F;
     a.C = p.C;
@@ -1493,13 +1645,14 @@ static RasterArgs raster_args(const Plan &p, const Inputs &in, const Bufs &b)
     a.ntiles = p.ntiles;
     a.CPS = p.CPS;
     a.NC = p.NC;
-    a.G = p.G;
-    a.NG = p.NG;
+    a.SL = p.SL;
+    a.NS = p.NS;
+    a.inv_w = (float)(1.0 / (double)p.W);
+    a.inv_h = (float)(1.0 / (double)p.H);
     a.dmax = p.dmax;
     a.halo = p.halo;
     a.neg_log2e_over_delta = (float)(-1.4426950408889634 / (double)p.delta);
     a.inv_delta = (float)(1.0 / (double)p.delta);
-    a.cap = p.cap;
     return a;
 }
 
@@ -1509,7 +1662,7 @@ static inline void mark(const PhaseEvents *pe, int i, hipStream_t st)
 }
 
 template <int T>
-static hipError_t fwd_T(const Plan &p, const Inputs &in, const Bufs &b, hipStream_t st, const PhaseEvents *pe)
+static void bin_T(const Plan &p, const Inputs &in, const Bufs &b, hipStream_t st)
 {
     BinArgs ba;
     ba.faces = in.faces;
@@ -1535,19 +1688,36 @@ static hipError_t fwd_T(const Plan &p, const Inputs &in, const Bufs &b, hipStrea
     hipLaunchKernelGGL(k_bin<T>, dim3(grid_for(nbin, 256)), dim3(256), 0, st, ba, 0);
     hipLaunchKernelGGL(k_scan1, dim3((unsigned)p.nblocks_scan), dim3(kScanThreads), 0, st, b.cnt, b.off, b.bsum,
                        p.ncounts);
-    hipLaunchKernelGGL(k_scan2, dim3(1), dim3(kScanThreads), 0, st, b.bsum, p.nblocks_scan, b.hdr, p.cap);
+    hipLaunchKernelGGL(k_scan2, dim3(1), dim3(kScanThreads), 0, st, b.bsum, p.nblocks_scan, &b.hdr->list_entries,
+                       &b.hdr->error_bits, p.cap);
     hipLaunchKernelGGL(k_scan3, dim3(grid_for(p.ncounts, 256)), dim3(256), 0, st, b.off, b.bsum, p.ncounts);
     hipLaunchKernelGGL(k_bin<T>, dim3(grid_for(nbin, 256)), dim3(256), 0, st, ba, 1);
+}
+
+template <int T, int SOLVER>
+static void raster_fwd_T(const Plan &p, const RasterArgs &ra, const Bufs &b, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_fg<T, SOLVER>), dim3((unsigned)p.ntct), dim3(kWave), 0, st, ra);
+    hipLaunchKernelGGL(k_scan1, dim3((unsigned)p.nblocks_tscan), dim3(kScanThreads), 0, st, b.tsl, b.toff, b.tbsum,
+                       p.ntct);
+    hipLaunchKernelGGL(k_scan2, dim3(1), dim3(kScanThreads), 0, st, b.tbsum, p.nblocks_tscan, &b.hdr->ntasks,
+                       (int32_t *)nullptr, (int64_t)0);
+    hipLaunchKernelGGL(k_scan3, dim3(grid_for(p.ntct, 256)), dim3(256), 0, st, b.toff, b.tbsum, p.ntct);
+    hipLaunchKernelGGL(k_tasks, dim3(grid_for(p.ntct, 256)), dim3(256), 0, st, b.tsl, b.toff, p.ntct, b.tasks,
+                       p.maxtasks);
+    hipLaunchKernelGGL((k_bg<T, SOLVER>), dim3((unsigned)p.persist), dim3(kWave), 0, st, ra);
+}
+
+template <int T>
+static void forward_T(const Plan &p, const Inputs &in, const Bufs &b, hipStream_t st, const PhaseEvents *pe)
+{
+    bin_T<T>(p, in, b, st);
     mark(pe, 2, st);
-    RasterArgs ra = raster_args(p, in, b);
-    const int64_t waves = (int64_t)p.ntiles * p.NG;
-    const unsigned blocks = grid_for(waves, 4);
+    const RasterArgs ra = raster_args(p, in, b);
     if (p.solver == RB_SOLVER_FAST)
-        hipLaunchKernelGGL((k_raster_fwd<T, RB_SOLVER_FAST>), dim3(blocks), dim3(256), 0, st, ra);
+        raster_fwd_T<T, RB_SOLVER_FAST>(p, ra, b, st);
     else
-        hipLaunchKernelGGL((k_raster_fwd<T, RB_SOLVER_RECOMPUTE>), dim3(blocks), dim3(256), 0, st, ra);
-    mark(pe, 3, st);
-    return hipGetLastError();
+        raster_fwd_T<T, RB_SOLVER_RECOMPUTE>(p, ra, b, st);
 }
 
 hipError_t launch_forward(const Plan &p, const Inputs &in, const Bufs &b, float *image, hipStream_t st,
@@ -1563,31 +1733,33 @@ hipError_t launch_forward(const Plan &p, const Inputs &in, const Bufs &b, float 
     hipLaunchKernelGGL(k_project, dim3(grid_for(nproj, 256)), dim3(256), 0, st, in.verts, in.model, in.faces, p.V,
                        p.S, p.F, vw, b.kf, b.kfz, b.hdr);
     mark(pe, 1, st);
-    hipError_t e;
     switch (p.T) {
-    case 1: e = fwd_T<1>(p, in, b, st, pe); break;
-    case 2: e = fwd_T<2>(p, in, b, st, pe); break;
-    case 4: e = fwd_T<4>(p, in, b, st, pe); break;
-    default: e = fwd_T<8>(p, in, b, st, pe); break;
+    case 1: forward_T<1>(p, in, b, st, pe); break;
+    case 2: forward_T<2>(p, in, b, st, pe); break;
+    case 4: forward_T<4>(p, in, b, st, pe); break;
+    default: forward_T<8>(p, in, b, st, pe); break;
     }
-    if (e != hipSuccess) return e;
-    const int64_t npix = (int64_t)(p.C + 1) * p.W * p.H;
-    hipLaunchKernelGGL(k_reduce_image, dim3(grid_for(npix, 256)), dim3(256), 0, st, b.part, image, p.C, p.W, p.H,
-                       p.tiles_x, p.ntiles, p.NG, 1.0f / (float)p.K, b.hdr);
+    mark(pe, 3, st);
+    hipLaunchKernelGGL(k_resolve, dim3((unsigned)p.ntiles), dim3(kWave), 0, st, raster_args(p, in, b), image);
     mark(pe, 4, st);
     return hipGetLastError();
 }
 
-template <int T>
-static void bwd_T(const Plan &p, const Inputs &in, const Bufs &b, const GradArgs &ga, hipStream_t st)
+template <int T, int SOLVER>
+static void raster_bwd_T(const Plan &p, const RasterArgs &ra, const GradArgs &ga, hipStream_t st)
 {
-    RasterArgs ra = raster_args(p, in, b);
-    const int64_t waves = (int64_t)p.ntiles * p.NG;
-    const unsigned blocks = grid_for(waves, 4);
+    hipLaunchKernelGGL((k_fg_bwd<T, SOLVER>), dim3((unsigned)p.ntct), dim3(kWave), 0, st, ra, ga);
+    hipLaunchKernelGGL((k_bg_bwd<T, SOLVER>), dim3((unsigned)p.persist), dim3(kWave), 0, st, ra, ga);
+}
+
+template <int T>
+static void backward_T(const Plan &p, const Inputs &in, const Bufs &b, const GradArgs &ga, hipStream_t st)
+{
+    const RasterArgs ra = raster_args(p, in, b);
     if (p.solver == RB_SOLVER_FAST)
-        hipLaunchKernelGGL((k_raster_bwd<T, RB_SOLVER_FAST>), dim3(blocks), dim3(256), 0, st, ra, ga);
+        raster_bwd_T<T, RB_SOLVER_FAST>(p, ra, ga, st);
     else
-        hipLaunchKernelGGL((k_raster_bwd<T, RB_SOLVER_RECOMPUTE>), dim3(blocks), dim3(256), 0, st, ra, ga);
+        raster_bwd_T<T, RB_SOLVER_RECOMPUTE>(p, ra, ga, st);
 }
 
 hipError_t launch_backward(const Plan &p, const Inputs &in, const Bufs &b, const float *grad_image, float *grad_verts,
@@ -1595,11 +1767,9 @@ hipError_t launch_backward(const Plan &p, const Inputs &in, const Bufs &b, const
 {
     mark(pe, 0, st);
     const int64_t ngkf = (int64_t)(p.S + 1) * p.V * 2;
-    hipLaunchKernelGGL(k_zero, dim3(grid_for(ngkf, 256) > 4096 ? 4096 : grid_for(ngkf, 256)), dim3(256), 0, st, b.gkf,
-                       ngkf);
     const int64_t nga = (int64_t)p.V * p.C;
-    hipLaunchKernelGGL(k_zero, dim3(grid_for(nga, 256) > 4096 ? 4096 : grid_for(nga, 256)), dim3(256), 0, st,
-                       grad_attrs, nga);
+    const unsigned gz = grid_for(ngkf + nga, 256);
+    hipLaunchKernelGGL(k_bwd_init, dim3(gz > 4096 ? 4096 : gz), dim3(256), 0, st, b.gkf, ngkf, grad_attrs, nga, b.hdr);
     GradArgs ga;
     ga.grad_image = grad_image;
     ga.gkf = b.gkf;
@@ -1607,10 +1777,10 @@ hipError_t launch_backward(const Plan &p, const Inputs &in, const Bufs &b, const
     ga.invK = 1.0f / (float)p.K;
     mark(pe, 1, st);
     switch (p.T) {
-    case 1: bwd_T<1>(p, in, b, ga, st); break;
-    case 2: bwd_T<2>(p, in, b, ga, st); break;
-    case 4: bwd_T<4>(p, in, b, ga, st); break;
-    default: bwd_T<8>(p, in, b, ga, st); break;
+    case 1: backward_T<1>(p, in, b, ga, st); break;
+    case 2: backward_T<2>(p, in, b, ga, st); break;
+    case 4: backward_T<4>(p, in, b, ga, st); break;
+    default: backward_T<8>(p, in, b, ga, st); break;
     }
     mark(pe, 2, st);
     ViewArgs vw;

@@ -24,7 +24,7 @@ class RenderOptions:
     eps_cutoff: float = 1e-8     # probabilities below this are dropped
     solver: str = "fast"         # "fast" (eq 8) or "recompute" (per sub-frame solve)
     chunk_len: int = 4           # sub-frames per work chunk (1, 2, 4, 8)
-    chunks_per_wave: int = 0     # 0: automatic
+    slice_len: int = 0           # background-list entries per task (0: automatic)
     check: bool = True           # read the device header after each forward (one sync)
 
     def c_struct(self, capacity: int) -> B.rb_options:
@@ -35,7 +35,7 @@ class RenderOptions:
         o.solver = {"fast": B.RB_SOLVER_FAST, "recompute": B.RB_SOLVER_RECOMPUTE}[self.solver]
         o.flags = 0
         o.chunk_len = int(self.chunk_len)
-        o.chunks_per_wave = int(self.chunks_per_wave)
+        o.slice_len = int(self.slice_len)
         o.list_capacity = int(capacity)
         return o
 
@@ -86,7 +86,7 @@ def render_forward(verts: torch.Tensor, faces: torch.Tensor, attrs: torch.Tensor
     S = model.shape[0] - 1
     motion = B.rb_motion(S, model.data_ptr())
     key = (V, F, C, S, opts.num_subframes, camera.width, camera.height, opts.chunk_len,
-           opts.chunks_per_wave, opts.solver)
+           opts.slice_len, opts.solver)
     cap = _capacity.get(key)
     known = cap is not None
     if cap is None:

@@ -69,7 +69,7 @@ def _args(V=100, F=50, C=3, S=2, K=16, W=64, H=48):
     mo = B.rb_motion(S, 0x1000)      # host-side checks only look at the pointer's presence
     op = B.rb_options()
     op.num_subframes, op.delta, op.eps_cutoff, op.solver = K, 1e-4, 1e-8, B.RB_SOLVER_FAST
-    op.chunk_len, op.chunks_per_wave, op.list_capacity = 4, 0, 1 << 16
+    op.chunk_len, op.slice_len, op.list_capacity = 4, 0, 1 << 16
     return V, F, C, mo, cam, op
 
 

@@ -27,14 +27,14 @@ def test_small_translation_parity(solver):
     assert_image_parity(img, ref.image, ref.flags, label=f"small/{solver}")
 
 
-@pytest.mark.parametrize("chunk_len,cpw", [(1, 1), (2, 3), (8, 1), (8, 2), (4, 5)])
-def test_chunking_does_not_change_the_image(chunk_len, cpw):
+@pytest.mark.parametrize("chunk_len,slice_len", [(1, 1), (2, 3), (8, 1), (8, 2), (4, 5), (4, 64)])
+def test_chunking_does_not_change_the_image(chunk_len, slice_len):
     sc = wl.make_workload(wl.SMALL, motion=wl.Motion("rotate", axis=(0.3, 1.0, -0.2), revs=1.0),
                           num_segments=12, num_subframes=37)
-    say(f"case: small rotate chunk_len={chunk_len} chunks_per_wave={cpw}")
+    say(f"case: small rotate chunk_len={chunk_len} slice_len={slice_len}")
     ref = oracle.render(sc, flags=True)
-    img, _, _ = gpu_forward(sc, chunk_len=chunk_len, chunks_per_wave=cpw)
-    assert_image_parity(img, ref.image, ref.flags, label=f"chunk{chunk_len}x{cpw}")
+    img, _, _ = gpu_forward(sc, chunk_len=chunk_len, slice_len=slice_len)
+    assert_image_parity(img, ref.image, ref.flags, label=f"chunk{chunk_len}x{slice_len}")
 
 
 @pytest.mark.parametrize("W,H,K,S", [(61, 37, 23, 5), (13, 70, 1, 1), (40, 40, 2, 1), (33, 31, 4, 7)])
