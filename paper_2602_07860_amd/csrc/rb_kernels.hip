@@ -194,14 +194,25 @@ __device__ __forceinline__ void face_tiles(const float x[3], const float y[3], c
     ty1 = r1 / kTile;
 }
 
+// Binning.  A block takes 256 consecutive faces of one chunk; meshes list
+// neighbouring faces close together, so the block's tiles form a small
+// window.  Per-tile counts are gathered with LDS atomics over that window and
+// reach global memory with one atomic per (window tile, list kind); in the
+// fill pass each window tile reserves one contiguous range of its list and
+// the block's entries go there at LDS-atomic ranks.  A block whose window
+// does not fit in LDS uses one global atomic per entry instead.
+constexpr int kBinThreads = 256;
+constexpr int kBinWin = 2048;   // window counters: 2 list kinds x tiles
+
+struct FaceTiles {
+    int ux0, ux1, uy0, uy1;                 // union of the background rects over the chunk
+};
+
 template <int T>
-__global__ __launch_bounds__(256) void k_bin(BinArgs a, int pass)
+__device__ __forceinline__ bool face_chunk_tiles(const BinArgs &a, int f, const Chunk &ch, int ftx0[T], int ftx1[T],
+                                                 int fty0[T], int fty1[T], int btx0[T], int btx1[T], int bty0[T],
+                                                 int bty1[T], FaceTiles &u)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)a.F * a.NC) return;
-    int c = (int)(i / a.F), f = (int)(i - (int64_t)c * a.F);
-    Chunk ch = chunk_info(c, a.K, a.S, a.CPS);
-    if (ch.n <= 0) return;
     float ax[3], ay[3], bx[3], by[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
@@ -213,8 +224,10 @@ __global__ __launch_bounds__(256) void k_bin(BinArgs a, int pass)
         bx[q] = (float)(r.x - p.x);
         by[q] = (float)(r.y - p.y);
     }
-    int ftx0[T], ftx1[T], fty0[T], fty1[T], btx0[T], btx1[T], bty0[T], bty1[T];
-    int ux0 = INT_MAX, ux1 = INT_MIN, uy0 = INT_MAX, uy1 = INT_MIN;
+    u.ux0 = INT_MAX;
+    u.ux1 = INT_MIN;
+    u.uy0 = INT_MAX;
+    u.uy1 = INT_MIN;
 #pragma unroll
     for (int j = 0; j < T; ++j) {
         ftx0[j] = fty0[j] = btx0[j] = bty0[j] = 1;
@@ -231,38 +244,115 @@ __global__ __launch_bounds__(256) void k_bin(BinArgs a, int pass)
             face_tiles(x, y, a, 0.0f, ftx0[j], ftx1[j], fty0[j], fty1[j]);
             face_tiles(x, y, a, a.halo, btx0[j], btx1[j], bty0[j], bty1[j]);
             if (btx0[j] <= btx1[j]) {
-                ux0 = min(ux0, btx0[j]);
-                ux1 = max(ux1, btx1[j]);
-                uy0 = min(uy0, bty0[j]);
-                uy1 = max(uy1, bty1[j]);
+                u.ux0 = min(u.ux0, btx0[j]);
+                u.ux1 = max(u.ux1, btx1[j]);
+                u.uy0 = min(u.uy0, bty0[j]);
+                u.uy1 = max(u.uy1, bty1[j]);
             }
         }
     }
-    if (ux0 > ux1) return;
-    for (int ty = uy0; ty <= uy1; ++ty) {
-        for (int tx = ux0; tx <= ux1; ++tx) {
-            uint32_t fm = 0, bm = 0;
+    return u.ux0 <= u.ux1;
+}
+
+template <int T>
+__global__ __launch_bounds__(kBinThreads) void k_bin(BinArgs a, int pass)
+{
+    __shared__ int lcnt[kBinWin];
+    __shared__ int64_t lbase[kBinWin];
+    __shared__ int win[4];
+    const int nfb = (a.F + kBinThreads - 1) / kBinThreads;
+    const int c = blockIdx.x / nfb;
+    const int f = (blockIdx.x - c * nfb) * kBinThreads + threadIdx.x;
+    const Chunk ch = chunk_info(c, a.K, a.S, a.CPS);
+    if (ch.n <= 0) return;   // block-uniform
+    int ftx0[T], ftx1[T], fty0[T], fty1[T], btx0[T], btx1[T], bty0[T], bty1[T];
+    FaceTiles u;
+    const bool has = f < a.F && face_chunk_tiles<T>(a, f, ch, ftx0, ftx1, fty0, fty1, btx0, btx1, bty0, bty1, u);
+    if (threadIdx.x == 0) {
+        win[0] = INT_MAX;
+        win[1] = INT_MIN;
+        win[2] = INT_MAX;
+        win[3] = INT_MIN;
+    }
+    __syncthreads();
+    if (has) {
+        atomicMin(&win[0], u.ux0);
+        atomicMax(&win[1], u.ux1);
+        atomicMin(&win[2], u.uy0);
+        atomicMax(&win[3], u.uy1);
+    }
+    __syncthreads();
+    const int wx0 = win[0], wy0 = win[2];
+    const int ww = win[1] - wx0 + 1, wh = win[3] - wy0 + 1;
+    if (win[0] > win[1]) return;   // no face of the block touches the image (block-uniform)
+    const int nwt = ww * wh;
+    const bool lds = 2 * (int64_t)nwt <= kBinWin;
+    if (lds) {
+        for (int i = threadIdx.x; i < 2 * nwt; i += kBinThreads) lcnt[i] = 0;
+        __syncthreads();
+    }
+    // visit the entries of this thread's face: fn(list kind, tile, mask, window slot)
+    auto visit = [&](auto &&fn) {
+        if (!has) return;
+        for (int ty = u.uy0; ty <= u.uy1; ++ty) {
+            for (int tx = u.ux0; tx <= u.ux1; ++tx) {
+                uint32_t fm = 0, bm = 0;
 #pragma unroll
-            for (int j = 0; j < T; ++j) {
-                if (tx >= ftx0[j] && tx <= ftx1[j] && ty >= fty0[j] && ty <= fty1[j]) fm |= 1u << j;
-                if (tx >= btx0[j] && tx <= btx1[j] && ty >= bty0[j] && ty <= bty1[j]) bm |= 1u << j;
-            }
-            int tile = ty * a.tiles_x + tx;
-#pragma unroll
-            for (int L = 0; L < 2; ++L) {
-                uint32_t m = L == 0 ? fm : bm;
-                if (!m) continue;
-                int64_t idx = ((int64_t)L * a.NC + c) * a.ntiles + tile;
-                if (pass == 0) {
-                    atomicAdd(&a.cnt[idx], 1);
-                } else {
-                    int64_t pos = a.off[idx] + atomicAdd(&a.cur[idx], 1);
-                    if (pos < a.cap) a.list[pos] = ((uint32_t)f << 8) | m;
+                for (int j = 0; j < T; ++j) {
+                    if (tx >= ftx0[j] && tx <= ftx1[j] && ty >= fty0[j] && ty <= fty1[j]) fm |= 1u << j;
+                    if (tx >= btx0[j] && tx <= btx1[j] && ty >= bty0[j] && ty <= bty1[j]) bm |= 1u << j;
                 }
+                const int tile = ty * a.tiles_x + tx;
+                const int w = (ty - wy0) * ww + (tx - wx0);
+                if (fm) fn(0, tile, fm, w);
+                if (bm) fn(1, tile, bm, nwt + w);
             }
+        }
+    };
+    auto gidx = [&](int L, int tile) { return ((int64_t)L * a.NC + c) * a.ntiles + tile; };
+    if (pass == 0) {
+        if (lds) {
+            visit([&](int, int, uint32_t, int w) { atomicAdd(&lcnt[w], 1); });
+            __syncthreads();
+            for (int i = threadIdx.x; i < 2 * nwt; i += kBinThreads) {
+                const int n = lcnt[i];
+                if (!n) continue;
+                const int L = i >= nwt, w = i - L * nwt;
+                const int tile = (wy0 + w / ww) * a.tiles_x + wx0 + w % ww;
+                atomicAdd(&a.cnt[gidx(L, tile)], n);
+            }
+        } else {
+            visit([&](int L, int tile, uint32_t, int) { atomicAdd(&a.cnt[gidx(L, tile)], 1); });
+        }
+    } else {
+        const uint32_t fbits = (uint32_t)f << 8;
+        if (lds) {
+            visit([&](int, int, uint32_t, int w) { atomicAdd(&lcnt[w], 1); });
+            __syncthreads();
+            for (int i = threadIdx.x; i < 2 * nwt; i += kBinThreads) {
+                const int n = lcnt[i];
+                if (!n) continue;
+                const int L = i >= nwt, w = i - L * nwt;
+                const int tile = (wy0 + w / ww) * a.tiles_x + wx0 + w % ww;
+                const int64_t g = gidx(L, tile);
+                lbase[i] = a.off[g] + atomicAdd(&a.cur[g], n);
+                lcnt[i] = 0;
+            }
+            __syncthreads();
+            visit([&](int, int, uint32_t m, int w) {
+                const int64_t pos = lbase[w] + atomicAdd(&lcnt[w], 1);
+                if (pos < a.cap) a.list[pos] = fbits | m;
+            });
+        } else {
+            visit([&](int L, int tile, uint32_t m, int) {
+                const int64_t g = gidx(L, tile);
+                const int64_t pos = a.off[g] + atomicAdd(&a.cur[g], 1);
+                if (pos < a.cap) a.list[pos] = fbits | m;
+            });
         }
     }
 }
+
 // ------------------------------------------------------------------- scan
 // exclusive prefix sum of n int32 counts into int64 offsets, 3 phases
 
@@ -1684,14 +1774,14 @@ static void bin_T(const Plan &p, const Inputs &in, const Bufs &b, hipStream_t st
     ba.NC = p.NC;
     ba.halo = p.halo;
     ba.cap = p.cap;
-    const int64_t nbin = (int64_t)p.F * p.NC;
-    hipLaunchKernelGGL(k_bin<T>, dim3(grid_for(nbin, 256)), dim3(256), 0, st, ba, 0);
+    const unsigned nbin = (unsigned)((int64_t)p.NC * grid_for(p.F, kBinThreads));
+    hipLaunchKernelGGL(k_bin<T>, dim3(nbin), dim3(kBinThreads), 0, st, ba, 0);
     hipLaunchKernelGGL(k_scan1, dim3((unsigned)p.nblocks_scan), dim3(kScanThreads), 0, st, b.cnt, b.off, b.bsum,
                        p.ncounts);
     hipLaunchKernelGGL(k_scan2, dim3(1), dim3(kScanThreads), 0, st, b.bsum, p.nblocks_scan, &b.hdr->list_entries,
                        &b.hdr->error_bits, p.cap);
     hipLaunchKernelGGL(k_scan3, dim3(grid_for(p.ncounts, 256)), dim3(256), 0, st, b.off, b.bsum, p.ncounts);
-    hipLaunchKernelGGL(k_bin<T>, dim3(grid_for(nbin, 256)), dim3(256), 0, st, ba, 1);
+    hipLaunchKernelGGL(k_bin<T>, dim3(nbin), dim3(kBinThreads), 0, st, ba, 1);
 }
 
 template <int T, int SOLVER>
