@@ -496,7 +496,6 @@ struct RasterArgs {
 
 constexpr int NCH = RB_MAX_CHANNELS;
 constexpr int NB = 32;              // list entries staged per batch
-constexpr int NGA = 12 + 3 * NCH;   // per-entry gradient slot: 3 vertices x 2 keyframes x (x, y), attributes
 constexpr int kHash = 128;          // face -> staged entry table (NB keys at most)
 constexpr int kVisOut = -4;         // vis_id of a pixel outside the image
 
@@ -1294,37 +1293,99 @@ struct GradArgs {
 
 __device__ __forceinline__ int hash_face(int f) { return (int)(((uint32_t)f * 2654435761u) >> 25); }
 
-// Add a lane's per-entry contribution to the entry's LDS slot.
-__device__ __forceinline__ void slot_add(float (*gacc)[NB], int e, int i, float v)
-{
-    if (v != 0.0f) atomicAdd(&gacc[i][e], v);
-}
+// Gradient accumulation.  Item contributions go to an LDS table keyed by
+// vertex (open addressing): per vertex, dL/d(x, y) at the chunk's two
+// keyframes and, in the foreground, dL/d(attributes).  Neighbouring faces
+// share vertices, so the table reaches global memory with one atomic per
+// (vertex, value) when it fills up or the task ends, instead of one per
+// (face, vertex, value).
+constexpr int kVT = 256;       // table slots
+constexpr int kVTLoad = 192;   // flush before a batch could push the table past this
 
-// Flush the staged entries' gradient slots to global memory and clear them.
-__device__ __forceinline__ void flush_slots(float (*gacc)[NB], const int (*vids)[3], int nb, int s,
-                                            const RasterArgs &a, const GradArgs &ga, bool with_attr)
+template <int NV>
+struct VTab {
+    int key[kVT];              // vertex index, -1 = empty
+    float g[NV][kVT];          // 0-3: keyframe s (x, y), keyframe s + 1 (x, y); 4+: attributes
+};
+
+template <int NV>
+__device__ __forceinline__ void vt_clear(VTab<NV> &vt)
 {
     const int lane = threadIdx.x & 63;
+    for (int i = lane; i < kVT; i += kWave) {
+        vt.key[i] = -1;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) vt.g[k][i] = 0.0f;
+    }
+}
+
+__device__ __forceinline__ int hash_vertex(int v) { return (int)(((uint32_t)v * 2654435761u) >> 24); }
+
+__device__ __forceinline__ int wave_sum_int(int x)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+    return x;
+}
+
+// Replace the staged entries' vertex indices vs[e][q] (e < nb) by their table
+// slots, inserting new vertices; returns the number of new keys.  The caller
+// keeps the table below kVTLoad of kVT slots, so a free slot is always found.
+template <int NV>
+__device__ __forceinline__ int vt_bind(VTab<NV> &vt, int (*vs)[3], int nb)
+{
+    const int lane = threadIdx.x & 63;
+    int fresh = 0;
     lds_sync();
     if (lane < nb) {
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            const int v = vids[lane][q];
-#pragma unroll
-            for (int sl = 0; sl < 2; ++sl) {
-                float *p = ga.gkf + ((size_t)(s + sl) * a.V + v) * 2;
-                const float gx = gacc[q * 4 + sl * 2][lane], gy = gacc[q * 4 + sl * 2 + 1][lane];
-                if (gx != 0.0f) unsafeAtomicAdd(p, gx);
-                if (gy != 0.0f) unsafeAtomicAdd(p + 1, gy);
-            }
-            if (with_attr)
-                for (int c = 0; c < a.C; ++c) {
-                    const float gv = gacc[12 + q * NCH + c][lane];
-                    if (gv != 0.0f) unsafeAtomicAdd(ga.gattr + (size_t)v * a.C + c, gv);
+            const int v = vs[lane][q];
+            int h = hash_vertex(v), slot = -1;
+            for (int probe = 0; probe < kVT; ++probe) {
+                const int old = atomicCAS(&vt.key[h], -1, v);
+                if (old == -1 || old == v) {
+                    slot = h;
+                    fresh += old == -1 ? 1 : 0;
+                    break;
                 }
+                h = (h + 1) & (kVT - 1);
+            }
+            vs[lane][q] = slot;
+        }
+    }
+    lds_sync();
+    return wave_sum_int(fresh);
+}
+
+template <int NV>
+__device__ __forceinline__ void vt_add(VTab<NV> &vt, int slot, int k, float v)
+{
+    if (v != 0.0f && slot >= 0) atomicAdd(&vt.g[k][slot], v);
+}
+
+// Add the table to the keyframe (and attribute) gradients and clear it.
+template <int NV>
+__device__ __forceinline__ void vt_flush(VTab<NV> &vt, int s, const RasterArgs &a, const GradArgs &ga)
+{
+    const int lane = threadIdx.x & 63;
+    lds_sync();
+    for (int i = lane; i < kVT; i += kWave) {
+        const int v = vt.key[i];
+        if (v < 0) continue;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float g = vt.g[k][i];
+            if (g != 0.0f) unsafeAtomicAdd(ga.gkf + ((size_t)(s + (k >> 1)) * a.V + v) * 2 + (k & 1), g);
+            vt.g[k][i] = 0.0f;
         }
 #pragma unroll
-        for (int i = 0; i < NGA; ++i) gacc[i][lane] = 0.0f;
+        for (int c = 0; c < NV - 4; ++c) {
+            const float g = vt.g[4 + c][i];
+            if (g != 0.0f && c < a.C) unsafeAtomicAdd(ga.gattr + (size_t)v * a.C + c, g);
+            vt.g[4 + c][i] = 0.0f;
+        }
+        vt.key[i] = -1;
     }
     lds_sync();
 }
@@ -1335,8 +1396,8 @@ template <int T>
 struct FgBwdShared {
     ItemShared<T> it;
     float at[3 * NCH][NB];    // staged entries' vertex attributes
-    int vid[NB][3];           // staged entries' vertex indices
-    float gacc[NGA][NB];      // per-entry gradient slots
+    int vslot[NB][3];         // staged entries' vertices: index, then vertex-table slot
+    VTab<4 + NCH> vt;
     float gI[NCH][kWave];     // dL/dcolour of each pixel, already divided by K
     int hkey[kHash];          // face -> staged entry (open addressing, -1 = empty)
     int hval[kHash];
@@ -1379,12 +1440,13 @@ __device__ __forceinline__ void fg_item_bwd(const RasterArgs &a, FgBwdShared<T> 
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
         const float gx = -w[q] * gxs, gy = -w[q] * gys;
-        slot_add(sh.gacc, e, q * 4 + 0, t0 * gx);
-        slot_add(sh.gacc, e, q * 4 + 1, t0 * gy);
-        slot_add(sh.gacc, e, q * 4 + 2, t1 * gx);
-        slot_add(sh.gacc, e, q * 4 + 3, t1 * gy);
+        const int slot = sh.vslot[e][q];
+        vt_add(sh.vt, slot, 0, t0 * gx);
+        vt_add(sh.vt, slot, 1, t0 * gy);
+        vt_add(sh.vt, slot, 2, t1 * gx);
+        vt_add(sh.vt, slot, 3, t1 * gy);
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) slot_add(sh.gacc, e, 12 + q * NCH + ch, w[q] * gI[ch]);
+        for (int ch = 0; ch < NCH; ++ch) vt_add(sh.vt, slot, 4 + ch, w[q] * gI[ch]);
     }
 }
 
@@ -1415,8 +1477,8 @@ __global__ __launch_bounds__(64) void k_fg_bwd(RasterArgs a, GradArgs ga)
         anyfg = anyfg || __ballot(gcol && vid[j] >= 0) != 0ull;
     }
     if (!anyfg) return;
-    if (lane < NB)
-        for (int i = 0; i < NGA; ++i) sh.gacc[i][lane] = 0.0f;
+    vt_clear(sh.vt);
+    int used = 0;
     sh.hkey[lane] = -1;
     sh.hkey[lane + kWave] = -1;
     float tau[T];
@@ -1428,6 +1490,10 @@ __global__ __launch_bounds__(64) void k_fg_bwd(RasterArgs a, GradArgs ga)
     const int n_e = a.cnt[ct];
     for (int base = 0; base < n_e; base += NB) {
         const int nb = min(NB, n_e - base);
+        if (used + 3 * nb > kVTLoad) {
+            vt_flush(sh.vt, ck.s, a, ga);
+            used = 0;
+        }
         lds_sync();
         int hb = -1;
         if (lane < nb) {
@@ -1439,7 +1505,7 @@ __global__ __launch_bounds__(64) void k_fg_bwd(RasterArgs a, GradArgs ga)
             store_rec(sh.it, lane, r);
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
-                sh.vid[lane][q] = vq[q];
+                sh.vslot[lane][q] = vq[q];
 #pragma unroll
                 for (int ch = 0; ch < NCH; ++ch)
                     sh.at[q * NCH + ch][lane] = ch < a.C ? a.attrs[(size_t)vq[q] * a.C + ch] : 0.0f;
@@ -1456,7 +1522,7 @@ __global__ __launch_bounds__(64) void k_fg_bwd(RasterArgs a, GradArgs ga)
             }
             if (hb >= 0) sh.hval[hb] = lane;
         }
-        lds_sync();
+        used += vt_bind(sh.vt, sh.vslot, nb);
         int qn = 0;
 #pragma unroll
         for (int j = 0; j < T; ++j) {
@@ -1488,8 +1554,8 @@ __global__ __launch_bounds__(64) void k_fg_bwd(RasterArgs a, GradArgs ga)
         }
         lds_sync();
         if (hb >= 0) sh.hkey[hb] = -1;
-        flush_slots(sh.gacc, sh.vid, nb, ck.s, a, ga, true);
     }
+    vt_flush(sh.vt, ck.s, a, ga);
 }
 
 // ------------------------------------------------------- backward: k_bg_bwd
@@ -1497,8 +1563,8 @@ __global__ __launch_bounds__(64) void k_fg_bwd(RasterArgs a, GradArgs ga)
 template <int T>
 struct BgBwdShared {
     ItemShared<T> it;
-    int vid[NB][3];
-    float gacc[NGA][NB];
+    int vslot[NB][3];         // staged entries' vertices: index, then vertex-table slot
+    VTab<4> vt;
     float P[T][kWave];        // forward product over non-zero factors
     int nz[T][kWave];
     float gal[kWave];         // dL/dalpha of each pixel, already divided by K
@@ -1604,7 +1670,11 @@ __device__ __forceinline__ void bg_item_bwd(const RasterArgs &a, BgBwdShared<T> 
         }
     }
 #pragma unroll
-    for (int q = 0; q < 12; ++q) slot_add(sh.gacc, e, q, gK[q]);
+    for (int q = 0; q < 3; ++q) {
+        const int slot = sh.vslot[e][q];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) vt_add(sh.vt, slot, k, gK[q * 4 + k]);
+    }
 }
 
 template <int T, int SOLVER>
@@ -1613,8 +1683,7 @@ __global__ __launch_bounds__(64) void k_bg_bwd(RasterArgs a, GradArgs ga)
     __shared__ BgBwdShared<T> sh;
     const int lane = threadIdx.x & 63;
     if (a.hdr->error_bits & kHdrOverflow) return;
-    if (lane < NB)
-        for (int i = 0; i < NGA; ++i) sh.gacc[i][lane] = 0.0f;
+    vt_clear(sh.vt);
     const int64_t ntasks = a.hdr->ntasks;
     for (;;) {
         const int64_t t = next_task(&a.hdr->task_ctr[1]);
@@ -1657,15 +1726,21 @@ __global__ __launch_bounds__(64) void k_bg_bwd(RasterArgs a, GradArgs ga)
         const int64_t beg = a.off[idx];
         const int n_e = a.cnt[idx];
         const int e0 = slice * a.SL, e1 = min(n_e, e0 + a.SL);
+        int used = 0;
         for (int base = e0; base < e1; base += NB) {
             const int nb = min(NB, e1 - base);
+            if (used + 3 * nb > kVTLoad) {
+                vt_flush(sh.vt, ck.s, a, ga);
+                used = 0;
+            }
             int cnt, pre;
             const int total =
-                stage_items<T>(a, sh.it, beg + base, nb, ck.s, g, tc, tau, kRecBg, a.halo, bgm, sh.vid, cnt, pre);
+                stage_items<T>(a, sh.it, beg + base, nb, ck.s, g, tc, tau, kRecBg, a.halo, bgm, sh.vslot, cnt, pre);
+            used += vt_bind(sh.vt, sh.vslot, nb);
             for_items<T>(sh.it, total, cnt, pre,
                          [&](int e, int p) { bg_item_bwd<T, SOLVER>(a, sh, e, p, tau, xbits, tc); });
-            flush_slots(sh.gacc, sh.vid, nb, ck.s, a, ga, false);
         }
+        if (used > 0) vt_flush(sh.vt, ck.s, a, ga);
     }
 }
 
