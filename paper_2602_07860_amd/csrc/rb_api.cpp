@@ -61,6 +61,8 @@ static rb_status make_plan(int32_t V, int32_t F, int32_t C, const rb_motion *mot
     }
     p.CPS = std::max(1, (nmax + T - 1) / T);
     p.NC = S * p.CPS;
+    // 32-bit chunk and (chunk, tile) index arithmetic on the device
+    if ((long long)p.CPS * K >= (1LL << 31) || (long long)p.NC * p.ntiles >= (1LL << 31)) return RB_EUNSUPPORTED;
     // background list entries per task: small enough that the longest lists
     // (silhouette tiles) spread over many waves, large enough to amortize a
     // task's set-up
@@ -74,7 +76,6 @@ static rb_status make_plan(int32_t V, int32_t F, int32_t C, const rb_motion *mot
     p.nblocks_tscan = std::max<int64_t>(1, (p.ntct + 4095) / 4096);
     // every (chunk, tile) contributes at most ceil(n_bg / SL) <= n_bg / SL + 1 tasks
     p.maxtasks = p.ntct + p.cap / p.SL + 1;
-    p.persist = 256 * 12;
 
     size_t o = 0;
     p.o_hdr = o;

@@ -39,8 +39,9 @@ __host__ __device__ inline Chunk chunk_info(int c, int K, int S, int CPS)
     int n = khi - klo;
     Chunk ch;
     ch.s = s;
-    ch.k0 = klo + (int)(((long long)j * n) / CPS);
-    ch.n = klo + (int)(((long long)(j + 1) * n) / CPS) - ch.k0;
+    // j * n <= CPS * K < 2^31 (checked when the plan is made)
+    ch.k0 = klo + (j * n) / CPS;
+    ch.n = klo + ((j + 1) * n) / CPS - ch.k0;
     return ch;
 }
 
@@ -72,7 +73,6 @@ struct Plan {
     int64_t cap;    // list capacity (entries)
     int64_t ntct;   // (chunk, tile) pairs = NC * ntiles
     int64_t maxtasks;
-    int persist;    // waves of the persistent background kernels
     // workspace byte offsets
     size_t o_hdr, o_kf, o_kfz, o_cnt, o_off, o_cur, o_bsum, o_list, o_vis_id, o_pix, o_tsl, o_toff, o_tbsum,
         o_tasks, o_gkf, total;

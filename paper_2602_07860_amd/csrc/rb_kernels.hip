@@ -540,15 +540,21 @@ __device__ __forceinline__ void lds_sync()
     __asm__ volatile("" ::: "memory");
 }
 
-__device__ __forceinline__ void stage_rec(const RasterArgs &a, int f, int s, double ua, double va, float tc, int kind,
-                                          FaceRec &r, int vid[3])
+// vertex indices of face f (clamped; out-of-range indices are reported by k_project)
+__device__ __forceinline__ void face_verts(const RasterArgs &a, int f, int vid[3])
+{
+#pragma unroll
+    for (int q = 0; q < 3; ++q) vid[q] = clampi(a.faces[3 * f + q], 0, a.V - 1);
+}
+
+__device__ __forceinline__ void stage_rec(const RasterArgs &a, int f, const int vid[3], int s, double ua, double va,
+                                          float tc, int kind, FaceRec &r)
 {
     r.f = f;
     double X0[3], Y0[3], X1[3], Y1[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-        const int v = clampi(a.faces[3 * f + q], 0, a.V - 1);
-        vid[q] = v;
+        const int v = vid[q];
         const double2 p = a.kf[(size_t)s * a.V + v];
         const double2 e = a.kf[(size_t)(s + 1) * a.V + v];
         X0[q] = p.x;
@@ -768,11 +774,11 @@ struct TileCtx {
     Chunk ck;
 };
 
-__device__ __forceinline__ void tile_ctx(const RasterArgs &a, int64_t ct, TileCtx &g)
+__device__ __forceinline__ void tile_ctx(const RasterArgs &a, int ct, TileCtx &g)
 {
     const int lane = threadIdx.x & 63;
-    g.c = (int)(ct / a.ntiles);
-    g.tile = (int)(ct - (int64_t)g.c * a.ntiles);
+    g.c = ct / a.ntiles;
+    g.tile = ct - g.c * a.ntiles;
     const int tx = g.tile % a.tiles_x, ty = g.tile / a.tiles_x;
     g.px = tx * kTile + (lane & 7);
     g.py = ty * kTile + (lane >> 3);
@@ -924,23 +930,45 @@ __device__ __forceinline__ void store_rec(ItemShared<T> &sh, int e, const FaceRe
     sh.rec[R_F][e] = __int_as_float(r.f);
 }
 
-// Stage entries [first, first + nb) of a list (one per lane) with their
-// per-sub-frame pixel masks; allow[j] is the set of pixels in question at
-// sub-frame j (0 for sub-frames outside the chunk).  Returns the number of
-// items; cnt / pre are the lane's entry's item count and first item.
+// A batch's list entries and their faces' vertex indices, loaded one batch
+// ahead so that staging waits for one level of gathers instead of three.
+struct Pref {
+    uint32_t ent;
+    int v[3];
+};
+
+__device__ __forceinline__ Pref prefetch(const RasterArgs &a, int64_t first, int nb)
+{
+    const int lane = threadIdx.x & 63;
+    Pref pf;
+    pf.ent = 0;
+    pf.v[0] = pf.v[1] = pf.v[2] = 0;
+    if (lane < nb) {
+        pf.ent = a.list[first + lane];
+        face_verts(a, (int)(pf.ent >> 8), pf.v);
+    }
+    return pf;
+}
+
+// Stage a batch of nb list entries (one per lane) with their per-sub-frame
+// pixel masks; allow[j] is the set of pixels in question at sub-frame j (0 for
+// sub-frames outside the chunk).  Returns the number of items; cnt / pre are
+// the lane's entry's item count and first item.  Optionally also stages the
+// vertex attributes (at) and vertex indices (vids).
 template <int T>
-__device__ __forceinline__ int stage_items(const RasterArgs &a, ItemShared<T> &sh, int64_t first, int nb, int s,
+__device__ __forceinline__ int stage_items(const RasterArgs &a, ItemShared<T> &sh, const Pref &pf, int nb, int s,
                                            const TileCtx &g, float tc, const float tau[T], int kind, float grow,
-                                           const uint64_t allow[T], int (*vids)[3], int &cnt, int &pre)
+                                           const uint64_t allow[T], float (*at)[NB], int (*vids)[3], int &cnt,
+                                           int &pre)
 {
     const int lane = threadIdx.x & 63;
     lds_sync();
     cnt = 0;
     if (lane < nb) {
-        const uint32_t ent = a.list[first + lane];
+        const uint32_t ent = pf.ent;
+        const int *vid = pf.v;
         FaceRec r;
-        int vid[3];
-        stage_rec(a, (int)(ent >> 8), s, g.ua, g.va, tc, kind, r, vid);
+        stage_rec(a, (int)(ent >> 8), vid, s, g.ua, g.va, tc, kind, r);
         uint64_t U = 0;
 #pragma unroll
         for (int j = 0; j < T; ++j) {
@@ -964,6 +992,12 @@ __device__ __forceinline__ int stage_items(const RasterArgs &a, ItemShared<T> &s
         }
         store_rec(sh, lane, r);
         sh.U[lane] = U;
+        if (at) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) at[q * NCH + c][lane] = c < a.C ? a.attrs[(size_t)vid[q] * a.C + c] : 0.0f;
+        }
         if (vids) {
 #pragma unroll
             for (int q = 0; q < 3; ++q) vids[lane][q] = vid[q];
@@ -1004,7 +1038,8 @@ __device__ __forceinline__ void for_items(ItemShared<T> &sh, int total, int cnt,
     }
 }
 
-// next task of a persistent kernel (wave-uniform); tasks >= n end the loop
+
+// next task of a persistent kernel (wave-uniform)
 __device__ __forceinline__ int64_t next_task(unsigned long long *ctr)
 {
     unsigned long long t = 0;
@@ -1052,14 +1087,10 @@ __device__ __forceinline__ void fg_item(const RasterArgs &a, FgShared<T> &sh, in
 
 // colour of the winning face at this lane's pixel: barycentric interpolation
 // of the vertex attributes (eq 9), from the same float32 record the depth
-// test used
-template <int SOLVER>
-__device__ __forceinline__ void shade_winner(const RasterArgs &a, int f, int s, const TileCtx &g, float tc, float tau,
-                                             float rgb[NCH])
+// test used (r) and the attributes at[q * NCH + c]
+template <int SOLVER, class R, class A>
+__device__ __forceinline__ void shade(const R &r, const A &at, float tc, float tau, const TileCtx &g, float rgb[NCH])
 {
-    FaceRec r;
-    int vid[3];
-    stage_rec(a, f, s, g.ua, g.va, tc, kRecGeom, r, vid);
     Bary<SOLVER> bc;
     bc.setup(r, tc, g.du, g.dv);
     float N[3];
@@ -1067,19 +1098,27 @@ __device__ __forceinline__ void shade_winner(const RasterArgs &a, int f, int s, 
     const float invD = rcp(N[0] + N[1] + N[2]);
     const float w0 = N[0] * invD, w1 = N[1] * invD, w2 = N[2] * invD;
 #pragma unroll
-    for (int ch = 0; ch < NCH; ++ch) {
-        float at[3];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) at[q] = ch < a.C ? a.attrs[(size_t)vid[q] * a.C + ch] : 0.0f;
-        rgb[ch] = fmaf(w0, at[0], fmaf(w1, at[1], w2 * at[2]));
-    }
+    for (int ch = 0; ch < NCH; ++ch) rgb[ch] = fmaf(w0, at(0 * NCH + ch), fmaf(w1, at(1 * NCH + ch), w2 * at(2 * NCH + ch)));
+}
+
+// the winner's record is no longer staged: gather it
+template <int SOLVER>
+__device__ __forceinline__ void shade_gather(const RasterArgs &a, int f, int s, const TileCtx &g, float tc, float tau,
+                                             float rgb[NCH])
+{
+    int vid[3];
+    face_verts(a, f, vid);
+    FaceRec r;
+    stage_rec(a, f, vid, s, g.ua, g.va, tc, kRecGeom, r);
+    shade<SOLVER>(r, [&](int k) { const int q = k / NCH, c = k - q * NCH; return c < a.C ? a.attrs[(size_t)vid[q] * a.C + c] : 0.0f; },
+                  tc, tau, g, rgb);
 }
 
 template <int T, int SOLVER>
 __global__ __launch_bounds__(64) void k_fg(RasterArgs a)
 {
     __shared__ FgShared<T> sh;
-    const int64_t ct = xcd_remap(blockIdx.x, gridDim.x);
+    const int ct = xcd_remap(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x & 63;
     TileCtx g;
     tile_ctx(a, ct, g);
@@ -1103,17 +1142,15 @@ __global__ __launch_bounds__(64) void k_fg(RasterArgs a)
         allow[j] = j < ck.n ? inimg : 0ull;
         sh.zb[j][lane] = ~0ull;
     }
-    {
-        const int64_t idx = ct;   // foreground list of (chunk, tile)
-        const int64_t beg = a.off[idx];
-        const int n_e = a.cnt[idx];
-        for (int base = 0; base < n_e; base += NB) {
-            const int nb = min(NB, n_e - base);
-            int cnt, pre;
-            const int total =
-                stage_items<T>(a, sh.it, beg + base, nb, ck.s, g, tc, tau, kRecFg, 0.0f, allow, nullptr, cnt, pre);
-            for_items<T>(sh.it, total, cnt, pre, [&](int e, int p) { fg_item<T, SOLVER>(a, sh, e, p, tau, tc); });
-        }
+    // foreground list of (chunk, tile)
+    const int64_t beg = a.off[ct];
+    const int n_e = a.cnt[ct];
+    for (int base = 0; base < n_e; base += NB) {
+        const int nb = min(NB, n_e - base);
+        int cnt, pre;
+        const int total = stage_items<T>(a, sh.it, prefetch(a, beg + base, nb), nb, ck.s, g, tc, tau, kRecFg, 0.0f,
+                                         allow, nullptr, nullptr, cnt, pre);
+        for_items<T>(sh.it, total, cnt, pre, [&](int e, int p) { fg_item<T, SOLVER>(a, sh, e, p, tau, tc); });
     }
     lds_sync();
     bool anyunc = false;
@@ -1127,7 +1164,7 @@ __global__ __launch_bounds__(64) void k_fg(RasterArgs a)
         float rgb[NCH];
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) rgb[ch] = 0.0f;
-        if (g.inimg && zid >= 0) shade_winner<SOLVER>(a, zid, ck.s, g, tc, tau[j], rgb);
+        if (g.inimg && zid >= 0) shade_gather<SOLVER>(a, zid, ck.s, g, tc, tau[j], rgb);
         a.vis_id[vis_index(a, g.tile, k, lane)] = g.inimg ? zid : kVisOut;
         // colour of a covered pixel; the background accumulators start at 0
         for (int sl = 0; sl < a.NS; ++sl) {
@@ -1199,12 +1236,10 @@ __global__ __launch_bounds__(64) void k_bg(RasterArgs a)
     __shared__ BgShared<T> sh;
     const int lane = threadIdx.x & 63;
     if (a.hdr->error_bits & kHdrOverflow) return;
-    const int64_t ntasks = a.hdr->ntasks;
-    for (;;) {
-        const int64_t t = next_task(&a.hdr->task_ctr[0]);
-        if (t >= ntasks || t >= a.maxtasks) break;
+    const int64_t ntasks = min(a.hdr->ntasks, a.maxtasks);
+    for (int64_t t = blockIdx.x; t < ntasks; t += gridDim.x) {
         const uint64_t task = a.tasks[t];
-        const int64_t ct = (int64_t)(task >> 32);
+        const int ct = (int)(task >> 32);
         const int slice = (int)(uint32_t)task;
         TileCtx g;
         tile_ctx(a, ct, g);
@@ -1226,11 +1261,14 @@ __global__ __launch_bounds__(64) void k_bg(RasterArgs a)
         const int64_t beg = a.off[idx];
         const int n_e = a.cnt[idx];
         const int e0 = slice * a.SL, e1 = min(n_e, e0 + a.SL);
+        Pref pf = prefetch(a, beg + e0, min(NB, e1 - e0));
         for (int base = e0; base < e1; base += NB) {
             const int nb = min(NB, e1 - base);
+            const Pref cur = pf;
+            if (base + NB < e1) pf = prefetch(a, beg + base + NB, min(NB, e1 - base - NB));
             int cnt, pre;
             const int total =
-                stage_items<T>(a, sh.it, beg + base, nb, ck.s, g, tc, tau, kRecBg, a.halo, unc, nullptr, cnt, pre);
+                stage_items<T>(a, sh.it, cur, nb, ck.s, g, tc, tau, kRecBg, a.halo, unc, nullptr, nullptr, cnt, pre);
             for_items<T>(sh.it, total, cnt, pre,
                          [&](int e, int p) { bg_item_fwd<T, SOLVER>(a, sh, e, p, tau, xbits, tc); });
         }
@@ -1454,7 +1492,7 @@ template <int T, int SOLVER>
 __global__ __launch_bounds__(64) void k_fg_bwd(RasterArgs a, GradArgs ga)
 {
     __shared__ FgBwdShared<T> sh;
-    const int64_t ct = xcd_remap(blockIdx.x, gridDim.x);
+    const int ct = xcd_remap(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x & 63;
     if (a.hdr->error_bits & kHdrOverflow) return;
     TileCtx g;
@@ -1488,8 +1526,11 @@ __global__ __launch_bounds__(64) void k_fg_bwd(RasterArgs a, GradArgs ga)
 
     const int64_t beg = a.off[ct];
     const int n_e = a.cnt[ct];
+    Pref pf = prefetch(a, beg, min(NB, n_e));
     for (int base = 0; base < n_e; base += NB) {
         const int nb = min(NB, n_e - base);
+        const Pref cur = pf;
+        if (base + NB < n_e) pf = prefetch(a, beg + base + NB, min(NB, n_e - base - NB));
         if (used + 3 * nb > kVTLoad) {
             vt_flush(sh.vt, ck.s, a, ga);
             used = 0;
@@ -1497,11 +1538,10 @@ __global__ __launch_bounds__(64) void k_fg_bwd(RasterArgs a, GradArgs ga)
         lds_sync();
         int hb = -1;
         if (lane < nb) {
-            const uint32_t ent = a.list[beg + base + lane];
-            const int f = (int)(ent >> 8);
+            const int f = (int)(cur.ent >> 8);
+            const int *vq = cur.v;
             FaceRec r;
-            int vq[3];
-            stage_rec(a, f, ck.s, g.ua, g.va, tc, kRecGeom, r, vq);
+            stage_rec(a, f, vq, ck.s, g.ua, g.va, tc, kRecGeom, r);
             store_rec(sh.it, lane, r);
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
@@ -1684,12 +1724,14 @@ __global__ __launch_bounds__(64) void k_bg_bwd(RasterArgs a, GradArgs ga)
     const int lane = threadIdx.x & 63;
     if (a.hdr->error_bits & kHdrOverflow) return;
     vt_clear(sh.vt);
-    const int64_t ntasks = a.hdr->ntasks;
+    // tasks vary more in cost here than in the forward (pixels without
+    // gradient drop out), so waves take them from a counter
+    const int64_t ntasks = min(a.hdr->ntasks, a.maxtasks);
     for (;;) {
         const int64_t t = next_task(&a.hdr->task_ctr[1]);
-        if (t >= ntasks || t >= a.maxtasks) break;
+        if (t >= ntasks) break;
         const uint64_t task = a.tasks[t];
-        const int64_t ct = (int64_t)(task >> 32);
+        const int ct = (int)(task >> 32);
         const int slice = (int)(uint32_t)task;
         TileCtx g;
         tile_ctx(a, ct, g);
@@ -1727,15 +1769,18 @@ __global__ __launch_bounds__(64) void k_bg_bwd(RasterArgs a, GradArgs ga)
         const int n_e = a.cnt[idx];
         const int e0 = slice * a.SL, e1 = min(n_e, e0 + a.SL);
         int used = 0;
+        Pref pf = prefetch(a, beg + e0, min(NB, e1 - e0));
         for (int base = e0; base < e1; base += NB) {
             const int nb = min(NB, e1 - base);
+            const Pref cur = pf;
+            if (base + NB < e1) pf = prefetch(a, beg + base + NB, min(NB, e1 - base - NB));
             if (used + 3 * nb > kVTLoad) {
                 vt_flush(sh.vt, ck.s, a, ga);
                 used = 0;
             }
             int cnt, pre;
-            const int total =
-                stage_items<T>(a, sh.it, beg + base, nb, ck.s, g, tc, tau, kRecBg, a.halo, bgm, sh.vslot, cnt, pre);
+            const int total = stage_items<T>(a, sh.it, cur, nb, ck.s, g, tc, tau, kRecBg, a.halo, bgm, nullptr,
+                                             sh.vslot, cnt, pre);
             used += vt_bind(sh.vt, sh.vslot, nb);
             for_items<T>(sh.it, total, cnt, pre,
                          [&](int e, int p) { bg_item_bwd<T, SOLVER>(a, sh, e, p, tau, xbits, tc); });
@@ -1782,6 +1827,21 @@ __global__ void k_kf_to_vertex(const float *__restrict__ verts, const float *__r
 // ---------------------------------------------------------------- launches
 
 static inline unsigned grid_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+// Waves a persistent kernel keeps resident on the current device: its
+// occupancy (registers, LDS) times the compute units.  Each wave takes every
+// grid-th task, so launching exactly what fits avoids waves that start late
+// with a full share of tasks.
+template <class K>
+static unsigned resident_waves(K kernel)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1024;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kWave, 0) != hipSuccess || per_cu <= 0)
+        per_cu = 8;
+    return (unsigned)(cus * per_cu);
+}
 
 static RasterArgs raster_args(const Plan &p, const Inputs &in, const Bufs &b)
 {
@@ -1870,7 +1930,8 @@ static void raster_fwd_T(const Plan &p, const RasterArgs &ra, const Bufs &b, hip
     hipLaunchKernelGGL(k_scan3, dim3(grid_for(p.ntct, 256)), dim3(256), 0, st, b.toff, b.tbsum, p.ntct);
     hipLaunchKernelGGL(k_tasks, dim3(grid_for(p.ntct, 256)), dim3(256), 0, st, b.tsl, b.toff, p.ntct, b.tasks,
                        p.maxtasks);
-    hipLaunchKernelGGL((k_bg<T, SOLVER>), dim3((unsigned)p.persist), dim3(kWave), 0, st, ra);
+    static const unsigned nw = resident_waves(k_bg<T, SOLVER>);
+    hipLaunchKernelGGL((k_bg<T, SOLVER>), dim3(nw), dim3(kWave), 0, st, ra);
 }
 
 template <int T>
@@ -1914,7 +1975,8 @@ template <int T, int SOLVER>
 static void raster_bwd_T(const Plan &p, const RasterArgs &ra, const GradArgs &ga, hipStream_t st)
 {
     hipLaunchKernelGGL((k_fg_bwd<T, SOLVER>), dim3((unsigned)p.ntct), dim3(kWave), 0, st, ra, ga);
-    hipLaunchKernelGGL((k_bg_bwd<T, SOLVER>), dim3((unsigned)p.persist), dim3(kWave), 0, st, ra, ga);
+    static const unsigned nw = 3 * resident_waves(k_bg_bwd<T, SOLVER>) / 2;
+    hipLaunchKernelGGL((k_bg_bwd<T, SOLVER>), dim3(nw), dim3(kWave), 0, st, ra, ga);
 }
 
 template <int T>
