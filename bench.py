@@ -28,18 +28,24 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "pixel-subframes/sec fwd+bwd, fast solver vs per-subframe recompute"
+KERNEL_NAMES = {"fg": "k_fg", "bg": "k_bg", "fg_bwd": "k_fg_bwd", "bg_bwd": "k_bg_bwd"}
 PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (packed); 78.6 without packing
 PEAK_HBM_GBS = 8000.0
 
-# Algorithmic FLOPs per counted unit (FMA = 2), see the design notes:
-#   forward raster: 18 per bbox pair, +6 per covering pair, 24 per
-#   (pixel, face, segment) coefficient setup, 75 per contributing background
-#   pair, 20 per foreground and 2 per background pixel-sub-frame;
-#   backward raster: 18 + 90 per foreground pixel-sub-frame (recomputed
-#   barycentrics + adjoint), 75 + 75 per contributing background pair.
-FWD_COEF = {"bbox_pairs": 18, "cover_pairs": 6, "setup_triples": 24, "bg_pairs": 75,
-            "fg_pixsub": 20, "bg_pixsub": 2}
-BWD_COEF = {"fg_pixsub": 108, "bg_pairs": 150}
+# Algorithmic FLOPs per counted unit (FMA = 2), per kernel:
+#   foreground pass: 18 per bbox pair, +6 per covering pair, 24 per
+#     (pixel, face, segment) coefficient setup, 20 per foreground pixel-sub-frame;
+#   background pass: 75 per contributing background pair, 2 per background
+#     pixel-sub-frame;
+#   foreground adjoint: 18 + 90 per foreground pixel-sub-frame (recomputed
+#     barycentrics + adjoint);
+#   background adjoint: 75 + 75 per contributing background pair.
+KERNEL_COEF = {
+    "fg": {"bbox_pairs": 18, "cover_pairs": 6, "setup_triples": 24, "fg_pixsub": 20},
+    "bg": {"bg_pairs": 75, "bg_pixsub": 2},
+    "fg_bwd": {"fg_pixsub": 108},
+    "bg_bwd": {"bg_pairs": 150},
+}
 
 
 def log(*a):
@@ -48,6 +54,13 @@ def log(*a):
 
 def flops(counters, coef):
     return float(sum(coef[k] * counters[k] for k in coef))
+
+
+def kernel_ms(prof):
+    f, b = max(1, prof.fwd_calls), max(1, prof.bwd_calls)
+    return {"project": prof.project_ms / f, "bin": prof.bin_ms / f, "fg": prof.fg_ms / f, "bg": prof.bg_ms / f,
+            "resolve": prof.resolve_ms / f, "fg_bwd": prof.fg_bwd_ms / b, "bg_bwd": prof.bg_bwd_ms / b,
+            "vertex_grad": prof.vertex_grad_ms / b}
 
 
 def main():
@@ -121,10 +134,10 @@ def main():
         prof = B.rb_profile_read()
         B.rb_profile_enable(False)
         results[solver] = dict(ms=ms, value=units / (ms * 1e-3), prof=prof)
+        km = kernel_ms(prof)
+        results[solver]["kernel_ms"] = km
         log(f"{solver}: {ms:.3f} ms/step  {units / (ms * 1e-3):.3e} px-sub/s  "
-            f"project {prof.project_ms / prof.fwd_calls:.3f} bin {prof.bin_ms / prof.fwd_calls:.3f} "
-            f"raster_fwd {prof.raster_fwd_ms / prof.fwd_calls:.3f} reduce {prof.reduce_ms / prof.fwd_calls:.3f} "
-            f"raster_bwd {prof.raster_bwd_ms / prof.bwd_calls:.3f} vgrad {prof.vertex_grad_ms / prof.bwd_calls:.3f} ms")
+            + " ".join(f"{k} {v:.3f}" for k, v in km.items()) + " ms")
 
     # ---- FP64 reference on the host: CPU baseline and exact pair counters
     cpu = None
@@ -143,17 +156,19 @@ def main():
         log(f"cpu oracle: {dt:.2f} s with {nth} threads; counters {counters}")
 
     fast = results["fast"]
-    pf = fast["prof"]
-    fwd_ms = pf.raster_fwd_ms / max(1, pf.fwd_calls)
-    bwd_ms = pf.raster_bwd_ms / max(1, pf.bwd_calls)
+    km = fast["kernel_ms"]
     roof = None
     if counters is not None:
-        ff, fb = flops(counters, FWD_COEF), flops(counters, BWD_COEF)
-        name, fl, ms = ("raster_bwd", fb, bwd_ms) if bwd_ms >= fwd_ms else ("raster_fwd", ff, fwd_ms)
+        # dominant kernel: the longest of the four raster kernels
+        name = max(KERNEL_COEF, key=lambda k: km[k])
+        fl, ms = flops(counters, KERNEL_COEF[name]), km[name]
         ach = fl / (ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "kernel": name, "achieved": round(ach, 4), "peak": PEAK_FP32_TFLOPS,
+        roof = {"bound": "alu", "kernel": KERNEL_NAMES[name], "achieved": round(ach, 4), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 6), "traffic": None,
-                "flop_per_launch": fl, "avg_launch_ms": round(ms, 5)}
+                "flop_per_launch": fl, "avg_launch_ms": round(ms, 5),
+                "all_kernels": {KERNEL_NAMES[k]: {"ms": round(km[k], 5),
+                                                  "tflops": round(flops(counters, KERNEL_COEF[k]) / (km[k] * 1e-3) / 1e12, 4)}
+                                for k in KERNEL_COEF}}
     out = {
         "metric": METRIC,
         "value": round(fast["value"], 1),
@@ -173,9 +188,7 @@ def main():
         "recompute": {"value": round(results["recompute"]["value"], 1),
                       "ms_per_step": round(results["recompute"]["ms"], 4)},
         "fast_over_recompute": round(fast["value"] / results["recompute"]["value"], 4),
-        "kernel_ms": {"project": pf.project_ms / pf.fwd_calls, "bin": pf.bin_ms / pf.fwd_calls,
-                      "raster_fwd": fwd_ms, "reduce": pf.reduce_ms / pf.fwd_calls, "raster_bwd": bwd_ms,
-                      "vertex_grad": pf.vertex_grad_ms / pf.bwd_calls},
+        "kernel_ms": {k: round(v, 5) for k, v in km.items()},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

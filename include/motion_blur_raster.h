@@ -32,6 +32,9 @@
  *    header and read with rb_read_header.
  *  - Calls that share a workspace must not overlap in time.  Distinct
  *    workspaces may be used concurrently from several threads / streams.
+ *  - Every call is a fixed sequence of kernel launches on the stream (no
+ *    host-device copies, no allocation), so it can be captured in a hipGraph
+ *    and replayed.
  */
 #ifndef MOTION_BLUR_RASTER_H
 #define MOTION_BLUR_RASTER_H
@@ -135,15 +138,59 @@ rb_status rb_render_blur_bwd(const float *verts, int32_t V, const int32_t *faces
  * stream.  Returns RB_OK, RB_EINVAL or RB_EDEVICE. */
 rb_status rb_read_header(const void *workspace, rb_header *out, void *stream);
 
-/* Kernel timing for benchmarks.  While enabled, every forward / backward
- * call records HIP events on its stream around each of its phases
- * (projection, binning, rasterization, image reduction; backward
- * rasterization, vertex-gradient mapping).  rb_profile_read SYNCHRONIZES on
- * those events, returns the accumulated milliseconds and call counts, and
- * clears them.  Enabling or disabling also clears.  Thread-safe. */
+/* Batched rendering: n meshes of any sizes, sub-frame counts and image sizes
+ * in one sequence of launches, every kernel covering all instances (the
+ * background passes are persistent kernels over the tasks of all instances).
+ * The rb_instance array is HOST memory holding DEVICE pointers.  options
+ * supplies delta, eps_cutoff, solver, chunk_len and slice_len for the whole
+ * batch; num_subframes and list_capacity of options are ignored in favour of
+ * each instance's own.  mode RB_BATCH_FORWARD writes every instance's image;
+ * RB_BATCH_BACKWARD reads grad_image and overwrites grad_verts / grad_attrs,
+ * reusing the state the forward left in the same workspace. */
 typedef struct {
-    double project_ms, bin_ms, raster_fwd_ms, reduce_ms;   /* forward phases  */
-    double raster_bwd_ms, vertex_grad_ms;                  /* backward phases */
+    const float *verts;      /* [V][3]                                          */
+    int32_t V;
+    const int32_t *faces;    /* [F][3]                                          */
+    int32_t F;
+    const float *attrs;      /* [V][C]                                          */
+    int32_t C;
+    rb_motion motion;
+    rb_camera camera;
+    int32_t num_subframes;   /* K >= 1                                          */
+    int64_t list_capacity;   /* bin-list entries; 0 = auto                      */
+    float *image;            /* [C+1][H][W], forward output                     */
+    const float *grad_image; /* [C+1][H][W], backward input                     */
+    float *grad_verts;       /* [V][3], backward output                         */
+    float *grad_attrs;       /* [V][C], backward output                         */
+} rb_instance;
+
+enum { RB_BATCH_FORWARD = 0, RB_BATCH_BACKWARD = 1 };
+
+/* Workspace bytes for a batch (HOST only).  Returns RB_OK, RB_EINVAL or
+ * RB_EUNSUPPORTED (n <= 0 or an instance's sizes). */
+rb_status rb_batch_workspace_size(const rb_instance *instances, int32_t n, const rb_options *options,
+                                  size_t *bytes);
+
+/* Render a batch (see above).  Returns the first failing instance's status
+ * for argument errors, RB_EWORKSPACE or RB_EDEVICE. */
+rb_status rb_render_blur_batched(const rb_instance *instances, int32_t n, const rb_options *options,
+                                 int32_t mode, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Headers of every instance of a batch into out[n] (HOST).  SYNCHRONIZES. */
+rb_status rb_batch_read_headers(const rb_instance *instances, int32_t n, const rb_options *options,
+                                const void *workspace, rb_header *out, void *stream);
+
+/* Kernel timing for benchmarks.  While enabled, every call records HIP events
+ * on its stream between its kernels.  Forward: projection (with workspace
+ * initialisation), binning, foreground pass (with the background task list),
+ * background pass, sub-frame average.  Backward: foreground adjoint (with
+ * the gradient clear), background adjoint, vertex-gradient mapping.
+ * rb_profile_read SYNCHRONIZES on those events, returns the accumulated
+ * milliseconds and call counts, and clears them.  Enabling or disabling also
+ * clears.  Thread-safe. */
+typedef struct {
+    double project_ms, bin_ms, fg_ms, bg_ms, resolve_ms;   /* forward phases  */
+    double fg_bwd_ms, bg_bwd_ms, vertex_grad_ms;           /* backward phases */
     int64_t fwd_calls, bwd_calls;
 } rb_profile_stats;
 

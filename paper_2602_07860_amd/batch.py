@@ -1,0 +1,196 @@
+"""Batched rendering: many meshes of uneven size, sub-frame count and
+resolution through one sequence of launches of the HIP library (every kernel
+covers all instances; the background passes are persistent kernels over the
+tasks of all instances), optionally captured once in a hipGraph and replayed,
+with the chunk length and the background slice length chosen by a small
+autotuner that times the candidates on the batch itself.
+
+Argument marshalling only: all rendering work runs in the library.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import torch
+
+from . import binding as B
+from .render import RenderOptions, SceneTensors, _check_tensor, _stream_ptr
+
+
+def _initial_capacity(st: SceneTensors, chunk_len: int) -> int:
+    F = st.faces.shape[0]
+    S = st.model.shape[0] - 1
+    return max(1 << 20, 6 * F * (st.num_subframes // max(1, chunk_len) + S))
+
+
+class BatchRenderer:
+    """Fixed batch of scenes with preallocated outputs.
+
+    forward() writes self.images[i] ([C+1, H, W] per instance); backward()
+    reads self.grad_images[i] and writes self.grad_verts[i] / self.grad_attrs[i].
+    Both are pure launch sequences on the current stream (no host copies, no
+    allocation), so they can be captured in a CUDA/HIP graph; fit() grows the
+    bin-list capacities until a forward needs no more, which must happen
+    before capture."""
+
+    def __init__(self, scenes: Sequence[SceneTensors], opts: RenderOptions,
+                 capacities: Optional[List[int]] = None):
+        self.scenes = list(scenes)
+        self.opts = opts
+        dev = self.scenes[0].verts.device
+        for st in self.scenes:
+            for t, n, d in ((st.verts, "verts", torch.float32), (st.faces, "faces", torch.int32),
+                            (st.attrs, "attrs", torch.float32), (st.model, "keyframe_model", torch.float32)):
+                _check_tensor(t, n, d)
+        self.images = [torch.empty((st.attrs.shape[1] + 1, st.camera.height, st.camera.width),
+                                   dtype=torch.float32, device=dev) for st in self.scenes]
+        self.grad_images = [torch.zeros_like(im) for im in self.images]
+        self.grad_verts = [torch.empty_like(st.verts) for st in self.scenes]
+        self.grad_attrs = [torch.empty_like(st.attrs) for st in self.scenes]
+        self.caps = list(capacities) if capacities else [_initial_capacity(st, opts.chunk_len) for st in self.scenes]
+        self._plan()
+
+    def _instances(self) -> List[B.rb_instance]:
+        out = []
+        for i, st in enumerate(self.scenes):
+            x = B.rb_instance()
+            x.verts, x.V = st.verts.data_ptr(), st.verts.shape[0]
+            x.faces, x.F = st.faces.data_ptr(), st.faces.shape[0]
+            x.attrs, x.C = st.attrs.data_ptr(), st.attrs.shape[1]
+            x.motion = B.rb_motion(st.model.shape[0] - 1, st.model.data_ptr())
+            x.camera = st.camera
+            x.num_subframes = st.num_subframes
+            x.list_capacity = int(self.caps[i])
+            x.image = self.images[i].data_ptr()
+            x.grad_image = self.grad_images[i].data_ptr()
+            x.grad_verts = self.grad_verts[i].data_ptr()
+            x.grad_attrs = self.grad_attrs[i].data_ptr()
+            out.append(x)
+        return out
+
+    def _plan(self) -> None:
+        self.inst = self._instances()
+        self.o = self.opts.c_struct(0)
+        self.ws_bytes = B.rb_batch_workspace_size(self.inst, self.o)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.images[0].device)
+
+    def forward(self) -> List[torch.Tensor]:
+        st = B.rb_render_blur_batched(self.inst, self.o, B.RB_BATCH_FORWARD, self.workspace.data_ptr(),
+                                      self.ws_bytes, _stream_ptr(self.workspace.device))
+        if st != B.RB_OK:
+            raise B.RenderError(st, "rb_render_blur_batched(forward)")
+        return self.images
+
+    def backward(self) -> Tuple[List[torch.Tensor], List[torch.Tensor]]:
+        st = B.rb_render_blur_batched(self.inst, self.o, B.RB_BATCH_BACKWARD, self.workspace.data_ptr(),
+                                      self.ws_bytes, _stream_ptr(self.workspace.device))
+        if st != B.RB_OK:
+            raise B.RenderError(st, "rb_render_blur_batched(backward)")
+        return self.grad_verts, self.grad_attrs
+
+    def headers(self) -> List[B.rb_header]:
+        return B.rb_batch_read_headers(self.inst, self.o, self.workspace.data_ptr(),
+                                       _stream_ptr(self.workspace.device))
+
+    def fit(self, max_rounds: int = 4) -> None:
+        """Run the forward, grow every overflowing list capacity and re-plan
+        until no instance overflows; raise on device-side argument errors."""
+        for _ in range(max_rounds):
+            self.forward()
+            hs = self.headers()
+            grow = False
+            for i, h in enumerate(hs):
+                if h.error_bits & B.HDR_FACE_RANGE:
+                    raise B.RenderError(B.RB_ERANGE, f"instance {i}")
+                if h.error_bits & B.HDR_BEHIND:
+                    raise B.RenderError(B.RB_EBEHIND, f"instance {i}")
+                if h.error_bits & B.HDR_OVERFLOW:
+                    self.caps[i] = int(h.list_entries * 1.25) + 4096
+                    grow = True
+            if not grow:
+                return
+            self._plan()
+        raise B.RenderError(B.RB_EOVERFLOW, "BatchRenderer.fit")
+
+
+class L2Step:
+    """One fwd + dL/dimage + bwd step of an L2 loss against fixed targets,
+    eager or captured in a graph and replayed."""
+
+    def __init__(self, renderer: BatchRenderer, targets: Sequence[torch.Tensor]):
+        self.r = renderer
+        self.targets = list(targets)
+        self.graph: Optional[torch.cuda.CUDAGraph] = None
+
+    def _body(self) -> None:
+        imgs = self.r.forward()
+        for g, im, tg in zip(self.r.grad_images, imgs, self.targets):
+            torch.sub(im, tg, out=g)
+            g.mul_(2.0)
+        self.r.backward()
+
+    def eager(self) -> None:
+        self._body()
+
+    def capture(self) -> None:
+        # warm up on a side stream (required before capture), then capture
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self._body()
+        torch.cuda.current_stream().wait_stream(s)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._body()
+
+    def replay(self) -> None:
+        self.graph.replay()
+
+
+# ---------------------------------------------------------------- autotuner
+
+_tuned: Dict[tuple, Tuple[int, int]] = {}
+
+
+def batch_signature(scenes: Sequence[SceneTensors], solver: str) -> tuple:
+    return (solver,) + tuple((st.verts.shape[0], st.faces.shape[0], st.attrs.shape[1], st.model.shape[0],
+                              st.num_subframes, st.camera.width, st.camera.height) for st in scenes)
+
+
+def autotune(scenes: Sequence[SceneTensors], targets: Sequence[torch.Tensor], solver: str = "fast",
+             chunk_lens=(1, 2, 4, 8), slice_lens=(32, 64, 128, 256), reps: int = 3,
+             log=None) -> Tuple[int, int]:
+    """Chunk length and background slice length with the shortest fwd+bwd L2
+    step on this batch (each candidate timed with device events over `reps`
+    eager steps after one warm-up that also sizes its lists).  Results are
+    remembered per batch signature."""
+    key = batch_signature(scenes, solver)
+    if key in _tuned:
+        return _tuned[key]
+    best, best_ms = None, float("inf")
+    caps = None
+    for T in chunk_lens:
+        caps = None   # list sizes depend on the chunk length
+        for SL in slice_lens:
+            r = BatchRenderer(scenes, RenderOptions(0, solver=solver, chunk_len=T, slice_len=SL), caps)
+            r.fit()
+            caps = r.caps
+            step = L2Step(r, targets)
+            step.eager()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                step.eager()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            if log:
+                log(f"autotune T={T} SL={SL}: {ms:.3f} ms")
+            if ms < best_ms:
+                best, best_ms = (T, SL), ms
+            del r, step
+    _tuned[key] = best
+    return best

@@ -18,7 +18,10 @@ RB_MAX_FACES = 1 << 23
 RB_MAX_CHUNK = 8
 HDR_FACE_RANGE, HDR_BEHIND, HDR_OVERFLOW = 1, 2, 4
 
+RB_BATCH_FORWARD, RB_BATCH_BACKWARD = 0, 1
+
 EXPORTED = ["rb_workspace_size", "rb_validate", "rb_render_blur_fwd", "rb_render_blur_bwd",
+            "rb_batch_workspace_size", "rb_render_blur_batched", "rb_batch_read_headers",
             "rb_read_header", "rb_profile_enable", "rb_profile_read", "rb_status_string"]
 
 
@@ -45,9 +48,20 @@ class rb_header(ctypes.Structure):
 
 class rb_profile_stats(ctypes.Structure):
     _fields_ = [("project_ms", ctypes.c_double), ("bin_ms", ctypes.c_double),
-                ("raster_fwd_ms", ctypes.c_double), ("reduce_ms", ctypes.c_double),
-                ("raster_bwd_ms", ctypes.c_double), ("vertex_grad_ms", ctypes.c_double),
+                ("fg_ms", ctypes.c_double), ("bg_ms", ctypes.c_double),
+                ("resolve_ms", ctypes.c_double), ("fg_bwd_ms", ctypes.c_double),
+                ("bg_bwd_ms", ctypes.c_double), ("vertex_grad_ms", ctypes.c_double),
                 ("fwd_calls", ctypes.c_int64), ("bwd_calls", ctypes.c_int64)]
+
+
+class rb_instance(ctypes.Structure):
+    _fields_ = [("verts", ctypes.c_void_p), ("V", ctypes.c_int32),
+                ("faces", ctypes.c_void_p), ("F", ctypes.c_int32),
+                ("attrs", ctypes.c_void_p), ("C", ctypes.c_int32),
+                ("motion", rb_motion), ("camera", rb_camera),
+                ("num_subframes", ctypes.c_int32), ("list_capacity", ctypes.c_int64),
+                ("image", ctypes.c_void_p), ("grad_image", ctypes.c_void_p),
+                ("grad_verts", ctypes.c_void_p), ("grad_attrs", ctypes.c_void_p)]
 
 
 class RenderError(RuntimeError):
@@ -90,6 +104,12 @@ def lib():
         L.rb_profile_read.argtypes = [P(rb_profile_stats)]
         L.rb_status_string.restype = ctypes.c_char_p
         L.rb_status_string.argtypes = [i32]
+        L.rb_batch_workspace_size.restype = i32
+        L.rb_batch_workspace_size.argtypes = [P(rb_instance), i32, P(rb_options), P(sz)]
+        L.rb_render_blur_batched.restype = i32
+        L.rb_render_blur_batched.argtypes = [P(rb_instance), i32, P(rb_options), i32, vp, sz, vp]
+        L.rb_batch_read_headers.restype = i32
+        L.rb_batch_read_headers.argtypes = [P(rb_instance), i32, P(rb_options), vp, P(rb_header), vp]
         _lib = L
     return _lib
 
@@ -122,6 +142,31 @@ def rb_render_blur_bwd(verts, V, faces, F, attrs, C, motion, camera, options, gr
     return lib().rb_render_blur_bwd(verts, V, faces, F, attrs, C, ctypes.byref(motion),
                                     ctypes.byref(camera), ctypes.byref(options), grad_image,
                                     grad_verts, grad_attrs, workspace, workspace_bytes, stream)
+
+
+def rb_batch_workspace_size(instances, options: rb_options) -> int:
+    arr = (rb_instance * len(instances))(*instances)
+    out = ctypes.c_size_t()
+    st = lib().rb_batch_workspace_size(arr, len(instances), ctypes.byref(options), ctypes.byref(out))
+    if st != RB_OK:
+        raise RenderError(st, "rb_batch_workspace_size")
+    return out.value
+
+
+def rb_render_blur_batched(instances, options: rb_options, mode: int, workspace, workspace_bytes,
+                           stream) -> int:
+    arr = (rb_instance * len(instances))(*instances)
+    return lib().rb_render_blur_batched(arr, len(instances), ctypes.byref(options), mode, workspace,
+                                        workspace_bytes, stream)
+
+
+def rb_batch_read_headers(instances, options: rb_options, workspace, stream):
+    arr = (rb_instance * len(instances))(*instances)
+    out = (rb_header * len(instances))()
+    st = lib().rb_batch_read_headers(arr, len(instances), ctypes.byref(options), workspace, out, stream)
+    if st != RB_OK:
+        raise RenderError(st, "rb_batch_read_headers")
+    return list(out)
 
 
 def rb_read_header(workspace, stream) -> rb_header:

@@ -68,6 +68,7 @@ static rb_status make_plan(int32_t V, int32_t F, int32_t C, const rb_motion *mot
     // task's set-up
     p.SL = opt->slice_len > 0 ? opt->slice_len : 64;
     p.NS = std::max(C, 2);
+    p.nfb = (F + 255) / 256;
     p.cap = opt->list_capacity > 0 ? opt->list_capacity
                                    : std::max<int64_t>(1 << 20, (int64_t)64 * F * std::min(p.NC, 64));
     p.ncounts = (int64_t)2 * p.NC * p.ntiles;
@@ -112,26 +113,72 @@ static rb_status make_plan(int32_t V, int32_t F, int32_t C, const rb_motion *mot
     return RB_OK;
 }
 
-static Bufs carve(const Plan &p, void *ws)
+// Plan a batch: instance workspaces one after another (256-byte aligned),
+// then the device instance table, the batch's task prefix and its header.
+static rb_status make_batch(const std::vector<Plan> &plans, Batch &bt)
 {
-    char *b = (char *)ws;
-    Bufs r;
-    r.hdr = (DevHeader *)(b + p.o_hdr);
-    r.kf = (double2 *)(b + p.o_kf);
-    r.kfz = (float *)(b + p.o_kfz);
-    r.cnt = (int32_t *)(b + p.o_cnt);
-    r.off = (int64_t *)(b + p.o_off);
-    r.cur = (int32_t *)(b + p.o_cur);
-    r.bsum = (int64_t *)(b + p.o_bsum);
-    r.list = (uint32_t *)(b + p.o_list);
-    r.vis_id = (int32_t *)(b + p.o_vis_id);
-    r.pix = (float *)(b + p.o_pix);
-    r.tsl = (int32_t *)(b + p.o_tsl);
-    r.toff = (int64_t *)(b + p.o_toff);
-    r.tbsum = (int64_t *)(b + p.o_tbsum);
-    r.tasks = (uint64_t *)(b + p.o_tasks);
-    r.gkf = (float *)(b + p.o_gkf);
-    return r;
+    bt.n = (int)plans.size();
+    if (bt.n <= 0) return RB_EINVAL;
+    bt.T = plans[0].T;
+    bt.solver = plans[0].solver;
+    bt.plans = plans;
+    bt.base.resize(bt.n);
+    Grids g{};
+    size_t o = 0;
+    for (int i = 0; i < bt.n; ++i) {
+        const Plan &p = plans[i];
+        bt.base[i] = o;
+        o = align256(o + p.total);
+        g.init += (p.ncounts + 255) / 256;
+        g.proj += ((int64_t)(p.S + 1) * p.V + p.F + 255) / 256;
+        g.bin += (int64_t)p.NC * p.nfb;
+        g.scan1 += p.nblocks_scan;
+        g.scan3 += (p.ncounts + 255) / 256;
+        g.tscan1 += p.nblocks_tscan;
+        g.tscan3 += (p.ntct + 255) / 256;
+        g.fg += p.ntct;
+        g.res += p.ntiles;
+        g.bwdinit += ((int64_t)(p.S + 1) * p.V * 2 + (int64_t)p.V * p.C + 255) / 256;
+        g.vtx += (p.V + 255) / 256;
+    }
+    // one launch covers every instance: block counts must fit the grid and
+    // the 32-bit block starts of the table
+    const int64_t lim = (1LL << 31) - 1;
+    for (int64_t v : {g.init, g.proj, g.bin, g.scan1, g.scan3, g.tscan1, g.tscan3, g.fg, g.res, g.bwdinit, g.vtx})
+        if (v > lim) return RB_EUNSUPPORTED;
+    bt.g = g;
+    bt.o_table = o;
+    o = align256(o + (size_t)bt.n * sizeof(Inst));
+    bt.o_tprefix = o;
+    o = align256(o + (size_t)(bt.n + 1) * sizeof(int64_t));
+    bt.o_bhdr = o;
+    o = align256(o + sizeof(BatchHeader));
+    bt.total = o;
+    return RB_OK;
+}
+
+static rb_status single_batch(int32_t V, int32_t F, int32_t C, const rb_motion *motion, const rb_camera *camera,
+                              const rb_options *options, Batch &bt)
+{
+    Plan p;
+    rb_status st = make_plan(V, F, C, motion, camera, options, p);
+    if (st != RB_OK) return st;
+    return make_batch(std::vector<Plan>{p}, bt);
+}
+
+// per-instance options of a batch: the batch's, with the instance's K and capacity
+static rb_status batch_plans(const rb_instance *inst, int32_t n, const rb_options *opt, std::vector<Plan> &plans)
+{
+    if (!inst || !opt || n <= 0) return RB_EINVAL;
+    plans.resize(n);
+    for (int i = 0; i < n; ++i) {
+        rb_options o = *opt;
+        o.num_subframes = inst[i].num_subframes;
+        o.list_capacity = inst[i].list_capacity;
+        rb_status st = make_plan(inst[i].V, inst[i].F, inst[i].C, &inst[i].motion, &inst[i].camera, &o, plans[i]);
+        if (st != RB_OK) return st;
+    }
+    return RB_OK;
 }
 
 // ---- benchmark timing (rb_profile_*)
@@ -156,8 +203,8 @@ static const PhaseEvents *prof_begin(int kind, PhaseEvents &pe)
 {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     if (!g_prof_on) return nullptr;
-    const int n = kind == 0 ? 5 : 4;
-    for (int i = 0; i < 5; ++i) pe.ev[i] = nullptr;
+    const int n = kind == 0 ? 6 : 4;
+    for (int i = 0; i < 6; ++i) pe.ev[i] = nullptr;
     for (int i = 0; i < n; ++i)
         if (hipEventCreate(&pe.ev[i]) != hipSuccess) pe.ev[i] = nullptr;
     g_prof.push_back(ProfRec{kind, pe});
@@ -174,21 +221,21 @@ rb_status rb_workspace_size(int32_t V, int32_t F, int32_t C, const rb_motion *mo
                             const rb_options *options, size_t *bytes)
 {
     if (!bytes) return RB_EINVAL;
-    Plan p;
-    rb_status st = make_plan(V, F, C, motion, camera, options, p);
+    Batch bt;
+    rb_status st = single_batch(V, F, C, motion, camera, options, bt);
     if (st != RB_OK) return st;
-    *bytes = p.total;
+    *bytes = bt.total;
     return RB_OK;
 }
 
 rb_status rb_validate(int32_t V, int32_t F, int32_t C, const rb_motion *motion, const rb_camera *camera,
                       const rb_options *options, size_t workspace_bytes)
 {
-    Plan p;
-    rb_status st = make_plan(V, F, C, motion, camera, options, p);
+    Batch bt;
+    rb_status st = single_batch(V, F, C, motion, camera, options, bt);
     if (st != RB_OK) return st;
     if (!motion->keyframe_model) return RB_EINVAL;
-    if (workspace_bytes < p.total) return RB_EWORKSPACE;
+    if (workspace_bytes < bt.total) return RB_EWORKSPACE;
     return RB_OK;
 }
 
@@ -199,13 +246,12 @@ rb_status rb_render_blur_fwd(const float *verts, int32_t V, const int32_t *faces
     if (!verts || !faces || !attrs || !image || !workspace) return RB_EINVAL;
     rb_status st = rb_validate(V, F, C, motion, camera, options, workspace_bytes);
     if (st != RB_OK) return st;
-    Plan p;
-    make_plan(V, F, C, motion, camera, options, p);
-    Bufs b = carve(p, workspace);
-    Inputs in{verts, faces, attrs, motion->keyframe_model};
+    Batch bt;
+    single_batch(V, F, C, motion, camera, options, bt);
+    std::vector<Io> io{Io{verts, faces, attrs, motion->keyframe_model, image, nullptr, nullptr, nullptr}};
     PhaseEvents pe;
     const PhaseEvents *pp = prof_begin(0, pe);
-    hipError_t e = launch_forward(p, in, b, image, (hipStream_t)stream, pp);
+    hipError_t e = launch_forward(bt, io, workspace, (hipStream_t)stream, pp);
     return e == hipSuccess ? RB_OK : RB_EDEVICE;
 }
 
@@ -217,14 +263,70 @@ rb_status rb_render_blur_bwd(const float *verts, int32_t V, const int32_t *faces
     if (!verts || !faces || !attrs || !grad_image || !grad_verts || !grad_attrs || !workspace) return RB_EINVAL;
     rb_status st = rb_validate(V, F, C, motion, camera, options, workspace_bytes);
     if (st != RB_OK) return st;
-    Plan p;
-    make_plan(V, F, C, motion, camera, options, p);
-    Bufs b = carve(p, workspace);
-    Inputs in{verts, faces, attrs, motion->keyframe_model};
+    Batch bt;
+    single_batch(V, F, C, motion, camera, options, bt);
+    std::vector<Io> io{Io{verts, faces, attrs, motion->keyframe_model, nullptr, grad_image, grad_verts, grad_attrs}};
     PhaseEvents pe;
     const PhaseEvents *pp = prof_begin(1, pe);
-    hipError_t e = launch_backward(p, in, b, grad_image, grad_verts, grad_attrs, (hipStream_t)stream, pp);
+    hipError_t e = launch_backward(bt, io, workspace, (hipStream_t)stream, pp);
     return e == hipSuccess ? RB_OK : RB_EDEVICE;
+}
+
+rb_status rb_batch_workspace_size(const rb_instance *instances, int32_t n, const rb_options *options, size_t *bytes)
+{
+    if (!bytes) return RB_EINVAL;
+    std::vector<Plan> plans;
+    rb_status st = batch_plans(instances, n, options, plans);
+    if (st != RB_OK) return st;
+    Batch bt;
+    st = make_batch(plans, bt);
+    if (st != RB_OK) return st;
+    *bytes = bt.total;
+    return RB_OK;
+}
+
+rb_status rb_render_blur_batched(const rb_instance *instances, int32_t n, const rb_options *options, int32_t mode,
+                                 void *workspace, size_t workspace_bytes, void *stream)
+{
+    if (!workspace || (mode != RB_BATCH_FORWARD && mode != RB_BATCH_BACKWARD)) return RB_EINVAL;
+    std::vector<Plan> plans;
+    rb_status st = batch_plans(instances, n, options, plans);
+    if (st != RB_OK) return st;
+    Batch bt;
+    st = make_batch(plans, bt);
+    if (st != RB_OK) return st;
+    if (workspace_bytes < bt.total) return RB_EWORKSPACE;
+    std::vector<Io> io(n);
+    for (int i = 0; i < n; ++i) {
+        const rb_instance &x = instances[i];
+        if (!x.verts || !x.faces || !x.attrs || !x.motion.keyframe_model) return RB_EINVAL;
+        if (mode == RB_BATCH_FORWARD && !x.image) return RB_EINVAL;
+        if (mode == RB_BATCH_BACKWARD && (!x.grad_image || !x.grad_verts || !x.grad_attrs)) return RB_EINVAL;
+        io[i] = Io{x.verts, x.faces, x.attrs, x.motion.keyframe_model, x.image, x.grad_image, x.grad_verts,
+                   x.grad_attrs};
+    }
+    PhaseEvents pe;
+    const PhaseEvents *pp = prof_begin(mode == RB_BATCH_FORWARD ? 0 : 1, pe);
+    hipError_t e = mode == RB_BATCH_FORWARD ? launch_forward(bt, io, workspace, (hipStream_t)stream, pp)
+                                             : launch_backward(bt, io, workspace, (hipStream_t)stream, pp);
+    return e == hipSuccess ? RB_OK : RB_EDEVICE;
+}
+
+rb_status rb_batch_read_headers(const rb_instance *instances, int32_t n, const rb_options *options,
+                                const void *workspace, rb_header *out, void *stream)
+{
+    if (!workspace || !out) return RB_EINVAL;
+    std::vector<Plan> plans;
+    rb_status st = batch_plans(instances, n, options, plans);
+    if (st != RB_OK) return st;
+    Batch bt;
+    st = make_batch(plans, bt);
+    if (st != RB_OK) return st;
+    for (int i = 0; i < n; ++i) {
+        st = rb_read_header((const char *)workspace + bt.base[i], &out[i], stream);
+        if (st != RB_OK) return st;
+    }
+    return RB_OK;
 }
 
 rb_status rb_read_header(const void *workspace, rb_header *out, void *stream)
@@ -269,12 +371,14 @@ rb_status rb_profile_read(rb_profile_stats *out)
         if (r.kind == 0) {
             out->project_ms += span(e[0], e[1]);
             out->bin_ms += span(e[1], e[2]);
-            out->raster_fwd_ms += span(e[2], e[3]);
-            out->reduce_ms += span(e[3], e[4]);
+            out->fg_ms += span(e[2], e[3]);
+            out->bg_ms += span(e[3], e[4]);
+            out->resolve_ms += span(e[4], e[5]);
             out->fwd_calls += 1;
         } else {
-            out->raster_bwd_ms += span(e[1], e[2]);
-            out->vertex_grad_ms += span(e[0], e[1]) + span(e[2], e[3]);
+            out->fg_bwd_ms += span(e[0], e[1]);
+            out->bg_bwd_ms += span(e[1], e[2]);
+            out->vertex_grad_ms += span(e[2], e[3]);
             out->bwd_calls += 1;
         }
     }

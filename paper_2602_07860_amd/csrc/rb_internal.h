@@ -3,6 +3,7 @@
 #pragma once
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include <hip/hip_runtime.h>
 
@@ -45,43 +46,41 @@ __host__ __device__ inline Chunk chunk_info(int c, int K, int S, int CPS)
     return ch;
 }
 
-// Workspace header as laid out on the device (first 256 bytes).
+// Per-instance workspace header as laid out on the device (first 256 bytes).
 struct DevHeader {
     int32_t error_bits;
     int32_t reserved;
     int64_t list_entries;
     int64_t list_capacity;
-    int64_t ntasks;                  // background tasks of the current forward
-    unsigned long long task_ctr[2];  // next task (forward, backward)
-    int64_t pad[2];
+    int64_t ntasks;       // background tasks of the current forward
+    int64_t pad[4];
 };
 
-// Everything a launch needs, derived on the host from sizes and options.
-struct Plan {
-    // problem
-    int V, F, C, S, K, W, H;
-    float tanf, delta, dmax, halo;
-    float view[12];
-    int solver;
-    // tiling and sub-frame chunks
-    int tiles_x, tiles_y, ntiles;
-    int T;          // chunk length (template)
-    int CPS;        // chunks per segment
-    int NC;         // chunks = S * CPS
-    int SL;         // background list entries per task
-    int NS;         // per (pixel, sub-frame) value slots: colour, or log-sum and zero count
-    int64_t cap;    // list capacity (entries)
-    int64_t ntct;   // (chunk, tile) pairs = NC * ntiles
-    int64_t maxtasks;
-    // workspace byte offsets
-    size_t o_hdr, o_kf, o_kfz, o_cnt, o_off, o_cur, o_bsum, o_list, o_vis_id, o_pix, o_tsl, o_toff, o_tbsum,
-        o_tasks, o_gkf, total;
-    int64_t ncounts;  // 2 * NC * ntiles
-    int64_t nblocks_scan, nblocks_tscan;
+// Batch-level device state, after the instance workspaces.
+struct BatchHeader {
+    unsigned long long bwd_task_ctr;   // next background adjoint task (all instances)
+    int64_t pad[3];
 };
 
-// Pointers into a workspace for one call.
-struct Bufs {
+struct ViewArgs {
+    float m[12];
+    float tanf;
+};
+
+// One instance as the kernels see it (device memory, written at the start of
+// every call).  Every kernel covers all instances of a batch; b_* is the first
+// block of this instance in the launch of that kernel.
+struct Inst {
+    // caller's arrays
+    const float *verts;
+    const int32_t *faces;
+    const float *attrs;
+    const float *model;
+    float *image;
+    const float *grad_image;
+    float *grad_verts;
+    float *grad_attrs;
+    // workspace
     DevHeader *hdr;
     double2 *kf;         // [S+1][V] keyframe (x, y), kept in double: edge-on (sliver)
                          // faces make barycentrics sensitive to 1e-8 position errors
@@ -98,23 +97,75 @@ struct Bufs {
     int64_t *tbsum;      // task scan block sums
     uint64_t *tasks;     // (chunk * ntiles + tile) << 32 | slice
     float *gkf;          // [S+1][V][2] keyframe gradient
+    // sizes
+    int V, F, C, S, K, W, H, tiles_x, tiles_y, ntiles;
+    int CPS, NC, SL, NS, nfb;
+    int ntct;            // (chunk, tile) pairs = NC * ntiles
+    int nblocks_scan, nblocks_tscan;
+    int64_t cap, maxtasks, ncounts;
+    float inv_w, inv_h, dmax, halo, neg_log2e_over_delta, inv_delta, invK;
+    ViewArgs vw;
+    // first block of this instance in each launch
+    int b_init, b_proj, b_bin, b_scan1, b_scan3, b_tscan1, b_tscan3, b_fg, b_res, b_bwdinit, b_vtx;
 };
 
-struct Inputs {
+// Host plan of one instance.
+struct Plan {
+    int V, F, C, S, K, W, H;
+    float tanf, delta, dmax, halo;
+    float view[12];
+    int solver;
+    int tiles_x, tiles_y, ntiles;
+    int T;          // chunk length (template)
+    int CPS;        // chunks per segment
+    int NC;         // chunks = S * CPS
+    int SL;         // background list entries per task
+    int NS;         // per (pixel, sub-frame) value slots: colour, or log-sum and zero count
+    int nfb;        // binning blocks per chunk
+    int64_t cap;    // list capacity (entries)
+    int64_t ntct;   // (chunk, tile) pairs = NC * ntiles
+    int64_t maxtasks;
+    // workspace byte offsets (from the instance's base)
+    size_t o_hdr, o_kf, o_kfz, o_cnt, o_off, o_cur, o_bsum, o_list, o_vis_id, o_pix, o_tsl, o_toff, o_tbsum,
+        o_tasks, o_gkf, total;
+    int64_t ncounts;  // 2 * NC * ntiles
+    int64_t nblocks_scan, nblocks_tscan;
+};
+
+// Block counts of each launch over a batch.
+struct Grids {
+    int64_t init, proj, bin, scan1, scan3, tscan1, tscan3, fg, res, bwdinit, vtx;
+};
+
+// Host plan of a batch: per-instance plans and where each instance's
+// workspace starts; the table of Inst and the batch header follow them.
+struct Batch {
+    int n, T, solver;
+    std::vector<Plan> plans;
+    std::vector<size_t> base;
+    Grids g;
+    size_t o_table, o_tprefix, o_bhdr, total;
+};
+
+// Per-instance arrays the host entry points pass in.
+struct Io {
     const float *verts;
     const int32_t *faces;
     const float *attrs;
     const float *model;
+    float *image;
+    const float *grad_image;
+    float *grad_verts;
+    float *grad_attrs;
 };
 
 // Optional phase events (benchmark timing); null entries are skipped.
 struct PhaseEvents {
-    hipEvent_t ev[5];
+    hipEvent_t ev[6];
 };
 
-hipError_t launch_forward(const Plan &p, const Inputs &in, const Bufs &b, float *image, hipStream_t st,
-                          const PhaseEvents *pe);
-hipError_t launch_backward(const Plan &p, const Inputs &in, const Bufs &b, const float *grad_image,
-                           float *grad_verts, float *grad_attrs, hipStream_t st, const PhaseEvents *pe);
+hipError_t launch_forward(const Batch &bt, const std::vector<Io> &io, void *ws, hipStream_t st, const PhaseEvents *pe);
+hipError_t launch_backward(const Batch &bt, const std::vector<Io> &io, void *ws, hipStream_t st,
+                           const PhaseEvents *pe);
 
 }  // namespace rb

@@ -31,6 +31,7 @@
 //     rest-vertex gradients.
 #include <cfloat>
 #include <climits>
+#include <cstring>
 
 #include "rb_internal.h"
 
@@ -75,55 +76,89 @@ __device__ __forceinline__ float one_minus_exp_neg(float x, float A)
     return 1.0f - A;
 }
 
+// ------------------------------------------------------------ instances
+//
+// Every kernel covers all instances of a batch (a single render is a batch
+// of one).  Instance i owns the blocks [b_X(i), b_X(i+1)) of launch X; a block
+// finds its instance by binary search over the (ascending) starts.
+
+template <int Inst::*B>
+__device__ __forceinline__ int inst_of(const Inst *__restrict__ tab, int n, int block)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab[mid].*B <= block)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// copies a chunk of the instance table (passed by value) to device memory
+constexpr int kTabChunk = 8;
+struct TabChunk {
+    int first, count;
+    Inst v[kTabChunk];
+};
+static_assert(sizeof(TabChunk) <= 4096, "kernel argument size");
+
+__global__ void k_set_table(TabChunk c, Inst *tab)
+{
+    // plain word copies, one struct per block
+    const int i = blockIdx.x;
+    if (i >= c.count) return;
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(&c.v[i]);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(&tab[c.first + i]);
+    for (int w = threadIdx.x; w < (int)(sizeof(Inst) / 4); w += blockDim.x) dst[w] = src[w];
+}
+
 // ------------------------------------------------------------ small kernels
 
-__global__ void k_init(DevHeader *hdr, int64_t cap, int32_t *cnt, int32_t *cur, int64_t n)
+__global__ void k_init(const Inst *__restrict__ tab, int n)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const Inst &a = tab[inst_of<&Inst::b_init>(tab, n, blockIdx.x)];
+    const int64_t i = (int64_t)(blockIdx.x - a.b_init) * blockDim.x + threadIdx.x;
     if (i == 0) {
-        hdr->error_bits = 0;
-        hdr->reserved = 0;
-        hdr->list_entries = 0;
-        hdr->list_capacity = cap;
-        hdr->ntasks = 0;
-        hdr->task_ctr[0] = 0;
-        hdr->task_ctr[1] = 0;
+        a.hdr->error_bits = 0;
+        a.hdr->reserved = 0;
+        a.hdr->list_entries = 0;
+        a.hdr->list_capacity = a.cap;
+        a.hdr->ntasks = 0;
     }
-    for (; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        cnt[i] = 0;
-        cur[i] = 0;
+    if (i < a.ncounts) {
+        a.cnt[i] = 0;
+        a.cur[i] = 0;
     }
 }
 
-// clear the keyframe and attribute gradients and the backward task counter
-__global__ void k_bwd_init(float *gkf, int64_t n1, float *gattr, int64_t n2, DevHeader *hdr)
+// clear the keyframe and attribute gradients (and, once, the batch's
+// background-adjoint task counter)
+__global__ void k_bwd_init(const Inst *__restrict__ tab, int n, BatchHeader *bh)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) hdr->task_ctr[1] = 0;
-    for (; i < n1 + n2; i += (int64_t)gridDim.x * blockDim.x) {
-        if (i < n1)
-            gkf[i] = 0.0f;
-        else
-            gattr[i - n1] = 0.0f;
-    }
+    const Inst &a = tab[inst_of<&Inst::b_bwdinit>(tab, n, blockIdx.x)];
+    if (blockIdx.x == 0 && threadIdx.x == 0) bh->bwd_task_ctr = 0;
+    const int64_t i = (int64_t)(blockIdx.x - a.b_bwdinit) * blockDim.x + threadIdx.x;
+    const int64_t n1 = (int64_t)(a.S + 1) * a.V * 2, n2 = (int64_t)a.V * a.C;
+    if (i < n1)
+        a.gkf[i] = 0.0f;
+    else if (i < n1 + n2)
+        a.grad_attrs[i - n1] = 0.0f;
 }
-
-struct ViewArgs {
-    float m[12];
-    float tanf;
-};
 
 // Keyframe projection (App. I): X = view (M_s P0), x = X.x/(X.z tan), y = X.y/(X.z tan)
-__global__ void k_project(const float *__restrict__ verts, const float *__restrict__ model,
-                          const int32_t *__restrict__ faces, int V, int S, int F, ViewArgs vw,
-                          double2 *__restrict__ kf, float *__restrict__ kfz, DevHeader *hdr)
+__global__ void k_project(const Inst *__restrict__ tab, int n)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t nkf = (int64_t)(S + 1) * V;
+    const Inst &a = tab[inst_of<&Inst::b_proj>(tab, n, blockIdx.x)];
+    const int64_t i = (int64_t)(blockIdx.x - a.b_proj) * blockDim.x + threadIdx.x;
+    const int V = a.V, F = a.F;
+    const int64_t nkf = (int64_t)(a.S + 1) * V;
+    const ViewArgs &vw = a.vw;
     if (i < nkf) {
         int s = (int)(i / V), v = (int)(i - (int64_t)s * V);
-        const float *m = model + (size_t)s * 12;
-        double p0 = verts[3 * v], p1 = verts[3 * v + 1], p2 = verts[3 * v + 2];
+        const float *m = a.model + (size_t)s * 12;
+        double p0 = a.verts[3 * v], p1 = a.verts[3 * v + 1], p2 = a.verts[3 * v + 2];
         double w[3], c[3];
 #pragma unroll
         for (int r = 0; r < 3; ++r)
@@ -134,27 +169,15 @@ __global__ void k_project(const float *__restrict__ verts, const float *__restri
                    (double)vw.m[4 * r + 3];
         double t = (double)vw.tanf;
         double x = c[0] / (c[2] * t), y = c[1] / (c[2] * t);
-        kf[i] = make_double2(x, y);
-        kfz[i] = (float)c[2];
-        if (!(c[2] > 1e-6)) atomicOr(&hdr->error_bits, kHdrBehind);
+        a.kf[i] = make_double2(x, y);
+        a.kfz[i] = (float)c[2];
+        if (!(c[2] > 1e-6)) atomicOr(&a.hdr->error_bits, kHdrBehind);
     } else if (i < nkf + F) {
         int f = (int)(i - nkf);
-        int a = faces[3 * f], b = faces[3 * f + 1], c = faces[3 * f + 2];
-        if (a < 0 || a >= V || b < 0 || b >= V || c < 0 || c >= V) atomicOr(&hdr->error_bits, kHdrFaceRange);
+        int q0 = a.faces[3 * f], q1 = a.faces[3 * f + 1], q2 = a.faces[3 * f + 2];
+        if (q0 < 0 || q0 >= V || q1 < 0 || q1 >= V || q2 < 0 || q2 >= V) atomicOr(&a.hdr->error_bits, kHdrFaceRange);
     }
 }
-
-struct BinArgs {
-    const int32_t *faces;
-    const double2 *kf;
-    int32_t *cnt;
-    const int64_t *off;
-    int32_t *cur;
-    uint32_t *list;
-    int V, F, S, K, W, H, tiles_x, tiles_y, ntiles, CPS, NC;
-    float halo;
-    int64_t cap;
-};
 
 __device__ __forceinline__ void pixel_range(float lo, float hi, float scale, float off, int n, int &a, int &b)
 {
@@ -170,7 +193,7 @@ __device__ __forceinline__ void pixel_range(float lo, float hi, float scale, flo
 
 // Tile ranges of one face at one sub-frame: foreground (exact box) and
 // background (box grown by halo).  Empty ranges come back with lo > hi.
-__device__ __forceinline__ void face_tiles(const float x[3], const float y[3], const BinArgs &a, float grow,
+__device__ __forceinline__ void face_tiles(const float x[3], const float y[3], const Inst &a, float grow,
                                            int &tx0, int &tx1, int &ty0, int &ty1)
 {
     float xmin = fminf(x[0], fminf(x[1], x[2])) - grow, xmax = fmaxf(x[0], fmaxf(x[1], x[2])) + grow;
@@ -209,7 +232,7 @@ struct FaceTiles {
 };
 
 template <int T>
-__device__ __forceinline__ bool face_chunk_tiles(const BinArgs &a, int f, const Chunk &ch, int ftx0[T], int ftx1[T],
+__device__ __forceinline__ bool face_chunk_tiles(const Inst &a, int f, const Chunk &ch, int ftx0[T], int ftx1[T],
                                                  int fty0[T], int fty1[T], int btx0[T], int btx1[T], int bty0[T],
                                                  int bty1[T], FaceTiles &u)
 {
@@ -255,14 +278,16 @@ __device__ __forceinline__ bool face_chunk_tiles(const BinArgs &a, int f, const 
 }
 
 template <int T>
-__global__ __launch_bounds__(kBinThreads) void k_bin(BinArgs a, int pass)
+__global__ __launch_bounds__(kBinThreads) void k_bin(const Inst *__restrict__ tab, int n, int pass)
 {
     __shared__ int lcnt[kBinWin];
     __shared__ int64_t lbase[kBinWin];
     __shared__ int win[4];
-    const int nfb = (a.F + kBinThreads - 1) / kBinThreads;
-    const int c = blockIdx.x / nfb;
-    const int f = (blockIdx.x - c * nfb) * kBinThreads + threadIdx.x;
+    const Inst &a = tab[inst_of<&Inst::b_bin>(tab, n, blockIdx.x)];
+    const int nfb = a.nfb;
+    const int lb = blockIdx.x - a.b_bin;
+    const int c = lb / nfb;
+    const int f = (lb - c * nfb) * kBinThreads + threadIdx.x;
     const Chunk ch = chunk_info(c, a.K, a.S, a.CPS);
     if (ch.n <= 0) return;   // block-uniform
     int ftx0[T], ftx1[T], fty0[T], fty1[T], btx0[T], btx1[T], bty0[T], bty1[T];
@@ -387,52 +412,94 @@ __device__ int64_t block_exclusive_scan(int64_t x, int64_t *total)
     return r;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan1(const int32_t *__restrict__ cnt, int64_t *__restrict__ off,
-                                                        int64_t *__restrict__ bsum, int64_t n)
+// which = 0: bin-list counts (cnt -> off, total to the header's list_entries,
+// overflow against the capacity); which = 1: background task counts (tsl ->
+// toff, total to the header's ntasks)
+struct ScanIo {
+    const int32_t *cnt;
+    int64_t *off, *bsum, *total;
+    int64_t n, nb;
+    int first1, first3;
+};
+
+__device__ __forceinline__ ScanIo scan_io(const Inst &a, int which)
+{
+    ScanIo r;
+    if (which == 0) {
+        r.cnt = a.cnt;
+        r.off = a.off;
+        r.bsum = a.bsum;
+        r.total = &a.hdr->list_entries;
+        r.n = a.ncounts;
+        r.nb = a.nblocks_scan;
+        r.first1 = a.b_scan1;
+        r.first3 = a.b_scan3;
+    } else {
+        r.cnt = a.tsl;
+        r.off = a.toff;
+        r.bsum = a.tbsum;
+        r.total = &a.hdr->ntasks;
+        r.n = a.ntct;
+        r.nb = a.nblocks_tscan;
+        r.first1 = a.b_tscan1;
+        r.first3 = a.b_tscan3;
+    }
+    return r;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan1(const Inst *__restrict__ tab, int n, int which)
 {
     __shared__ int64_t tot;
-    int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanPer;
+    const Inst &a = which == 0 ? tab[inst_of<&Inst::b_scan1>(tab, n, blockIdx.x)]
+                               : tab[inst_of<&Inst::b_tscan1>(tab, n, blockIdx.x)];
+    const ScanIo io = scan_io(a, which);
+    const int blk = blockIdx.x - io.first1;
+    int64_t base = (int64_t)blk * kScanBlock + (int64_t)threadIdx.x * kScanPer;
     int64_t v[kScanPer];
     int64_t s = 0;
 #pragma unroll
     for (int q = 0; q < kScanPer; ++q) {
-        v[q] = base + q < n ? cnt[base + q] : 0;
+        v[q] = base + q < io.n ? io.cnt[base + q] : 0;
         s += v[q];
     }
     int64_t ex = block_exclusive_scan(s, &tot);
 #pragma unroll
     for (int q = 0; q < kScanPer; ++q) {
-        if (base + q < n) off[base + q] = ex;
+        if (base + q < io.n) io.off[base + q] = ex;
         ex += v[q];
     }
-    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+    if (threadIdx.x == 0) io.bsum[blk] = tot;
 }
 
-// block sums -> block offsets; the grand total goes to *total, and the error
-// bit is raised in *err (if given) when it exceeds cap
-__global__ __launch_bounds__(kScanThreads) void k_scan2(int64_t *__restrict__ bsum, int64_t nb, int64_t *total,
-                                                        int32_t *err, int64_t cap)
+// block sums -> block offsets, one block per instance; the grand total goes
+// to the header (bin lists: overflow bit when it exceeds the capacity)
+__global__ __launch_bounds__(kScanThreads) void k_scan2(const Inst *__restrict__ tab, int which)
 {
     __shared__ int64_t tot;
+    const Inst &a = tab[blockIdx.x];
+    const ScanIo io = scan_io(a, which);
     int64_t carry = 0;
-    for (int64_t b0 = 0; b0 < nb; b0 += kScanThreads) {
+    for (int64_t b0 = 0; b0 < io.nb; b0 += kScanThreads) {
         int64_t i = b0 + threadIdx.x;
-        int64_t x = i < nb ? bsum[i] : 0;
+        int64_t x = i < io.nb ? io.bsum[i] : 0;
         int64_t ex = block_exclusive_scan(x, &tot);
-        if (i < nb) bsum[i] = ex + carry;
+        if (i < io.nb) io.bsum[i] = ex + carry;
         carry += tot;
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        *total = carry;
-        if (err && carry > cap) atomicOr(err, kHdrOverflow);
+        *io.total = carry;
+        if (which == 0 && carry > a.cap) atomicOr(&a.hdr->error_bits, kHdrOverflow);
     }
 }
 
-__global__ void k_scan3(int64_t *__restrict__ off, const int64_t *__restrict__ bsum, int64_t n)
+__global__ void k_scan3(const Inst *__restrict__ tab, int n, int which)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) off[i] += bsum[i / kScanBlock];
+    const Inst &a = which == 0 ? tab[inst_of<&Inst::b_scan3>(tab, n, blockIdx.x)]
+                               : tab[inst_of<&Inst::b_tscan3>(tab, n, blockIdx.x)];
+    const ScanIo io = scan_io(a, which);
+    const int64_t i = (int64_t)(blockIdx.x - io.first3) * blockDim.x + threadIdx.x;
+    if (i < io.n) io.off[i] += io.bsum[i / kScanBlock];
 }
 
 // ----------------------------------------------------------------- raster
@@ -475,24 +542,6 @@ __global__ void k_scan3(int64_t *__restrict__ off, const int64_t *__restrict__ b
 // as the forward.  Per-entry LDS gradient slots collect the items'
 // contributions and are added to global memory with one atomic per non-zero
 // value and batch.
-
-struct RasterArgs {
-    const double2 *kf;
-    const float *kfz;
-    const int32_t *faces;
-    const float *attrs;
-    const int32_t *cnt;
-    const int64_t *off;
-    const uint32_t *list;
-    int32_t *vis_id;
-    float *pix;
-    int32_t *tsl;
-    const uint64_t *tasks;
-    DevHeader *hdr;
-    int64_t maxtasks;
-    int V, F, C, S, K, W, H, tiles_x, ntiles, CPS, NC, SL, NS;
-    float inv_w, inv_h, dmax, halo, neg_log2e_over_delta, inv_delta;
-};
 
 constexpr int NCH = RB_MAX_CHANNELS;
 constexpr int NB = 32;              // list entries staged per batch
@@ -541,13 +590,13 @@ __device__ __forceinline__ void lds_sync()
 }
 
 // vertex indices of face f (clamped; out-of-range indices are reported by k_project)
-__device__ __forceinline__ void face_verts(const RasterArgs &a, int f, int vid[3])
+__device__ __forceinline__ void face_verts(const Inst &a, int f, int vid[3])
 {
 #pragma unroll
     for (int q = 0; q < 3; ++q) vid[q] = clampi(a.faces[3 * f + q], 0, a.V - 1);
 }
 
-__device__ __forceinline__ void stage_rec(const RasterArgs &a, int f, const int vid[3], int s, double ua, double va,
+__device__ __forceinline__ void stage_rec(const Inst &a, int f, const int vid[3], int s, double ua, double va,
                                           float tc, int kind, FaceRec &r)
 {
     r.f = f;
@@ -774,7 +823,7 @@ struct TileCtx {
     Chunk ck;
 };
 
-__device__ __forceinline__ void tile_ctx(const RasterArgs &a, int ct, TileCtx &g)
+__device__ __forceinline__ void tile_ctx(const Inst &a, int ct, TileCtx &g)
 {
     const int lane = threadIdx.x & 63;
     g.c = ct / a.ntiles;
@@ -792,7 +841,7 @@ __device__ __forceinline__ void tile_ctx(const RasterArgs &a, int ct, TileCtx &g
 
 // local time of sub-frame j of a chunk and whether eq 13 takes the segment's
 // end keyframe (tau > 1/2, decided in integers)
-__device__ __forceinline__ float chunk_tau(const RasterArgs &a, const Chunk &ch, int j, int &X)
+__device__ __forceinline__ float chunk_tau(const Inst &a, const Chunk &ch, int j, int &X)
 {
     const int rem = (ch.k0 + j) * a.S - ch.s * (a.K - 1);
     X = 2 * rem > a.K - 1 ? 1 : 0;
@@ -800,7 +849,7 @@ __device__ __forceinline__ float chunk_tau(const RasterArgs &a, const Chunk &ch,
 }
 
 template <int T>
-__device__ __forceinline__ void chunk_taus(const RasterArgs &a, const Chunk &ch, float tau[T], uint32_t &xbits)
+__device__ __forceinline__ void chunk_taus(const Inst &a, const Chunk &ch, float tau[T], uint32_t &xbits)
 {
     xbits = 0;
 #pragma unroll
@@ -823,11 +872,11 @@ __device__ __forceinline__ float chunk_centre(const float tau[T], int n)
 }
 
 // record index of pixel lane, sub-frame k of a tile
-__device__ __forceinline__ size_t vis_index(const RasterArgs &a, int tile, int k, int lane)
+__device__ __forceinline__ size_t vis_index(const Inst &a, int tile, int k, int lane)
 {
     return ((size_t)tile * a.K + k) * kWave + lane;
 }
-__device__ __forceinline__ size_t pix_index(const RasterArgs &a, int tile, int k, int slot, int lane)
+__device__ __forceinline__ size_t pix_index(const Inst &a, int tile, int k, int slot, int lane)
 {
     return (((size_t)tile * a.K + k) * a.NS + slot) * kWave + lane;
 }
@@ -937,7 +986,7 @@ struct Pref {
     int v[3];
 };
 
-__device__ __forceinline__ Pref prefetch(const RasterArgs &a, int64_t first, int nb)
+__device__ __forceinline__ Pref prefetch(const Inst &a, int64_t first, int nb)
 {
     const int lane = threadIdx.x & 63;
     Pref pf;
@@ -956,7 +1005,7 @@ __device__ __forceinline__ Pref prefetch(const RasterArgs &a, int64_t first, int
 // the lane's entry's item count and first item.  Optionally also stages the
 // vertex attributes (at) and vertex indices (vids).
 template <int T>
-__device__ __forceinline__ int stage_items(const RasterArgs &a, ItemShared<T> &sh, const Pref &pf, int nb, int s,
+__device__ __forceinline__ int stage_items(const Inst &a, ItemShared<T> &sh, const Pref &pf, int nb, int s,
                                            const TileCtx &g, float tc, const float tau[T], int kind, float grow,
                                            const uint64_t allow[T], float (*at)[NB], int (*vids)[3], int &cnt,
                                            int &pre)
@@ -1059,7 +1108,7 @@ struct FgShared {
 
 // foreground item: coverage (eqs 1-3 / 8) and depth test (eq 9) per sub-frame
 template <int T, int SOLVER>
-__device__ __forceinline__ void fg_item(const RasterArgs &a, FgShared<T> &sh, int e, int p, const float tau[T],
+__device__ __forceinline__ void fg_item(const Inst &a, FgShared<T> &sh, int e, int p, const float tau[T],
                                         float tc)
 {
     const LdsRec r = lds_rec(sh.it, e);
@@ -1103,7 +1152,7 @@ __device__ __forceinline__ void shade(const R &r, const A &at, float tc, float t
 
 // the winner's record is no longer staged: gather it
 template <int SOLVER>
-__device__ __forceinline__ void shade_gather(const RasterArgs &a, int f, int s, const TileCtx &g, float tc, float tau,
+__device__ __forceinline__ void shade_gather(const Inst &a, int f, int s, const TileCtx &g, float tc, float tau,
                                              float rgb[NCH])
 {
     int vid[3];
@@ -1115,10 +1164,12 @@ __device__ __forceinline__ void shade_gather(const RasterArgs &a, int f, int s, 
 }
 
 template <int T, int SOLVER>
-__global__ __launch_bounds__(64) void k_fg(RasterArgs a)
+__global__ __launch_bounds__(64) void k_fg(const Inst *__restrict__ tab, int n)
 {
     __shared__ FgShared<T> sh;
-    const int ct = xcd_remap(blockIdx.x, gridDim.x);
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const Inst &a = tab[inst_of<&Inst::b_fg>(tab, n, lb)];
+    const int ct = lb - a.b_fg;
     const int lane = threadIdx.x & 63;
     TileCtx g;
     tile_ctx(a, ct, g);
@@ -1182,15 +1233,42 @@ __global__ __launch_bounds__(64) void k_fg(RasterArgs a)
 }
 
 // write the task list: tasks[toff[ct] + i] = (ct, i), i < tsl[ct]
-__global__ void k_tasks(const int32_t *__restrict__ tsl, const int64_t *__restrict__ toff, int64_t ntct,
-                        uint64_t *__restrict__ tasks, int64_t maxtasks)
+__global__ void k_tasks(const Inst *__restrict__ tab, int n)
 {
-    const int64_t ct = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (ct >= ntct) return;
-    const int n = tsl[ct];
-    const int64_t o = toff[ct];
-    for (int i = 0; i < n; ++i)
-        if (o + i < maxtasks) tasks[o + i] = ((uint64_t)ct << 32) | (uint32_t)i;
+    const Inst &a = tab[inst_of<&Inst::b_tscan3>(tab, n, blockIdx.x)];
+    const int64_t ct = (int64_t)(blockIdx.x - a.b_tscan3) * blockDim.x + threadIdx.x;
+    if (ct >= a.ntct) return;
+    const int m = a.tsl[ct];
+    const int64_t o = a.toff[ct];
+    for (int i = 0; i < m; ++i)
+        if (o + i < a.maxtasks) a.tasks[o + i] = ((uint64_t)ct << 32) | (uint32_t)i;
+}
+
+// first background task of every instance in the batch's task numbering
+__global__ void k_tprefix(const Inst *__restrict__ tab, int n, int64_t *__restrict__ tprefix)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int64_t s = 0;
+    for (int i = 0; i < n; ++i) {
+        tprefix[i] = s;
+        const Inst &a = tab[i];
+        if (!(a.hdr->error_bits & kHdrOverflow)) s += min(a.hdr->ntasks, a.maxtasks);
+    }
+    tprefix[n] = s;
+}
+
+// instance owning batch task t (tprefix ascending, t < tprefix[n])
+__device__ __forceinline__ int task_inst(const int64_t *__restrict__ tprefix, int n, int64_t t)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tprefix[mid] <= t)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
 }
 
 // --------------------------------------------------------- forward: k_bg
@@ -1204,7 +1282,7 @@ struct BgShared {
 
 // background item: eqs 10, 13-15, accumulated as log2(1 - A)
 template <int T, int SOLVER>
-__device__ __forceinline__ void bg_item_fwd(const RasterArgs &a, BgShared<T> &sh, int e, int p, const float tau[T],
+__device__ __forceinline__ void bg_item_fwd(const Inst &a, BgShared<T> &sh, int e, int p, const float tau[T],
                                             uint32_t xbits, float tc)
 {
     const LdsRec r = lds_rec(sh.it, e);
@@ -1231,13 +1309,15 @@ __device__ __forceinline__ void bg_item_fwd(const RasterArgs &a, BgShared<T> &sh
 }
 
 template <int T, int SOLVER>
-__global__ __launch_bounds__(64) void k_bg(RasterArgs a)
+__global__ __launch_bounds__(64) void k_bg(const Inst *__restrict__ tab, int n, const int64_t *__restrict__ tprefix)
 {
     __shared__ BgShared<T> sh;
     const int lane = threadIdx.x & 63;
-    if (a.hdr->error_bits & kHdrOverflow) return;
-    const int64_t ntasks = min(a.hdr->ntasks, a.maxtasks);
-    for (int64_t t = blockIdx.x; t < ntasks; t += gridDim.x) {
+    const int64_t ntasks = tprefix[n];
+    for (int64_t tb = blockIdx.x; tb < ntasks; tb += gridDim.x) {
+        const int ii = task_inst(tprefix, n, tb);
+        const Inst &a = tab[ii];
+        const int64_t t = tb - tprefix[ii];
         const uint64_t task = a.tasks[t];
         const int ct = (int)(task >> 32);
         const int slice = (int)(uint32_t)task;
@@ -1288,10 +1368,12 @@ __global__ __launch_bounds__(64) void k_bg(RasterArgs a)
 
 // image = mean over the K sub-frames of the winner's colour (premultiplied,
 // alpha 1) or, where uncovered, alpha = 1 - prod (1 - A) (eq 15)
-__global__ __launch_bounds__(64) void k_resolve(RasterArgs a, float *__restrict__ image)
+__global__ __launch_bounds__(64) void k_resolve(const Inst *__restrict__ tab, int n)
 {
+    const Inst &a = tab[inst_of<&Inst::b_res>(tab, n, blockIdx.x)];
+    float *__restrict__ image = a.image;
     const int lane = threadIdx.x & 63;
-    const int tile = blockIdx.x;
+    const int tile = blockIdx.x - a.b_res;
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
     const int px = tx * kTile + (lane & 7), py = ty * kTile + (lane >> 3);
     if (px >= a.W || py >= a.H) return;
@@ -1322,12 +1404,6 @@ __global__ __launch_bounds__(64) void k_resolve(RasterArgs a, float *__restrict_
 
 // ---------------------------------------------------------------- adjoint
 
-struct GradArgs {
-    const float *grad_image;
-    float *gkf;
-    float *gattr;
-    float invK;
-};
 
 __device__ __forceinline__ int hash_face(int f) { return (int)(((uint32_t)f * 2654435761u) >> 25); }
 
@@ -1404,7 +1480,7 @@ __device__ __forceinline__ void vt_add(VTab<NV> &vt, int slot, int k, float v)
 
 // Add the table to the keyframe (and attribute) gradients and clear it.
 template <int NV>
-__device__ __forceinline__ void vt_flush(VTab<NV> &vt, int s, const RasterArgs &a, const GradArgs &ga)
+__device__ __forceinline__ void vt_flush(VTab<NV> &vt, int s, const Inst &a)
 {
     const int lane = threadIdx.x & 63;
     lds_sync();
@@ -1414,13 +1490,13 @@ __device__ __forceinline__ void vt_flush(VTab<NV> &vt, int s, const RasterArgs &
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const float g = vt.g[k][i];
-            if (g != 0.0f) unsafeAtomicAdd(ga.gkf + ((size_t)(s + (k >> 1)) * a.V + v) * 2 + (k & 1), g);
+            if (g != 0.0f) unsafeAtomicAdd(a.gkf + ((size_t)(s + (k >> 1)) * a.V + v) * 2 + (k & 1), g);
             vt.g[k][i] = 0.0f;
         }
 #pragma unroll
         for (int c = 0; c < NV - 4; ++c) {
             const float g = vt.g[4 + c][i];
-            if (g != 0.0f && c < a.C) unsafeAtomicAdd(ga.gattr + (size_t)v * a.C + c, g);
+            if (g != 0.0f && c < a.C) unsafeAtomicAdd(a.grad_attrs + (size_t)v * a.C + c, g);
             vt.g[4 + c][i] = 0.0f;
         }
         vt.key[i] = -1;
@@ -1446,7 +1522,7 @@ struct FgBwdShared {
 // colour = sum_i w_i c_i, dL/dw through the static solve (dw = -F^-1 dF w),
 // dL/dc_i = w_i dL/dcolour.
 template <int T, int SOLVER>
-__device__ __forceinline__ void fg_item_bwd(const RasterArgs &a, FgBwdShared<T> &sh, int e, int p, float tau, float tc)
+__device__ __forceinline__ void fg_item_bwd(const Inst &a, FgBwdShared<T> &sh, int e, int p, float tau, float tc)
 {
     const LdsRec r = lds_rec(sh.it, e);
     const float du = pix_du(p, a.inv_w), dv = pix_dv(p, a.inv_h);
@@ -1489,10 +1565,12 @@ __device__ __forceinline__ void fg_item_bwd(const RasterArgs &a, FgBwdShared<T> 
 }
 
 template <int T, int SOLVER>
-__global__ __launch_bounds__(64) void k_fg_bwd(RasterArgs a, GradArgs ga)
+__global__ __launch_bounds__(64) void k_fg_bwd(const Inst *__restrict__ tab, int n)
 {
     __shared__ FgBwdShared<T> sh;
-    const int ct = xcd_remap(blockIdx.x, gridDim.x);
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const Inst &a = tab[inst_of<&Inst::b_fg>(tab, n, lb)];
+    const int ct = lb - a.b_fg;
     const int lane = threadIdx.x & 63;
     if (a.hdr->error_bits & kHdrOverflow) return;
     TileCtx g;
@@ -1503,7 +1581,7 @@ __global__ __launch_bounds__(64) void k_fg_bwd(RasterArgs a, GradArgs ga)
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) {
         float v = 0.0f;
-        if (g.inimg && ch < a.C) v = ga.grad_image[((size_t)ch * a.H + g.py) * a.W + g.px] * ga.invK;
+        if (g.inimg && ch < a.C) v = a.grad_image[((size_t)ch * a.H + g.py) * a.W + g.px] * a.invK;
         sh.gI[ch][lane] = v;
         gcol = gcol || v != 0.0f;
     }
@@ -1532,7 +1610,7 @@ __global__ __launch_bounds__(64) void k_fg_bwd(RasterArgs a, GradArgs ga)
         const Pref cur = pf;
         if (base + NB < n_e) pf = prefetch(a, beg + base + NB, min(NB, n_e - base - NB));
         if (used + 3 * nb > kVTLoad) {
-            vt_flush(sh.vt, ck.s, a, ga);
+            vt_flush(sh.vt, ck.s, a);
             used = 0;
         }
         lds_sync();
@@ -1595,7 +1673,7 @@ __global__ __launch_bounds__(64) void k_fg_bwd(RasterArgs a, GradArgs ga)
         lds_sync();
         if (hb >= 0) sh.hkey[hb] = -1;
     }
-    vt_flush(sh.vt, ck.s, a, ga);
+    vt_flush(sh.vt, ck.s, a);
 }
 
 // ------------------------------------------------------- backward: k_bg_bwd
@@ -1614,7 +1692,7 @@ struct BgBwdShared {
 // dA/dd = -A/delta, then the chain through d = |p - p*|^2, the closest point
 // (edge parameter where unclamped), q = F(X) w and w(tau) (dw = -F^-1 dF w).
 template <int T, int SOLVER>
-__device__ __forceinline__ void bg_item_bwd(const RasterArgs &a, BgBwdShared<T> &sh, int e, int p,
+__device__ __forceinline__ void bg_item_bwd(const Inst &a, BgBwdShared<T> &sh, int e, int p,
                                             const float tau[T], uint32_t xbits, float tc)
 {
     const LdsRec r = lds_rec(sh.it, e);
@@ -1718,25 +1796,28 @@ __device__ __forceinline__ void bg_item_bwd(const RasterArgs &a, BgBwdShared<T> 
 }
 
 template <int T, int SOLVER>
-__global__ __launch_bounds__(64) void k_bg_bwd(RasterArgs a, GradArgs ga)
+__global__ __launch_bounds__(64) void k_bg_bwd(const Inst *__restrict__ tab, int n,
+                                                const int64_t *__restrict__ tprefix, BatchHeader *bh)
 {
     __shared__ BgBwdShared<T> sh;
     const int lane = threadIdx.x & 63;
-    if (a.hdr->error_bits & kHdrOverflow) return;
     vt_clear(sh.vt);
     // tasks vary more in cost here than in the forward (pixels without
     // gradient drop out), so waves take them from a counter
-    const int64_t ntasks = min(a.hdr->ntasks, a.maxtasks);
+    const int64_t ntasks = tprefix[n];
     for (;;) {
-        const int64_t t = next_task(&a.hdr->task_ctr[1]);
-        if (t >= ntasks) break;
+        const int64_t tb = next_task(&bh->bwd_task_ctr);
+        if (tb >= ntasks) break;
+        const int ii = task_inst(tprefix, n, tb);
+        const Inst &a = tab[ii];
+        const int64_t t = tb - tprefix[ii];
         const uint64_t task = a.tasks[t];
         const int ct = (int)(task >> 32);
         const int slice = (int)(uint32_t)task;
         TileCtx g;
         tile_ctx(a, ct, g);
         const Chunk &ck = g.ck;
-        const float gal = g.inimg ? ga.grad_image[((size_t)a.C * a.H + g.py) * a.W + g.px] * ga.invK : 0.0f;
+        const float gal = g.inimg ? a.grad_image[((size_t)a.C * a.H + g.py) * a.W + g.px] * a.invK : 0.0f;
         float tau[T];
         uint32_t xbits;
         chunk_taus<T>(a, ck, tau, xbits);
@@ -1775,7 +1856,7 @@ __global__ __launch_bounds__(64) void k_bg_bwd(RasterArgs a, GradArgs ga)
             const Pref cur = pf;
             if (base + NB < e1) pf = prefetch(a, beg + base + NB, min(NB, e1 - base - NB));
             if (used + 3 * nb > kVTLoad) {
-                vt_flush(sh.vt, ck.s, a, ga);
+                vt_flush(sh.vt, ck.s, a);
                 used = 0;
             }
             int cnt, pre;
@@ -1785,16 +1866,22 @@ __global__ __launch_bounds__(64) void k_bg_bwd(RasterArgs a, GradArgs ga)
             for_items<T>(sh.it, total, cnt, pre,
                          [&](int e, int p) { bg_item_bwd<T, SOLVER>(a, sh, e, p, tau, xbits, tc); });
         }
-        if (used > 0) vt_flush(sh.vt, ck.s, a, ga);
+        if (used > 0) vt_flush(sh.vt, ck.s, a);
     }
 }
 
 // dL/dP0 = sum_s (d(x, y)_s / dP0)^T dL/d(x, y)_s through the projection and
 // the keyframe transform (App. I); camera depth carries no gradient.
-__global__ void k_kf_to_vertex(const float *__restrict__ verts, const float *__restrict__ model,
-                               const float *__restrict__ gkf, int V, int S, ViewArgs vw, float *__restrict__ grad_verts)
+__global__ void k_kf_to_vertex(const Inst *__restrict__ tab, int n)
 {
-    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    const Inst &a = tab[inst_of<&Inst::b_vtx>(tab, n, blockIdx.x)];
+    const int v = (blockIdx.x - a.b_vtx) * blockDim.x + threadIdx.x;
+    const int V = a.V, S = a.S;
+    const float *__restrict__ verts = a.verts;
+    const float *__restrict__ model = a.model;
+    const float *__restrict__ gkf = a.gkf;
+    float *__restrict__ grad_verts = a.grad_verts;
+    const ViewArgs &vw = a.vw;
     if (v >= V) return;
     const double p0 = verts[3 * v], p1 = verts[3 * v + 1], p2 = verts[3 * v + 2];
     const double t = (double)vw.tanf;
@@ -1826,12 +1913,10 @@ __global__ void k_kf_to_vertex(const float *__restrict__ verts, const float *__r
 
 // ---------------------------------------------------------------- launches
 
-static inline unsigned grid_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+static inline int64_t grid_for(int64_t n, int b) { return (n + b - 1) / b; }
 
 // Waves a persistent kernel keeps resident on the current device: its
-// occupancy (registers, LDS) times the compute units.  Each wave takes every
-// grid-th task, so launching exactly what fits avoids waves that start late
-// with a full share of tasks.
+// occupancy (registers, LDS) times the compute units.
 template <class K>
 static unsigned resident_waves(K kernel)
 {
@@ -1843,22 +1928,38 @@ static unsigned resident_waves(K kernel)
     return (unsigned)(cus * per_cu);
 }
 
-static RasterArgs raster_args(const Plan &p, const Inputs &in, const Bufs &b)
+static inline void mark(const PhaseEvents *pe, int i, hipStream_t st)
 {
-    RasterArgs a;
-    a.kf = b.kf;
-    a.kfz = b.kfz;
-    a.faces = in.faces;
-    a.attrs = in.attrs;
-    a.cnt = b.cnt;
-    a.off = b.off;
-    a.list = b.list;
-    a.vis_id = b.vis_id;
-    a.pix = b.pix;
-    a.tsl = b.tsl;
-    a.tasks = b.tasks;
-    a.hdr = b.hdr;
-    a.maxtasks = p.maxtasks;
+    if (pe && pe->ev[i]) (void)hipEventRecord(pe->ev[i], st);
+}
+
+static Inst make_inst(const Plan &p, const Io &io, char *base, const Grids &start)
+{
+    Inst a;
+    std::memset(&a, 0, sizeof(a));
+    a.verts = io.verts;
+    a.faces = io.faces;
+    a.attrs = io.attrs;
+    a.model = io.model;
+    a.image = io.image;
+    a.grad_image = io.grad_image;
+    a.grad_verts = io.grad_verts;
+    a.grad_attrs = io.grad_attrs;
+    a.hdr = (DevHeader *)(base + p.o_hdr);
+    a.kf = (double2 *)(base + p.o_kf);
+    a.kfz = (float *)(base + p.o_kfz);
+    a.cnt = (int32_t *)(base + p.o_cnt);
+    a.off = (int64_t *)(base + p.o_off);
+    a.cur = (int32_t *)(base + p.o_cur);
+    a.bsum = (int64_t *)(base + p.o_bsum);
+    a.list = (uint32_t *)(base + p.o_list);
+    a.vis_id = (int32_t *)(base + p.o_vis_id);
+    a.pix = (float *)(base + p.o_pix);
+    a.tsl = (int32_t *)(base + p.o_tsl);
+    a.toff = (int64_t *)(base + p.o_toff);
+    a.tbsum = (int64_t *)(base + p.o_tbsum);
+    a.tasks = (uint64_t *)(base + p.o_tasks);
+    a.gkf = (float *)(base + p.o_gkf);
     a.V = p.V;
     a.F = p.F;
     a.C = p.C;
@@ -1867,154 +1968,149 @@ static RasterArgs raster_args(const Plan &p, const Inputs &in, const Bufs &b)
     a.W = p.W;
     a.H = p.H;
     a.tiles_x = p.tiles_x;
+    a.tiles_y = p.tiles_y;
     a.ntiles = p.ntiles;
     a.CPS = p.CPS;
     a.NC = p.NC;
     a.SL = p.SL;
     a.NS = p.NS;
+    a.nfb = p.nfb;
+    a.ntct = (int)p.ntct;
+    a.nblocks_scan = (int)p.nblocks_scan;
+    a.nblocks_tscan = (int)p.nblocks_tscan;
+    a.cap = p.cap;
+    a.maxtasks = p.maxtasks;
+    a.ncounts = p.ncounts;
     a.inv_w = (float)(1.0 / (double)p.W);
     a.inv_h = (float)(1.0 / (double)p.H);
     a.dmax = p.dmax;
     a.halo = p.halo;
     a.neg_log2e_over_delta = (float)(-1.4426950408889634 / (double)p.delta);
     a.inv_delta = (float)(1.0 / (double)p.delta);
+    a.invK = 1.0f / (float)p.K;
+    for (int i = 0; i < 12; ++i) a.vw.m[i] = p.view[i];
+    a.vw.tanf = p.tanf;
+    a.b_init = (int)start.init;
+    a.b_proj = (int)start.proj;
+    a.b_bin = (int)start.bin;
+    a.b_scan1 = (int)start.scan1;
+    a.b_scan3 = (int)start.scan3;
+    a.b_tscan1 = (int)start.tscan1;
+    a.b_tscan3 = (int)start.tscan3;
+    a.b_fg = (int)start.fg;
+    a.b_res = (int)start.res;
+    a.b_bwdinit = (int)start.bwdinit;
+    a.b_vtx = (int)start.vtx;
     return a;
 }
 
-static inline void mark(const PhaseEvents *pe, int i, hipStream_t st)
+// Fill the device instance table (kernel arguments carry the values, so the
+// call stays a pure launch sequence) and return it.
+static const Inst *write_table(const Batch &bt, const std::vector<Io> &io, void *ws, hipStream_t st)
 {
-    if (pe && pe->ev[i]) (void)hipEventRecord(pe->ev[i], st);
-}
-
-template <int T>
-static void bin_T(const Plan &p, const Inputs &in, const Bufs &b, hipStream_t st)
-{
-    BinArgs ba;
-    ba.faces = in.faces;
-    ba.kf = b.kf;
-    ba.cnt = b.cnt;
-    ba.off = b.off;
-    ba.cur = b.cur;
-    ba.list = b.list;
-    ba.V = p.V;
-    ba.F = p.F;
-    ba.S = p.S;
-    ba.K = p.K;
-    ba.W = p.W;
-    ba.H = p.H;
-    ba.tiles_x = p.tiles_x;
-    ba.tiles_y = p.tiles_y;
-    ba.ntiles = p.ntiles;
-    ba.CPS = p.CPS;
-    ba.NC = p.NC;
-    ba.halo = p.halo;
-    ba.cap = p.cap;
-    const unsigned nbin = (unsigned)((int64_t)p.NC * grid_for(p.F, kBinThreads));
-    hipLaunchKernelGGL(k_bin<T>, dim3(nbin), dim3(kBinThreads), 0, st, ba, 0);
-    hipLaunchKernelGGL(k_scan1, dim3((unsigned)p.nblocks_scan), dim3(kScanThreads), 0, st, b.cnt, b.off, b.bsum,
-                       p.ncounts);
-    hipLaunchKernelGGL(k_scan2, dim3(1), dim3(kScanThreads), 0, st, b.bsum, p.nblocks_scan, &b.hdr->list_entries,
-                       &b.hdr->error_bits, p.cap);
-    hipLaunchKernelGGL(k_scan3, dim3(grid_for(p.ncounts, 256)), dim3(256), 0, st, b.off, b.bsum, p.ncounts);
-    hipLaunchKernelGGL(k_bin<T>, dim3(nbin), dim3(kBinThreads), 0, st, ba, 1);
+    char *w = (char *)ws;
+    Inst *tab = (Inst *)(w + bt.o_table);
+    Grids start{};
+    TabChunk c;
+    c.first = 0;
+    c.count = 0;
+    for (int i = 0; i < bt.n; ++i) {
+        const Plan &p = bt.plans[i];
+        c.v[c.count++] = make_inst(p, io[i], w + bt.base[i], start);
+        start.init += grid_for(p.ncounts, 256);
+        start.proj += grid_for((int64_t)(p.S + 1) * p.V + p.F, 256);
+        start.bin += (int64_t)p.NC * p.nfb;
+        start.scan1 += p.nblocks_scan;
+        start.scan3 += grid_for(p.ncounts, 256);
+        start.tscan1 += p.nblocks_tscan;
+        start.tscan3 += grid_for(p.ntct, 256);
+        start.fg += p.ntct;
+        start.res += p.ntiles;
+        start.bwdinit += grid_for((int64_t)(p.S + 1) * p.V * 2 + (int64_t)p.V * p.C, 256);
+        start.vtx += grid_for(p.V, 256);
+        if (c.count == kTabChunk || i == bt.n - 1) {
+            hipLaunchKernelGGL(k_set_table, dim3(c.count), dim3(64), 0, st, c, tab);
+            c.first = i + 1;
+            c.count = 0;
+        }
+    }
+    return tab;
 }
 
 template <int T, int SOLVER>
-static void raster_fwd_T(const Plan &p, const RasterArgs &ra, const Bufs &b, hipStream_t st)
+static void forward_T(const Batch &bt, const Inst *tab, void *ws, hipStream_t st, const PhaseEvents *pe)
 {
-    hipLaunchKernelGGL((k_fg<T, SOLVER>), dim3((unsigned)p.ntct), dim3(kWave), 0, st, ra);
-    hipLaunchKernelGGL(k_scan1, dim3((unsigned)p.nblocks_tscan), dim3(kScanThreads), 0, st, b.tsl, b.toff, b.tbsum,
-                       p.ntct);
-    hipLaunchKernelGGL(k_scan2, dim3(1), dim3(kScanThreads), 0, st, b.tbsum, p.nblocks_tscan, &b.hdr->ntasks,
-                       (int32_t *)nullptr, (int64_t)0);
-    hipLaunchKernelGGL(k_scan3, dim3(grid_for(p.ntct, 256)), dim3(256), 0, st, b.toff, b.tbsum, p.ntct);
-    hipLaunchKernelGGL(k_tasks, dim3(grid_for(p.ntct, 256)), dim3(256), 0, st, b.tsl, b.toff, p.ntct, b.tasks,
-                       p.maxtasks);
-    static const unsigned nw = resident_waves(k_bg<T, SOLVER>);
-    hipLaunchKernelGGL((k_bg<T, SOLVER>), dim3(nw), dim3(kWave), 0, st, ra);
-}
-
-template <int T>
-static void forward_T(const Plan &p, const Inputs &in, const Bufs &b, hipStream_t st, const PhaseEvents *pe)
-{
-    bin_T<T>(p, in, b, st);
+    const int n = bt.n;
+    const Grids &g = bt.g;
+    int64_t *tprefix = (int64_t *)((char *)ws + bt.o_tprefix);
+    hipLaunchKernelGGL(k_bin<T>, dim3((unsigned)g.bin), dim3(kBinThreads), 0, st, tab, n, 0);
+    hipLaunchKernelGGL(k_scan1, dim3((unsigned)g.scan1), dim3(kScanThreads), 0, st, tab, n, 0);
+    hipLaunchKernelGGL(k_scan2, dim3((unsigned)n), dim3(kScanThreads), 0, st, tab, 0);
+    hipLaunchKernelGGL(k_scan3, dim3((unsigned)g.scan3), dim3(256), 0, st, tab, n, 0);
+    hipLaunchKernelGGL(k_bin<T>, dim3((unsigned)g.bin), dim3(kBinThreads), 0, st, tab, n, 1);
     mark(pe, 2, st);
-    const RasterArgs ra = raster_args(p, in, b);
-    if (p.solver == RB_SOLVER_FAST)
-        raster_fwd_T<T, RB_SOLVER_FAST>(p, ra, b, st);
-    else
-        raster_fwd_T<T, RB_SOLVER_RECOMPUTE>(p, ra, b, st);
+    hipLaunchKernelGGL((k_fg<T, SOLVER>), dim3((unsigned)g.fg), dim3(kWave), 0, st, tab, n);
+    hipLaunchKernelGGL(k_scan1, dim3((unsigned)g.tscan1), dim3(kScanThreads), 0, st, tab, n, 1);
+    hipLaunchKernelGGL(k_scan2, dim3((unsigned)n), dim3(kScanThreads), 0, st, tab, 1);
+    hipLaunchKernelGGL(k_scan3, dim3((unsigned)g.tscan3), dim3(256), 0, st, tab, n, 1);
+    hipLaunchKernelGGL(k_tasks, dim3((unsigned)g.tscan3), dim3(256), 0, st, tab, n);
+    hipLaunchKernelGGL(k_tprefix, dim3(1), dim3(64), 0, st, tab, n, tprefix);
+    mark(pe, 3, st);
+    static const unsigned nw = resident_waves(k_bg<T, SOLVER>);
+    hipLaunchKernelGGL((k_bg<T, SOLVER>), dim3(nw), dim3(kWave), 0, st, tab, n, (const int64_t *)tprefix);
 }
 
-hipError_t launch_forward(const Plan &p, const Inputs &in, const Bufs &b, float *image, hipStream_t st,
-                          const PhaseEvents *pe)
+hipError_t launch_forward(const Batch &bt, const std::vector<Io> &io, void *ws, hipStream_t st, const PhaseEvents *pe)
 {
+    const int n = bt.n;
+    const Grids &g = bt.g;
     mark(pe, 0, st);
-    hipLaunchKernelGGL(k_init, dim3(grid_for(p.ncounts, 256) > 4096 ? 4096 : grid_for(p.ncounts, 256) + 1), dim3(256), 0,
-                       st, b.hdr, p.cap, b.cnt, b.cur, p.ncounts);
-    ViewArgs vw;
-    for (int i = 0; i < 12; ++i) vw.m[i] = p.view[i];
-    vw.tanf = p.tanf;
-    const int64_t nproj = (int64_t)(p.S + 1) * p.V + p.F;
-    hipLaunchKernelGGL(k_project, dim3(grid_for(nproj, 256)), dim3(256), 0, st, in.verts, in.model, in.faces, p.V,
-                       p.S, p.F, vw, b.kf, b.kfz, b.hdr);
+    const Inst *tab = write_table(bt, io, ws, st);
+    hipLaunchKernelGGL(k_init, dim3((unsigned)g.init), dim3(256), 0, st, tab, n);
+    hipLaunchKernelGGL(k_project, dim3((unsigned)g.proj), dim3(256), 0, st, tab, n);
     mark(pe, 1, st);
-    switch (p.T) {
-    case 1: forward_T<1>(p, in, b, st, pe); break;
-    case 2: forward_T<2>(p, in, b, st, pe); break;
-    case 4: forward_T<4>(p, in, b, st, pe); break;
-    default: forward_T<8>(p, in, b, st, pe); break;
+    const bool fast = bt.solver == RB_SOLVER_FAST;
+    switch (bt.T) {
+    case 1: fast ? forward_T<1, RB_SOLVER_FAST>(bt, tab, ws, st, pe) : forward_T<1, RB_SOLVER_RECOMPUTE>(bt, tab, ws, st, pe); break;
+    case 2: fast ? forward_T<2, RB_SOLVER_FAST>(bt, tab, ws, st, pe) : forward_T<2, RB_SOLVER_RECOMPUTE>(bt, tab, ws, st, pe); break;
+    case 4: fast ? forward_T<4, RB_SOLVER_FAST>(bt, tab, ws, st, pe) : forward_T<4, RB_SOLVER_RECOMPUTE>(bt, tab, ws, st, pe); break;
+    default: fast ? forward_T<8, RB_SOLVER_FAST>(bt, tab, ws, st, pe) : forward_T<8, RB_SOLVER_RECOMPUTE>(bt, tab, ws, st, pe); break;
     }
-    mark(pe, 3, st);
-    hipLaunchKernelGGL(k_resolve, dim3((unsigned)p.ntiles), dim3(kWave), 0, st, raster_args(p, in, b), image);
     mark(pe, 4, st);
+    hipLaunchKernelGGL(k_resolve, dim3((unsigned)g.res), dim3(kWave), 0, st, tab, n);
+    mark(pe, 5, st);
     return hipGetLastError();
 }
 
 template <int T, int SOLVER>
-static void raster_bwd_T(const Plan &p, const RasterArgs &ra, const GradArgs &ga, hipStream_t st)
+static void backward_T(const Batch &bt, const Inst *tab, void *ws, hipStream_t st, const PhaseEvents *pe)
 {
-    hipLaunchKernelGGL((k_fg_bwd<T, SOLVER>), dim3((unsigned)p.ntct), dim3(kWave), 0, st, ra, ga);
-    static const unsigned nw = 3 * resident_waves(k_bg_bwd<T, SOLVER>) / 2;
-    hipLaunchKernelGGL((k_bg_bwd<T, SOLVER>), dim3(nw), dim3(kWave), 0, st, ra, ga);
-}
-
-template <int T>
-static void backward_T(const Plan &p, const Inputs &in, const Bufs &b, const GradArgs &ga, hipStream_t st)
-{
-    const RasterArgs ra = raster_args(p, in, b);
-    if (p.solver == RB_SOLVER_FAST)
-        raster_bwd_T<T, RB_SOLVER_FAST>(p, ra, ga, st);
-    else
-        raster_bwd_T<T, RB_SOLVER_RECOMPUTE>(p, ra, ga, st);
-}
-
-hipError_t launch_backward(const Plan &p, const Inputs &in, const Bufs &b, const float *grad_image, float *grad_verts,
-                           float *grad_attrs, hipStream_t st, const PhaseEvents *pe)
-{
-    mark(pe, 0, st);
-    const int64_t ngkf = (int64_t)(p.S + 1) * p.V * 2;
-    const int64_t nga = (int64_t)p.V * p.C;
-    const unsigned gz = grid_for(ngkf + nga, 256);
-    hipLaunchKernelGGL(k_bwd_init, dim3(gz > 4096 ? 4096 : gz), dim3(256), 0, st, b.gkf, ngkf, grad_attrs, nga, b.hdr);
-    GradArgs ga;
-    ga.grad_image = grad_image;
-    ga.gkf = b.gkf;
-    ga.gattr = grad_attrs;
-    ga.invK = 1.0f / (float)p.K;
+    const int n = bt.n;
+    const int64_t *tprefix = (const int64_t *)((char *)ws + bt.o_tprefix);
+    BatchHeader *bh = (BatchHeader *)((char *)ws + bt.o_bhdr);
+    hipLaunchKernelGGL((k_fg_bwd<T, SOLVER>), dim3((unsigned)bt.g.fg), dim3(kWave), 0, st, tab, n);
     mark(pe, 1, st);
-    switch (p.T) {
-    case 1: backward_T<1>(p, in, b, ga, st); break;
-    case 2: backward_T<2>(p, in, b, ga, st); break;
-    case 4: backward_T<4>(p, in, b, ga, st); break;
-    default: backward_T<8>(p, in, b, ga, st); break;
+    // the tasks vary in cost: more waves than fit at once, taking tasks from a counter
+    static const unsigned nw = 3 * resident_waves(k_bg_bwd<T, SOLVER>) / 2;
+    hipLaunchKernelGGL((k_bg_bwd<T, SOLVER>), dim3(nw), dim3(kWave), 0, st, tab, n, tprefix, bh);
+}
+
+hipError_t launch_backward(const Batch &bt, const std::vector<Io> &io, void *ws, hipStream_t st, const PhaseEvents *pe)
+{
+    const int n = bt.n;
+    mark(pe, 0, st);
+    const Inst *tab = write_table(bt, io, ws, st);
+    BatchHeader *bh = (BatchHeader *)((char *)ws + bt.o_bhdr);
+    hipLaunchKernelGGL(k_bwd_init, dim3((unsigned)bt.g.bwdinit), dim3(256), 0, st, tab, n, bh);
+    const bool fast = bt.solver == RB_SOLVER_FAST;
+    switch (bt.T) {
+    case 1: fast ? backward_T<1, RB_SOLVER_FAST>(bt, tab, ws, st, pe) : backward_T<1, RB_SOLVER_RECOMPUTE>(bt, tab, ws, st, pe); break;
+    case 2: fast ? backward_T<2, RB_SOLVER_FAST>(bt, tab, ws, st, pe) : backward_T<2, RB_SOLVER_RECOMPUTE>(bt, tab, ws, st, pe); break;
+    case 4: fast ? backward_T<4, RB_SOLVER_FAST>(bt, tab, ws, st, pe) : backward_T<4, RB_SOLVER_RECOMPUTE>(bt, tab, ws, st, pe); break;
+    default: fast ? backward_T<8, RB_SOLVER_FAST>(bt, tab, ws, st, pe) : backward_T<8, RB_SOLVER_RECOMPUTE>(bt, tab, ws, st, pe); break;
     }
     mark(pe, 2, st);
-    ViewArgs vw;
-    for (int i = 0; i < 12; ++i) vw.m[i] = p.view[i];
-    vw.tanf = p.tanf;
-    hipLaunchKernelGGL(k_kf_to_vertex, dim3(grid_for(p.V, 256)), dim3(256), 0, st, in.verts, in.model, b.gkf, p.V,
-                       p.S, vw, grad_verts);
+    hipLaunchKernelGGL(k_kf_to_vertex, dim3((unsigned)bt.g.vtx), dim3(256), 0, st, tab, n);
     mark(pe, 3, st);
     return hipGetLastError();
 }

@@ -47,16 +47,20 @@ def test_library_exports_every_declared_symbol(L):
 
 
 def test_struct_layouts_match_the_header(tmp_path):
+    fields = [("rb_camera", None), ("rb_motion", None), ("rb_options", None), ("rb_header", None),
+              ("rb_profile_stats", None), ("rb_instance", None), ("rb_options", "list_capacity"),
+              ("rb_motion", "keyframe_model"), ("rb_instance", "motion"), ("rb_instance", "camera"),
+              ("rb_instance", "list_capacity"), ("rb_instance", "grad_attrs"),
+              ("rb_profile_stats", "fwd_calls")]
+    exprs = [f"sizeof({t})" if f is None else f"offsetof({t}, {f})" for t, f in fields]
     src = tmp_path / "probe.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "motion_blur_raster.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(rb_camera), sizeof(rb_motion),'
-                   ' sizeof(rb_options), sizeof(rb_header), offsetof(rb_options, list_capacity),'
-                   ' offsetof(rb_motion, keyframe_model)); return 0;}\n')
+                   'int main(void){' + "".join(f'printf("%zu\\n", (size_t){e});' for e in exprs)
+                   + ' return 0;}\n')
     exe = tmp_path / "probe"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
-    want = [ctypes.sizeof(B.rb_camera), ctypes.sizeof(B.rb_motion), ctypes.sizeof(B.rb_options),
-            ctypes.sizeof(B.rb_header), B.rb_options.list_capacity.offset, B.rb_motion.keyframe_model.offset]
+    want = [ctypes.sizeof(getattr(B, t)) if f is None else getattr(getattr(B, t), f).offset for t, f in fields]
     assert got == want
 
 
