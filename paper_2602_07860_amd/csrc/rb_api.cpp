@@ -114,7 +114,7 @@ static rb_status make_plan(int32_t V, int32_t F, int32_t C, const rb_motion *mot
 }
 
 // Plan a batch: instance workspaces one after another (256-byte aligned),
-// then the device instance table, the batch's task prefix and its header.
+// then the device instance table and the batch's task numbering.
 static rb_status make_batch(const std::vector<Plan> &plans, Batch &bt)
 {
     bt.n = (int)plans.size();
@@ -151,8 +151,6 @@ static rb_status make_batch(const std::vector<Plan> &plans, Batch &bt)
     o = align256(o + (size_t)bt.n * sizeof(Inst));
     bt.o_tprefix = o;
     o = align256(o + (size_t)(bt.n + 1) * sizeof(int64_t));
-    bt.o_bhdr = o;
-    o = align256(o + sizeof(BatchHeader));
     bt.total = o;
     return RB_OK;
 }

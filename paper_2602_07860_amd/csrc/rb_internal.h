@@ -53,12 +53,7 @@ struct DevHeader {
     int64_t list_entries;
     int64_t list_capacity;
     int64_t ntasks;       // background tasks of the current forward
-    int64_t pad[4];
-};
-
-// Batch-level device state, after the instance workspaces.
-struct BatchHeader {
-    unsigned long long bwd_task_ctr;   // next background adjoint task (all instances)
+    unsigned long long bwd_task_ctr;   // next background-adjoint task
     int64_t pad[3];
 };
 
@@ -138,13 +133,13 @@ struct Grids {
 };
 
 // Host plan of a batch: per-instance plans and where each instance's
-// workspace starts; the table of Inst and the batch header follow them.
+// workspace starts; the table of Inst and the task numbering follow them.
 struct Batch {
     int n, T, solver;
     std::vector<Plan> plans;
     std::vector<size_t> base;
     Grids g;
-    size_t o_table, o_tprefix, o_bhdr, total;
+    size_t o_table, o_tprefix, total;
 };
 
 // Per-instance arrays the host entry points pass in.

@@ -118,7 +118,7 @@ __global__ void k_set_table(TabChunk c, Inst *tab)
 
 __global__ void k_init(const Inst *__restrict__ tab, int n)
 {
-    const Inst &a = tab[inst_of<&Inst::b_init>(tab, n, blockIdx.x)];
+    const Inst a = tab[inst_of<&Inst::b_init>(tab, n, blockIdx.x)];
     const int64_t i = (int64_t)(blockIdx.x - a.b_init) * blockDim.x + threadIdx.x;
     if (i == 0) {
         a.hdr->error_bits = 0;
@@ -133,13 +133,13 @@ __global__ void k_init(const Inst *__restrict__ tab, int n)
     }
 }
 
-// clear the keyframe and attribute gradients (and, once, the batch's
-// background-adjoint task counter)
-__global__ void k_bwd_init(const Inst *__restrict__ tab, int n, BatchHeader *bh)
+// clear the keyframe and attribute gradients and the background-adjoint
+// task counter
+__global__ void k_bwd_init(const Inst *__restrict__ tab, int n)
 {
-    const Inst &a = tab[inst_of<&Inst::b_bwdinit>(tab, n, blockIdx.x)];
-    if (blockIdx.x == 0 && threadIdx.x == 0) bh->bwd_task_ctr = 0;
+    const Inst a = tab[inst_of<&Inst::b_bwdinit>(tab, n, blockIdx.x)];
     const int64_t i = (int64_t)(blockIdx.x - a.b_bwdinit) * blockDim.x + threadIdx.x;
+    if (i == 0) a.hdr->bwd_task_ctr = 0;
     const int64_t n1 = (int64_t)(a.S + 1) * a.V * 2, n2 = (int64_t)a.V * a.C;
     if (i < n1)
         a.gkf[i] = 0.0f;
@@ -150,7 +150,7 @@ __global__ void k_bwd_init(const Inst *__restrict__ tab, int n, BatchHeader *bh)
 // Keyframe projection (App. I): X = view (M_s P0), x = X.x/(X.z tan), y = X.y/(X.z tan)
 __global__ void k_project(const Inst *__restrict__ tab, int n)
 {
-    const Inst &a = tab[inst_of<&Inst::b_proj>(tab, n, blockIdx.x)];
+    const Inst a = tab[inst_of<&Inst::b_proj>(tab, n, blockIdx.x)];
     const int64_t i = (int64_t)(blockIdx.x - a.b_proj) * blockDim.x + threadIdx.x;
     const int V = a.V, F = a.F;
     const int64_t nkf = (int64_t)(a.S + 1) * V;
@@ -283,7 +283,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const Inst *__restrict__ ta
     __shared__ int lcnt[kBinWin];
     __shared__ int64_t lbase[kBinWin];
     __shared__ int win[4];
-    const Inst &a = tab[inst_of<&Inst::b_bin>(tab, n, blockIdx.x)];
+    const Inst a = tab[inst_of<&Inst::b_bin>(tab, n, blockIdx.x)];
     const int nfb = a.nfb;
     const int lb = blockIdx.x - a.b_bin;
     const int c = lb / nfb;
@@ -476,7 +476,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan1(const Inst *__restrict__
 __global__ __launch_bounds__(kScanThreads) void k_scan2(const Inst *__restrict__ tab, int which)
 {
     __shared__ int64_t tot;
-    const Inst &a = tab[blockIdx.x];
+    const Inst a = tab[blockIdx.x];
     const ScanIo io = scan_io(a, which);
     int64_t carry = 0;
     for (int64_t b0 = 0; b0 < io.nb; b0 += kScanThreads) {
@@ -1168,7 +1168,7 @@ __global__ __launch_bounds__(64) void k_fg(const Inst *__restrict__ tab, int n)
 {
     __shared__ FgShared<T> sh;
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
-    const Inst &a = tab[inst_of<&Inst::b_fg>(tab, n, lb)];
+    const Inst a = tab[inst_of<&Inst::b_fg>(tab, n, lb)];
     const int ct = lb - a.b_fg;
     const int lane = threadIdx.x & 63;
     TileCtx g;
@@ -1235,7 +1235,7 @@ __global__ __launch_bounds__(64) void k_fg(const Inst *__restrict__ tab, int n)
 // write the task list: tasks[toff[ct] + i] = (ct, i), i < tsl[ct]
 __global__ void k_tasks(const Inst *__restrict__ tab, int n)
 {
-    const Inst &a = tab[inst_of<&Inst::b_tscan3>(tab, n, blockIdx.x)];
+    const Inst a = tab[inst_of<&Inst::b_tscan3>(tab, n, blockIdx.x)];
     const int64_t ct = (int64_t)(blockIdx.x - a.b_tscan3) * blockDim.x + threadIdx.x;
     if (ct >= a.ntct) return;
     const int m = a.tsl[ct];
@@ -1251,7 +1251,7 @@ __global__ void k_tprefix(const Inst *__restrict__ tab, int n, int64_t *__restri
     int64_t s = 0;
     for (int i = 0; i < n; ++i) {
         tprefix[i] = s;
-        const Inst &a = tab[i];
+        const Inst a = tab[i];
         if (!(a.hdr->error_bits & kHdrOverflow)) s += min(a.hdr->ntasks, a.maxtasks);
     }
     tprefix[n] = s;
@@ -1313,11 +1313,16 @@ __global__ __launch_bounds__(64) void k_bg(const Inst *__restrict__ tab, int n, 
 {
     __shared__ BgShared<T> sh;
     const int lane = threadIdx.x & 63;
-    const int64_t ntasks = tprefix[n];
-    for (int64_t tb = blockIdx.x; tb < ntasks; tb += gridDim.x) {
-        const int ii = task_inst(tprefix, n, tb);
-        const Inst &a = tab[ii];
-        const int64_t t = tb - tprefix[ii];
+    // batch task tb goes to wave tb mod G; the instance record is loaded once
+    // per (wave, instance)
+    const int64_t G = gridDim.x;
+    for (int ii = 0; ii < n; ++ii) {
+        const int64_t lo = tprefix[ii], hi = tprefix[ii + 1];
+        int64_t tb = lo + (((int64_t)blockIdx.x - lo) % G + G) % G;
+        if (tb >= hi) continue;
+        const Inst a = tab[ii];
+    for (; tb < hi; tb += G) {
+        const int64_t t = tb - lo;
         const uint64_t task = a.tasks[t];
         const int ct = (int)(task >> 32);
         const int slice = (int)(uint32_t)task;
@@ -1362,6 +1367,7 @@ __global__ __launch_bounds__(64) void k_bg(const Inst *__restrict__ tab, int n, 
             if (nz) atomicAdd((int *)&a.pix[pix_index(a, g.tile, ck.k0 + j, 1, lane)], nz);
         }
     }
+    }
 }
 
 // ---------------------------------------------------- forward: k_resolve
@@ -1370,7 +1376,7 @@ __global__ __launch_bounds__(64) void k_bg(const Inst *__restrict__ tab, int n, 
 // alpha 1) or, where uncovered, alpha = 1 - prod (1 - A) (eq 15)
 __global__ __launch_bounds__(64) void k_resolve(const Inst *__restrict__ tab, int n)
 {
-    const Inst &a = tab[inst_of<&Inst::b_res>(tab, n, blockIdx.x)];
+    const Inst a = tab[inst_of<&Inst::b_res>(tab, n, blockIdx.x)];
     float *__restrict__ image = a.image;
     const int lane = threadIdx.x & 63;
     const int tile = blockIdx.x - a.b_res;
@@ -1569,7 +1575,7 @@ __global__ __launch_bounds__(64) void k_fg_bwd(const Inst *__restrict__ tab, int
 {
     __shared__ FgBwdShared<T> sh;
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
-    const Inst &a = tab[inst_of<&Inst::b_fg>(tab, n, lb)];
+    const Inst a = tab[inst_of<&Inst::b_fg>(tab, n, lb)];
     const int ct = lb - a.b_fg;
     const int lane = threadIdx.x & 63;
     if (a.hdr->error_bits & kHdrOverflow) return;
@@ -1796,21 +1802,21 @@ __device__ __forceinline__ void bg_item_bwd(const Inst &a, BgBwdShared<T> &sh, i
 }
 
 template <int T, int SOLVER>
-__global__ __launch_bounds__(64) void k_bg_bwd(const Inst *__restrict__ tab, int n,
-                                                const int64_t *__restrict__ tprefix, BatchHeader *bh)
+__global__ __launch_bounds__(64) void k_bg_bwd(const Inst *__restrict__ tab, int n)
 {
     __shared__ BgBwdShared<T> sh;
     const int lane = threadIdx.x & 63;
     vt_clear(sh.vt);
     // tasks vary more in cost here than in the forward (pixels without
-    // gradient drop out), so waves take them from a counter
-    const int64_t ntasks = tprefix[n];
+    // gradient drop out), so waves take them from a counter per instance,
+    // moving through the instances in order
+    for (int ii = 0; ii < n; ++ii) {
+        const Inst a = tab[ii];
+        if (a.hdr->error_bits & kHdrOverflow) continue;
+        const int64_t ntasks = min(a.hdr->ntasks, a.maxtasks);
     for (;;) {
-        const int64_t tb = next_task(&bh->bwd_task_ctr);
-        if (tb >= ntasks) break;
-        const int ii = task_inst(tprefix, n, tb);
-        const Inst &a = tab[ii];
-        const int64_t t = tb - tprefix[ii];
+        const int64_t t = next_task(&a.hdr->bwd_task_ctr);
+        if (t >= ntasks) break;
         const uint64_t task = a.tasks[t];
         const int ct = (int)(task >> 32);
         const int slice = (int)(uint32_t)task;
@@ -1868,13 +1874,14 @@ __global__ __launch_bounds__(64) void k_bg_bwd(const Inst *__restrict__ tab, int
         }
         if (used > 0) vt_flush(sh.vt, ck.s, a);
     }
+    }
 }
 
 // dL/dP0 = sum_s (d(x, y)_s / dP0)^T dL/d(x, y)_s through the projection and
 // the keyframe transform (App. I); camera depth carries no gradient.
 __global__ void k_kf_to_vertex(const Inst *__restrict__ tab, int n)
 {
-    const Inst &a = tab[inst_of<&Inst::b_vtx>(tab, n, blockIdx.x)];
+    const Inst a = tab[inst_of<&Inst::b_vtx>(tab, n, blockIdx.x)];
     const int v = (blockIdx.x - a.b_vtx) * blockDim.x + threadIdx.x;
     const int V = a.V, S = a.S;
     const float *__restrict__ verts = a.verts;
@@ -2086,13 +2093,11 @@ template <int T, int SOLVER>
 static void backward_T(const Batch &bt, const Inst *tab, void *ws, hipStream_t st, const PhaseEvents *pe)
 {
     const int n = bt.n;
-    const int64_t *tprefix = (const int64_t *)((char *)ws + bt.o_tprefix);
-    BatchHeader *bh = (BatchHeader *)((char *)ws + bt.o_bhdr);
     hipLaunchKernelGGL((k_fg_bwd<T, SOLVER>), dim3((unsigned)bt.g.fg), dim3(kWave), 0, st, tab, n);
     mark(pe, 1, st);
     // the tasks vary in cost: more waves than fit at once, taking tasks from a counter
     static const unsigned nw = 3 * resident_waves(k_bg_bwd<T, SOLVER>) / 2;
-    hipLaunchKernelGGL((k_bg_bwd<T, SOLVER>), dim3(nw), dim3(kWave), 0, st, tab, n, tprefix, bh);
+    hipLaunchKernelGGL((k_bg_bwd<T, SOLVER>), dim3(nw), dim3(kWave), 0, st, tab, n);
 }
 
 hipError_t launch_backward(const Batch &bt, const std::vector<Io> &io, void *ws, hipStream_t st, const PhaseEvents *pe)
@@ -2100,8 +2105,7 @@ hipError_t launch_backward(const Batch &bt, const std::vector<Io> &io, void *ws,
     const int n = bt.n;
     mark(pe, 0, st);
     const Inst *tab = write_table(bt, io, ws, st);
-    BatchHeader *bh = (BatchHeader *)((char *)ws + bt.o_bhdr);
-    hipLaunchKernelGGL(k_bwd_init, dim3((unsigned)bt.g.bwdinit), dim3(256), 0, st, tab, n, bh);
+    hipLaunchKernelGGL(k_bwd_init, dim3((unsigned)bt.g.bwdinit), dim3(256), 0, st, tab, n);
     const bool fast = bt.solver == RB_SOLVER_FAST;
     switch (bt.T) {
     case 1: fast ? backward_T<1, RB_SOLVER_FAST>(bt, tab, ws, st, pe) : backward_T<1, RB_SOLVER_RECOMPUTE>(bt, tab, ws, st, pe); break;
