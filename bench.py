@@ -2,18 +2,26 @@
 """Throughput benchmark of the motion-blur rasterizer: pixel-sub-frames per
 second of one forward + backward step.
 
-Workload (default): nu=32 geodesic sphere (10242 V / 20480 F) displaced by
-0.02 N(0,1), per-vertex RGB, 256x256, K = 64 sub-frames, 3 revolutions about a
-seeded axis cut into S = 36 linear segments; L2 loss against the render of a
-second seeded displacement.  One step = forward render + dL/dI + adjoint into
-vertex positions and colours.  Inputs are resident in GPU memory before the
-timed region.  The step is timed for the fast solver (eq 8) and for the
-per-sub-frame recompute (eqs 1-3) on the same GPU.
+Workloads (synthetic, seeded; see paper_2602_07860_amd/workloads.py):
+  medium (default): nu=32 geodesic sphere (10242 V / 20480 F) displaced by
+    0.02 N(0,1), per-vertex RGB, 256x256, K = 64 sub-frames, 3 revolutions
+    about a seeded axis cut into S = 36 linear segments; L2 loss against the
+    render of a second seeded displacement.
+  large: nu=64 (40962 V / 81920 F), multi-octave displacement, 1024x1024,
+    K = 512, 5 revolutions + 200 px translation in S = 60 segments.
+  batch: 32 instances of mixed sizes, resolutions {128, 256, 512}^2,
+    K in [32, 256], half translation / half rotation, all in one launch
+    sequence captured in a graph and replayed; chunk and slice lengths from
+    the autotuner.
+One step = forward render + dL/dI + adjoint into vertex positions and colours.
+Inputs are resident in GPU memory before the timed region.  The step is timed
+for the fast solver (eq 8) and for the per-sub-frame recompute (eqs 1-3) on
+the same GPU.
 
-Prints ONE JSON line (rank 0).  Extra objects: "roofline" for the dominant
-kernel (algorithmic FLOPs from the FP64 reference's exact pair counters,
-divided by the kernel's average duration measured with HIP events on its
-stream), and "cpu_baseline": the FP64 reference renderer timed on this host.
+Prints ONE JSON line.  Extra objects: "roofline" for the dominant kernel
+(algorithmic FLOPs from the FP64 reference's exact pair counters, divided by
+the kernel's average duration measured with HIP events on its stream), and
+"cpu_baseline": the FP64 reference renderer timed on this host.
 """
 import argparse
 import json
@@ -63,11 +71,120 @@ def kernel_ms(prof):
             "vertex_grad": prof.vertex_grad_ms / b}
 
 
+def timed(fn, steps, B, torch, phases=True):
+    """Average ms of fn() over `steps` calls (device events) and, optionally,
+    the per-kernel phases of a second pass of `steps` calls."""
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    if not phases:
+        return ms, None
+    B.rb_profile_enable(True)
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    prof = B.rb_profile_read()
+    B.rb_profile_enable(False)
+    return ms, kernel_ms(prof)
+
+
+def run_single(sc, tg, args, torch, B, R):
+    dev = "cuda:0"
+    st = R.scene_tensors(sc, dev)
+    tt = R.scene_tensors(tg, dev)
+
+    def opts(solver, check=True):
+        return R.RenderOptions(sc.num_subframes, solver=solver, chunk_len=args.chunk_len,
+                               slice_len=args.slice_len, check=check)
+
+    target, _ = R.render_forward(tt.verts, tt.faces, tt.attrs, tt.model, tt.camera, opts("fast"))
+    res = {}
+    for solver in ("fast", "recompute"):
+        box = {"o": opts(solver, check=True)}
+
+        def step():
+            img, state = R.render_forward(st.verts, st.faces, st.attrs, st.model, st.camera, box["o"])
+            gv, ga = R.render_backward(st.verts, st.faces, st.attrs, st.model, state, 2.0 * (img - target))
+            box["out"] = (img, gv, ga, state)
+
+        for _ in range(max(1, args.warmup)):
+            step()
+            box["o"] = opts(solver, check=False)
+        ms, km = timed(step, args.steps, B, torch)
+        img, gv, ga, state = box["out"]
+        h = B.rb_read_header(state.workspace.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        if h.error_bits:
+            raise RuntimeError(f"device header reports error bits {h.error_bits}")
+        if not (torch.isfinite(img).all() and torch.isfinite(gv).all() and torch.isfinite(ga).all()):
+            raise RuntimeError("non-finite output")
+        res[solver] = dict(ms=ms, km=km)
+    return res
+
+
+def run_batch(scenes, targets_sc, args, torch, B, R):
+    from paper_2602_07860_amd import batch as BT
+    dev = "cuda:0"
+    sts = [R.scene_tensors(sc, dev) for sc in scenes]
+    tr = BT.BatchRenderer([R.scene_tensors(t, dev) for t in targets_sc], R.RenderOptions(0))
+    tr.fit()
+    targets = [im.clone() for im in tr.forward()]
+    del tr
+    res = {}
+    for solver in ("fast", "recompute"):
+        T, SL = BT.autotune(sts, targets, solver=solver, log=log)
+        log(f"autotuned {solver}: chunk_len {T} slice_len {SL}")
+        r = BT.BatchRenderer(sts, R.RenderOptions(0, solver=solver, chunk_len=T, slice_len=SL))
+        r.fit()
+        step = BT.L2Step(r, targets)
+        step.capture()
+        for _ in range(max(1, args.warmup)):
+            step.replay()
+        ms, _ = timed(step.replay, args.steps, B, torch, phases=False)
+        _, km = timed(step.eager, max(2, args.steps // 4), B, torch)   # phase events need eager calls
+        hs = r.headers()
+        if any(h.error_bits for h in hs):
+            raise RuntimeError("device header reports errors")
+        if not all(bool(torch.isfinite(x).all()) for x in r.images + r.grad_verts + r.grad_attrs):
+            raise RuntimeError("non-finite output")
+        res[solver] = dict(ms=ms, km=km, chunk_len=T, slice_len=SL)
+        del step, r
+    return res
+
+
+def cpu_oracle(scenes, rows_step, nth, label):
+    """FP64 oracle fwd+bwd on every rows_step-th pixel row of each scene:
+    time, pixel-sub-frames covered and pair counters scaled to all rows."""
+    import oracle
+    t = 0.0
+    units = 0
+    counters = None
+    for sc in scenes:
+        rows = (0, sc.height, rows_step)
+        G = np.random.default_rng(0).normal(size=(sc.attrs.shape[1] + 1, sc.height, sc.width))
+        t0 = time.perf_counter()
+        ref = oracle.render(sc, grad_image=G, counters=True, nthreads=nth, rows=rows)
+        t += time.perf_counter() - t0
+        nr = len(range(*rows))
+        units += nr * sc.width * sc.num_subframes
+        c = {k: v * sc.height / nr for k, v in ref.counters.items()}
+        counters = c if counters is None else {k: counters[k] + c[k] for k in c}
+    cpu = {"value": units / t, "unit": "pixel-subframes/s", "cores": nth, "kind": "oracle",
+           "sample": f"{label}: forward + backward on every {rows_step}th pixel row, {units} pixel-sub-frames, "
+                     f"FP64, {nth} OpenMP threads, {t:.1f} s"}
+    return cpu, counters
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=("medium", "large", "batch"), default="medium")
     ap.add_argument("--chunk-len", type=int, default=4)
     ap.add_argument("--slice-len", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -87,76 +204,43 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
-    dev = "cuda:0"
-    sc = wl.make_workload(wl.MEDIUM)
-    tg = wl.make_target(sc, 2)
-    st = R.scene_tensors(sc, dev)
-    tt = R.scene_tensors(tg, dev)
-    H, W, K = sc.height, sc.width, sc.num_subframes
-    units = H * W * K
 
-    def opts(solver, check=True):
-        return R.RenderOptions(K, solver=solver, chunk_len=args.chunk_len,
-                               slice_len=args.slice_len, check=check)
+    if args.workload == "batch":
+        scenes = wl.make_batch(seed=3, n=32)
+        targets = [wl.make_target(sc, 1003 + i) for i, sc in enumerate(scenes)]
+        res = run_batch(scenes, targets, args, torch, B, R)
+        config = {"workload": "batch32-mixed fwd+bwd L2, one graph replay", "instances": len(scenes),
+                  "faces_total": int(sum(len(s.faces) for s in scenes)),
+                  "chunk_len": res["fast"]["chunk_len"], "slice_len": res["fast"]["slice_len"], "solver": "fast"}
+    else:
+        sc = wl.make_workload(wl.MEDIUM if args.workload == "medium" else wl.LARGE)
+        scenes = [sc]
+        tg = wl.make_target(sc, 2)
+        res = run_single(sc, tg, args, torch, B, R)
+        config = {"workload": f"{sc.name} fwd+bwd L2", "vertices": int(len(sc.verts)),
+                  "faces": int(len(sc.faces)), "resolution": f"{sc.width}x{sc.height}",
+                  "subframes": sc.num_subframes, "segments": sc.num_segments, "solver": "fast",
+                  "chunk_len": args.chunk_len}
+    units = sum(s.height * s.width * s.num_subframes for s in scenes)
+    for solver, r in res.items():
+        log(f"{solver}: {r['ms']:.3f} ms/step  {units / (r['ms'] * 1e-3):.3e} px-sub/s  "
+            + " ".join(f"{k} {v:.3f}" for k, v in r["km"].items()) + " ms")
 
-    target, _ = R.render_forward(tt.verts, tt.faces, tt.attrs, tt.model, tt.camera, opts("fast"))
-
-    def step(o):
-        img, state = R.render_forward(st.verts, st.faces, st.attrs, st.model, st.camera, o)
-        g = 2.0 * (img - target)
-        gv, ga = R.render_backward(st.verts, st.faces, st.attrs, st.model, state, g)
-        return img, gv, ga, state
-
-    results = {}
-    for solver in ("fast", "recompute"):
-        o = opts(solver, check=True)
-        for _ in range(max(1, args.warmup)):
-            step(o)
-            o = opts(solver, check=False)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(args.steps):
-            img, gv, ga, state = step(o)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / args.steps
-        h = B.rb_read_header(state.workspace.data_ptr(), torch.cuda.current_stream().cuda_stream)
-        if h.error_bits:
-            raise RuntimeError(f"device header reports error bits {h.error_bits}")
-        if not (torch.isfinite(img).all() and torch.isfinite(gv).all() and torch.isfinite(ga).all()):
-            raise RuntimeError("non-finite output")
-        # per-kernel durations: a second timed pass with phase events on the stream
-        B.rb_profile_enable(True)
-        for _ in range(args.steps):
-            step(o)
-        torch.cuda.synchronize()
-        prof = B.rb_profile_read()
-        B.rb_profile_enable(False)
-        results[solver] = dict(ms=ms, value=units / (ms * 1e-3), prof=prof)
-        km = kernel_ms(prof)
-        results[solver]["kernel_ms"] = km
-        log(f"{solver}: {ms:.3f} ms/step  {units / (ms * 1e-3):.3e} px-sub/s  "
-            + " ".join(f"{k} {v:.3f}" for k, v in km.items()) + " ms")
-
-    # ---- FP64 reference on the host: CPU baseline and exact pair counters
+    # ---- FP64 reference on the host: CPU baseline and pair counters
     cpu = None
     counters = None
     if not args.no_cpu_baseline:
-        import oracle
         nth = args.cpu_threads or int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
-        G = np.random.default_rng(0).normal(size=(4, H, W))
-        t0 = time.perf_counter()
-        ref = oracle.render(sc, grad_image=G, counters=True, nthreads=nth)
-        dt = time.perf_counter() - t0
-        counters = ref.counters
-        cpu = {"value": units / dt, "unit": "pixel-subframes/s", "cores": nth, "kind": "oracle",
-               "sample": f"full workload, forward + backward, {H}x{W}x{K} pixel-sub-frames, "
-                         f"FP64, {nth} OpenMP threads, {dt:.1f} s"}
-        log(f"cpu oracle: {dt:.2f} s with {nth} threads; counters {counters}")
+        if args.workload == "medium":
+            cpu, counters = cpu_oracle(scenes, 1, nth, "full workload")
+        elif args.workload == "large":
+            cpu, counters = cpu_oracle(scenes, 128, nth, "large workload (8 rows; counters scaled to all rows)")
+        else:
+            cpu, counters = cpu_oracle(scenes, 32, nth, "all 32 instances (counters scaled to all rows)")
+        log(f"cpu oracle: {cpu['sample']}; counters {counters}")
 
-    fast = results["fast"]
-    km = fast["kernel_ms"]
+    fast = res["fast"]
+    km = fast["km"]
     roof = None
     if counters is not None:
         # dominant kernel: the longest of the four raster kernels
@@ -167,11 +251,12 @@ def main():
                 "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 6), "traffic": None,
                 "flop_per_launch": fl, "avg_launch_ms": round(ms, 5),
                 "all_kernels": {KERNEL_NAMES[k]: {"ms": round(km[k], 5),
-                                                  "tflops": round(flops(counters, KERNEL_COEF[k]) / (km[k] * 1e-3) / 1e12, 4)}
+                                                  "tflops": round(flops(counters, KERNEL_COEF[k]) / (km[k] * 1e-3)
+                                                                  / 1e12, 4)}
                                 for k in KERNEL_COEF}}
     out = {
         "metric": METRIC,
-        "value": round(fast["value"], 1),
+        "value": round(units / (fast["ms"] * 1e-3), 1),
         "unit": "pixel-subframes/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -182,12 +267,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{sc.name} fwd+bwd L2", "vertices": int(len(sc.verts)),
-                   "faces": int(len(sc.faces)), "resolution": f"{W}x{H}", "subframes": K,
-                   "segments": sc.num_segments, "solver": "fast", "chunk_len": args.chunk_len},
-        "recompute": {"value": round(results["recompute"]["value"], 1),
-                      "ms_per_step": round(results["recompute"]["ms"], 4)},
-        "fast_over_recompute": round(fast["value"] / results["recompute"]["value"], 4),
+        "config": config,
+        "recompute": {"value": round(units / (res["recompute"]["ms"] * 1e-3), 1),
+                      "ms_per_step": round(res["recompute"]["ms"], 4)},
+        "fast_over_recompute": round(res["recompute"]["ms"] / fast["ms"], 4),
         "kernel_ms": {k: round(v, 5) for k, v in km.items()},
         "roofline": roof,
         "cpu_baseline": cpu,
