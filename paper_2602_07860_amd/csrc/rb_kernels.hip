@@ -1309,7 +1309,7 @@ __device__ __forceinline__ void bg_item_fwd(const Inst &a, BgShared<T> &sh, int 
 }
 
 template <int T, int SOLVER>
-__global__ __launch_bounds__(64) void k_bg(const Inst *__restrict__ tab, int n, const int64_t *__restrict__ tprefix)
+__global__ __launch_bounds__(64, 4) void k_bg(const Inst *__restrict__ tab, int n, const int64_t *__restrict__ tprefix)
 {
     __shared__ BgShared<T> sh;
     const int lane = threadIdx.x & 63;
@@ -1802,7 +1802,7 @@ __device__ __forceinline__ void bg_item_bwd(const Inst &a, BgBwdShared<T> &sh, i
 }
 
 template <int T, int SOLVER>
-__global__ __launch_bounds__(64) void k_bg_bwd(const Inst *__restrict__ tab, int n)
+__global__ __launch_bounds__(64, 3) void k_bg_bwd(const Inst *__restrict__ tab, int n)
 {
     __shared__ BgBwdShared<T> sh;
     const int lane = threadIdx.x & 63;
