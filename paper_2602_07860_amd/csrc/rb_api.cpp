@@ -67,6 +67,10 @@ static rb_status make_plan(int32_t V, int32_t F, int32_t C, const rb_motion *mot
     // (silhouette tiles) spread over many waves, large enough to amortize a
     // task's set-up
     p.SL = opt->slice_len > 0 ? opt->slice_len : 64;
+    // Runs of items per lane in the background adjoint: longer runs share
+    // more of a lane's accumulation (fewer LDS atomics) when faces reach many
+    // pixels, i.e. when the background halo spans many pixels.
+    p.seq_bg = std::sqrt(dmax) * 0.5 * std::max(p.W, p.H) >= 12.0 ? 8 : 4;
     p.NS = std::max(C, 2);
     p.nfb = (F + 255) / 256;
     p.cap = opt->list_capacity > 0 ? opt->list_capacity

@@ -57,6 +57,15 @@ struct DevHeader {
     int64_t pad[3];
 };
 
+// The device pass sees an instance's buffers as global-memory pointers, so
+// that its loads, stores and atomics compile to global (not flat)
+// instructions; the host pass sees plain pointers of the same size.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define RB_G __attribute__((address_space(1)))
+#else
+#define RB_G
+#endif
+
 struct ViewArgs {
     float m[12];
     float tanf;
@@ -67,34 +76,35 @@ struct ViewArgs {
 // block of this instance in the launch of that kernel.
 struct Inst {
     // caller's arrays
-    const float *verts;
-    const int32_t *faces;
-    const float *attrs;
-    const float *model;
-    float *image;
-    const float *grad_image;
-    float *grad_verts;
-    float *grad_attrs;
+    const float RB_G *verts;
+    const int32_t RB_G *faces;
+    const float RB_G *attrs;
+    const float RB_G *model;
+    float RB_G *image;
+    const float RB_G *grad_image;
+    float RB_G *grad_verts;
+    float RB_G *grad_attrs;
     // workspace
-    DevHeader *hdr;
-    double2 *kf;         // [S+1][V] keyframe (x, y), kept in double: edge-on (sliver)
+    DevHeader RB_G *hdr;
+    double2 RB_G *kf;         // [S+1][V] keyframe (x, y), kept in double: edge-on (sliver)
                          // faces make barycentrics sensitive to 1e-8 position errors
-    float *kfz;          // [S+1][V] keyframe camera depth
-    int32_t *cnt;        // [2][NC][ntiles] list lengths (fg, bg)
-    int64_t *off;        // [2][NC][ntiles] list starts
-    int32_t *cur;        // [2][NC][ntiles] fill cursors
-    int64_t *bsum;       // scan block sums
-    uint32_t *list;      // entries: face << 8 | sub-frame mask
-    int32_t *vis_id;     // [ntiles][K][64] winner face; -1 uncovered; -4 outside the image
-    float *pix;          // [ntiles][K][NS][64] winner colour, or (sum log2(1 - A), #zero factors)
-    int32_t *tsl;        // [NC][ntiles] background tasks (list slices) per (chunk, tile)
-    int64_t *toff;       // [NC][ntiles] first task
-    int64_t *tbsum;      // task scan block sums
-    uint64_t *tasks;     // (chunk * ntiles + tile) << 32 | slice
-    float *gkf;          // [S+1][V][2] keyframe gradient
+    float RB_G *kfz;          // [S+1][V] keyframe camera depth
+    int32_t RB_G *cnt;        // [2][NC][ntiles] list lengths (fg, bg)
+    int64_t RB_G *off;        // [2][NC][ntiles] list starts
+    int32_t RB_G *cur;        // [2][NC][ntiles] fill cursors
+    int64_t RB_G *bsum;       // scan block sums
+    uint32_t RB_G *list;      // entries: face << 8 | sub-frame mask
+    int32_t RB_G *vis_id;     // [ntiles][K][64] winner face; -1 uncovered; -4 outside the image
+    float RB_G *pix;          // [ntiles][K][NS][64] winner colour, or (sum log2(1 - A), #zero factors)
+    int32_t RB_G *tsl;        // [NC][ntiles] background tasks (list slices) per (chunk, tile)
+    int64_t RB_G *toff;       // [NC][ntiles] first task
+    int64_t RB_G *tbsum;      // task scan block sums
+    uint64_t RB_G *tasks;     // (chunk * ntiles + tile) << 32 | slice
+    float RB_G *gkf;          // [S+1][V][2] keyframe gradient
     // sizes
     int V, F, C, S, K, W, H, tiles_x, tiles_y, ntiles;
     int CPS, NC, SL, NS, nfb;
+    int seq_bg;          // consecutive items per lane in the background adjoint
     int ntct;            // (chunk, tile) pairs = NC * ntiles
     int nblocks_scan, nblocks_tscan;
     int64_t cap, maxtasks, ncounts;
@@ -115,6 +125,7 @@ struct Plan {
     int CPS;        // chunks per segment
     int NC;         // chunks = S * CPS
     int SL;         // background list entries per task
+    int seq_bg;     // consecutive items per lane in the background adjoint
     int NS;         // per (pixel, sub-frame) value slots: colour, or log-sum and zero count
     int nfb;        // binning blocks per chunk
     int64_t cap;    // list capacity (entries)

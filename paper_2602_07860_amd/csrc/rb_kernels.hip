@@ -536,17 +536,17 @@ __global__ void k_scan3(const Inst *__restrict__ tab, int n, int which)
 //    (depth bits, face index), which keeps the lowest face index on exact
 //    depth ties; background items add log2(1 - A) with LDS float atomics.
 //
-// Backward, two kernels: k_fg_bwd per (chunk, tile): each (pixel, sub-frame)
-// finds its winning face among the staged entries through a small LDS hash
-// table and is queued for that entry; k_bg_bwd over the same background tasks
-// as the forward.  Per-entry LDS gradient slots collect the items'
-// contributions and are added to global memory with one atomic per non-zero
-// value and batch.
+// Backward, two kernels: k_fg_bwd per (chunk, tile) stages only the faces
+// that win a (pixel, sub-frame) with a colour gradient, found from the
+// visibility record; k_bg_bwd over the same background tasks as the forward.
+// A vertex-keyed LDS table collects the items' contributions and is added to
+// global memory with one atomic per non-zero value when it fills or the work
+// unit ends.
 
 constexpr int NCH = RB_MAX_CHANNELS;
 constexpr int NB = 32;              // list entries staged per batch
-constexpr int kHash = 128;          // face -> staged entry table (NB keys at most)
 constexpr int kVisOut = -4;         // vis_id of a pixel outside the image
+constexpr int kSeqFg = 4;           // consecutive items per lane in the foreground adjoint
 
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
@@ -900,6 +900,29 @@ __device__ __forceinline__ uint64_t rect_mask(float x0, float x1, float y0, floa
     return (row * 0x0101010101010101ull) & hi & ~lo;
 }
 
+// mask of the tile pixels whose centres lie within distance g of the box
+// [x0, x1] x [y0, y1] (anchor-local), with a margin of 0.05 pixel: a superset
+// of the pixels within distance g of a triangle inside the box, i.e. of the
+// pixels the background term can reach (the box grown by g, corners rounded)
+__device__ __forceinline__ uint64_t disc_mask(float x0, float x1, float y0, float y1, float g, float W, float H)
+{
+    const float ih = rcp(H), my = 0.1f * ih, g2 = g * g;
+    uint64_t m = 0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        // row r has centre dv = (7 - 2r)/H
+        const float v = (float)(7 - 2 * r) * ih;
+        const float dy = fmaxf(fmaxf(y0 - v, v - y1) - my, 0.0f);
+        const float h2 = fmaf(-dy, dy, g2);
+        const float hx = sqrtf(fmaxf(h2, 0.0f));
+        const float ca = fmaf(x0 - hx, W, 7.0f) * 0.5f - 0.05f, cb = fmaf(x1 + hx, W, 7.0f) * 0.5f + 0.05f;
+        const int c0 = max((int)ceilf(fmaxf(ca, -1.0f)), 0), c1 = min((int)floorf(fminf(cb, 8.0f)), 7);
+        const uint32_t row = (h2 >= 0.0f && c0 <= c1) ? ((0xffu >> (7 - c1 + c0)) << c0) : 0u;
+        m |= (uint64_t)row << (8 * r);
+    }
+    return m;
+}
+
 // position of the r-th set bit (r < popcount(m))
 __device__ __forceinline__ int select64(uint64_t m, int r)
 {
@@ -960,7 +983,7 @@ struct ItemShared {
     float rec[R_N][NB];  // staged entries, field-major
     uint64_t m[T][NB];   // per sub-frame and entry: pixels to evaluate
     uint64_t U[NB];      // union over the sub-frames
-    int pre[NB];         // number of the entry's first item
+    int pre[NB + 1];     // number of the entry's first item (entry nb: the batch's item count)
     int ne[NB];          // entries with at least one item, in order
     uint8_t flag[kWave];
 };
@@ -1034,7 +1057,9 @@ __device__ __forceinline__ int stage_items(const Inst &a, ItemShared<T> &sh, con
                     y0 = fminf(y0, yt);
                     y1 = fmaxf(y1, yt);
                 }
-                mj = rect_mask(x0, x1, y0, y1, grow, (float)a.W, (float)a.H) & allow[j];
+                mj = (kind == kRecBg ? disc_mask(x0, x1, y0, y1, grow, (float)a.W, (float)a.H)
+                                     : rect_mask(x0, x1, y0, y1, grow, (float)a.W, (float)a.H)) &
+                     allow[j];
             }
             sh.m[j][lane] = mj;
             U |= mj;
@@ -1056,10 +1081,8 @@ __device__ __forceinline__ int stage_items(const Inst &a, ItemShared<T> &sh, con
     const int incl = wave_incl_scan(cnt);
     pre = incl - cnt;
     const uint64_t bal = __ballot(cnt > 0);
-    if (cnt > 0) {
-        sh.pre[lane] = pre;
-        sh.ne[lane_rank(bal)] = lane;
-    }
+    if (lane <= nb) sh.pre[lane] = pre;
+    if (cnt > 0) sh.ne[lane_rank(bal)] = lane;
     lds_sync();
     return __shfl(incl, 63, 64);
 }
@@ -1087,6 +1110,54 @@ __device__ __forceinline__ void for_items(ItemShared<T> &sh, int total, int cnt,
     }
 }
 
+
+// Deal the batch's items out M consecutive ones per lane (64 M per round):
+// item(e, p) for each item of the lane's range in order, flush(e) after the
+// lane's last item of entry e.  An entry's items are consecutive, so a lane's
+// accumulators hold one entry at a time and reach the shared tables once per
+// (lane, entry) rather than once per item: far fewer LDS atomics, and far
+// fewer lanes adding to the same vertex at once.  pre is the lane's staged
+// entry's first item (the item count for lanes past the last entry);
+// sh.pre[0..nb] and sh.U must be in place.
+template <int T, class Fi, class Ff>
+__device__ __forceinline__ void for_items_seq(ItemShared<T> &sh, int M, int total, int pre, Fi &&item, Ff &&flush)
+{
+    const int lane = threadIdx.x & 63;
+    for (int rb = 0; rb < total; rb += kWave * M) {
+        const int i0 = rb + lane * M;
+        // entry holding item i0: the last staged entry whose first item is <= i0
+        int L = 0;
+#pragma unroll
+        for (int st = 32; st >= 1; st >>= 1) {
+            const int v = __shfl(pre, L + st, 64);
+            if (v <= i0) L += st;
+        }
+        if (i0 < total) {
+            const int i1 = min(i0 + M, total);
+            int e = L;
+            int end = sh.pre[e + 1];
+            uint64_t rem = sh.U[e];
+            int p = select64(rem, i0 - sh.pre[e]);
+            rem = p == 63 ? 0ull : rem & (~0ull << (p + 1));
+            for (int i = i0;;) {
+                item(e, p);
+                if (++i == i1) break;
+                if (i == end) {
+                    flush(e);
+                    // the next entry with items (one exists: i < total)
+                    do {
+                        ++e;
+                    } while (sh.pre[e + 1] == sh.pre[e]);
+                    end = sh.pre[e + 1];
+                    rem = sh.U[e];
+                }
+                p = __builtin_ctzll(rem);
+                rem &= rem - 1ull;
+            }
+            flush(e);
+        }
+    }
+}
 
 // next task of a persistent kernel (wave-uniform)
 __device__ __forceinline__ int64_t next_task(unsigned long long *ctr)
@@ -1320,7 +1391,7 @@ __global__ __launch_bounds__(64, 4) void k_bg(const Inst *__restrict__ tab, int 
         const int64_t lo = tprefix[ii], hi = tprefix[ii + 1];
         int64_t tb = lo + (((int64_t)blockIdx.x - lo) % G + G) % G;
         if (tb >= hi) continue;
-        const Inst a = tab[ii];
+        const Inst &a = tab[ii];
     for (; tb < hi; tb += G) {
         const int64_t t = tb - lo;
         const uint64_t task = a.tasks[t];
@@ -1411,7 +1482,6 @@ __global__ __launch_bounds__(64) void k_resolve(const Inst *__restrict__ tab, in
 // ---------------------------------------------------------------- adjoint
 
 
-__device__ __forceinline__ int hash_face(int f) { return (int)(((uint32_t)f * 2654435761u) >> 25); }
 
 // Gradient accumulation.  Item contributions go to an LDS table keyed by
 // vertex (open addressing): per vertex, dL/d(x, y) at the chunk's two
@@ -1419,27 +1489,32 @@ __device__ __forceinline__ int hash_face(int f) { return (int)(((uint32_t)f * 26
 // share vertices, so the table reaches global memory with one atomic per
 // (vertex, value) when it fills up or the task ends, instead of one per
 // (face, vertex, value).
-constexpr int kVT = 256;       // table slots
-constexpr int kVTLoad = 192;   // flush before a batch could push the table past this
-
-template <int NV>
+template <int NV, int NS>
 struct VTab {
-    int key[kVT];              // vertex index, -1 = empty
-    float g[NV][kVT];          // 0-3: keyframe s (x, y), keyframe s + 1 (x, y); 4+: attributes
+    static_assert((NS & (NS - 1)) == 0 && NS >= 64 && NS <= 1024, "slot count");
+    static constexpr int kSlots = NS;
+    static constexpr int kLoad = NS * 3 / 4;   // flush before a batch could push the table past this
+    static constexpr int kShift = NS == 64 ? 26 : NS == 128 ? 25 : NS == 256 ? 24 : NS == 512 ? 23 : 22;
+    int key[NS];               // vertex index, -1 = empty
+    float g[NV][NS];           // 0-3: keyframe s (x, y), keyframe s + 1 (x, y); 4+: attributes
 };
 
-template <int NV>
-__device__ __forceinline__ void vt_clear(VTab<NV> &vt)
+template <int NV, int NS>
+__device__ __forceinline__ void vt_clear(VTab<NV, NS> &vt)
 {
     const int lane = threadIdx.x & 63;
-    for (int i = lane; i < kVT; i += kWave) {
+    for (int i = lane; i < NS; i += kWave) {
         vt.key[i] = -1;
 #pragma unroll
         for (int k = 0; k < NV; ++k) vt.g[k][i] = 0.0f;
     }
 }
 
-__device__ __forceinline__ int hash_vertex(int v) { return (int)(((uint32_t)v * 2654435761u) >> 24); }
+template <int NS>
+__device__ __forceinline__ int hash_vertex(int v)
+{
+    return (int)(((uint32_t)v * 2654435761u) >> VTab<1, NS>::kShift);
+}
 
 __device__ __forceinline__ int wave_sum_int(int x)
 {
@@ -1450,9 +1525,9 @@ __device__ __forceinline__ int wave_sum_int(int x)
 
 // Replace the staged entries' vertex indices vs[e][q] (e < nb) by their table
 // slots, inserting new vertices; returns the number of new keys.  The caller
-// keeps the table below kVTLoad of kVT slots, so a free slot is always found.
-template <int NV>
-__device__ __forceinline__ int vt_bind(VTab<NV> &vt, int (*vs)[3], int nb)
+// keeps the table below kLoad of its NS slots, so a free slot is always found.
+template <int NV, int NS>
+__device__ __forceinline__ int vt_bind(VTab<NV, NS> &vt, int (*vs)[3], int nb)
 {
     const int lane = threadIdx.x & 63;
     int fresh = 0;
@@ -1461,15 +1536,15 @@ __device__ __forceinline__ int vt_bind(VTab<NV> &vt, int (*vs)[3], int nb)
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             const int v = vs[lane][q];
-            int h = hash_vertex(v), slot = -1;
-            for (int probe = 0; probe < kVT; ++probe) {
+            int h = hash_vertex<NS>(v), slot = -1;
+            for (int probe = 0; probe < NS; ++probe) {
                 const int old = atomicCAS(&vt.key[h], -1, v);
                 if (old == -1 || old == v) {
                     slot = h;
                     fresh += old == -1 ? 1 : 0;
                     break;
                 }
-                h = (h + 1) & (kVT - 1);
+                h = (h + 1) & (NS - 1);
             }
             vs[lane][q] = slot;
         }
@@ -1478,19 +1553,19 @@ __device__ __forceinline__ int vt_bind(VTab<NV> &vt, int (*vs)[3], int nb)
     return wave_sum_int(fresh);
 }
 
-template <int NV>
-__device__ __forceinline__ void vt_add(VTab<NV> &vt, int slot, int k, float v)
+template <int NV, int NS>
+__device__ __forceinline__ void vt_add(VTab<NV, NS> &vt, int slot, int k, float v)
 {
     if (v != 0.0f && slot >= 0) atomicAdd(&vt.g[k][slot], v);
 }
 
 // Add the table to the keyframe (and attribute) gradients and clear it.
-template <int NV>
-__device__ __forceinline__ void vt_flush(VTab<NV> &vt, int s, const Inst &a)
+template <int NV, int NS>
+__device__ __forceinline__ void vt_flush(VTab<NV, NS> &vt, int s, const Inst &a)
 {
     const int lane = threadIdx.x & 63;
     lds_sync();
-    for (int i = lane; i < kVT; i += kWave) {
+    for (int i = lane; i < NS; i += kWave) {
         const int v = vt.key[i];
         if (v < 0) continue;
 #pragma unroll
@@ -1514,25 +1589,25 @@ __device__ __forceinline__ void vt_flush(VTab<NV> &vt, int s, const Inst &a)
 
 template <int T>
 struct FgBwdShared {
-    ItemShared<T> it;
-    float at[3 * NCH][NB];    // staged entries' vertex attributes
-    int vslot[NB][3];         // staged entries' vertices: index, then vertex-table slot
-    VTab<4 + NCH> vt;
+    ItemShared<T> it;         // staged winning faces, their (pixel, sub-frame) masks and items
+    float at[3 * NCH][NB];    // their vertex attributes
+    int vslot[NB][3];         // their vertices: index, then vertex-table slot
+    VTab<4 + NCH, 128> vt;    // one batch of at most NB faces between flushes
     float gI[NCH][kWave];     // dL/dcolour of each pixel, already divided by K
-    int hkey[kHash];          // face -> staged entry (open addressing, -1 = empty)
-    int hval[kHash];
-    uint32_t q[T * kWave];    // items: entry | pixel << 8 | sub-frame << 16
 };
 
-// Foreground adjoint of one (pixel, sub-frame) whose winner is staged entry e:
-// colour = sum_i w_i c_i, dL/dw through the static solve (dw = -F^-1 dF w),
-// dL/dc_i = w_i dL/dcolour.
+// Foreground adjoint of one item (pixel p of staged face e, at every
+// sub-frame of the chunk where e wins p): colour = sum_i w_i c_i, dL/dw
+// through the static solve (dw = -F^-1 dF w), dL/dc_i = w_i dL/dcolour.
+// Adds to acc: per vertex q, dL/d(x_s, y_s, x_s+1, y_s+1) at 4 q and
+// dL/d(attributes) at 12 + NCH q.
 template <int T, int SOLVER>
-__device__ __forceinline__ void fg_item_bwd(const Inst &a, FgBwdShared<T> &sh, int e, int p, float tau, float tc)
+__device__ __forceinline__ void fg_item_bwd(const Inst &a, FgBwdShared<T> &sh, int e, int p, const float tau[T],
+                                            float tc, float (&acc)[12 + 3 * NCH])
 {
     const LdsRec r = lds_rec(sh.it, e);
     const float du = pix_du(p, a.inv_w), dv = pix_dv(p, a.inv_h);
-    float gI[NCH], gw[3];
+    float gI[NCH], gw[3], ws[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) gI[ch] = sh.gI[ch][p];
 #pragma unroll
@@ -1543,31 +1618,37 @@ __device__ __forceinline__ void fg_item_bwd(const Inst &a, FgBwdShared<T> &sh, i
     }
     Bary<SOLVER> bc;
     bc.setup(r, tc, du, dv);
-    const float t = tau - tc;
-    float N[3];
-    bc.eval(r, t, N);
-    const float invD = rcp(N[0] + N[1] + N[2]);
-    const float w[3] = {N[0] * invD, N[1] * invD, N[2] * invD};
-    float xt[3], yt[3];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        xt[q] = fmaf(t, r.at(R_DX + q), r.at(R_XC + q));
-        yt[q] = fmaf(t, r.at(R_DY + q), r.at(R_YC + q));
+    for (int j = 0; j < T; ++j) {
+        if (!((sh.it.m[j][e] >> p) & 1ull)) continue;
+        const float t = tau[j] - tc;
+        float N[3];
+        bc.eval(r, t, N);
+        const float invD = rcp(N[0] + N[1] + N[2]);
+        const float w[3] = {N[0] * invD, N[1] * invD, N[2] * invD};
+        float xt[3], yt[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            xt[q] = fmaf(t, r.at(R_DX + q), r.at(R_XC + q));
+            yt[q] = fmaf(t, r.at(R_DY + q), r.at(R_YC + q));
+        }
+        const float gxs = fmaf(gw[0], yt[1] - yt[2], fmaf(gw[1], yt[2] - yt[0], gw[2] * (yt[0] - yt[1]))) * invD;
+        const float gys = fmaf(gw[0], xt[2] - xt[1], fmaf(gw[1], xt[0] - xt[2], gw[2] * (xt[1] - xt[0]))) * invD;
+        const float t1 = tau[j], t0 = 1.0f - tau[j];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const float gx = -w[q] * gxs, gy = -w[q] * gys;
+            acc[q * 4 + 0] = fmaf(t0, gx, acc[q * 4 + 0]);
+            acc[q * 4 + 1] = fmaf(t0, gy, acc[q * 4 + 1]);
+            acc[q * 4 + 2] = fmaf(t1, gx, acc[q * 4 + 2]);
+            acc[q * 4 + 3] = fmaf(t1, gy, acc[q * 4 + 3]);
+            ws[q] += w[q];
+        }
     }
-    const float gxs = fmaf(gw[0], yt[1] - yt[2], fmaf(gw[1], yt[2] - yt[0], gw[2] * (yt[0] - yt[1]))) * invD;
-    const float gys = fmaf(gw[0], xt[2] - xt[1], fmaf(gw[1], xt[0] - xt[2], gw[2] * (xt[1] - xt[0]))) * invD;
-    const float t1 = tau, t0 = 1.0f - tau;
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        const float gx = -w[q] * gxs, gy = -w[q] * gys;
-        const int slot = sh.vslot[e][q];
-        vt_add(sh.vt, slot, 0, t0 * gx);
-        vt_add(sh.vt, slot, 1, t0 * gy);
-        vt_add(sh.vt, slot, 2, t1 * gx);
-        vt_add(sh.vt, slot, 3, t1 * gy);
+    for (int q = 0; q < 3; ++q)
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) vt_add(sh.vt, slot, 4 + ch, w[q] * gI[ch]);
-    }
+        for (int ch = 0; ch < NCH; ++ch) acc[12 + q * NCH + ch] = fmaf(ws[q], gI[ch], acc[12 + q * NCH + ch]);
 }
 
 template <int T, int SOLVER>
@@ -1575,7 +1656,7 @@ __global__ __launch_bounds__(64) void k_fg_bwd(const Inst *__restrict__ tab, int
 {
     __shared__ FgBwdShared<T> sh;
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
-    const Inst a = tab[inst_of<&Inst::b_fg>(tab, n, lb)];
+    const Inst &a = tab[inst_of<&Inst::b_fg>(tab, n, lb)];
     const int ct = lb - a.b_fg;
     const int lane = threadIdx.x & 63;
     if (a.hdr->error_bits & kHdrOverflow) return;
@@ -1591,93 +1672,117 @@ __global__ __launch_bounds__(64) void k_fg_bwd(const Inst *__restrict__ tab, int
         sh.gI[ch][lane] = v;
         gcol = gcol || v != 0.0f;
     }
+    // (pixel, sub-frame) pairs with a winner and a colour gradient
     int vid[T];
+    uint64_t pend[T];
     bool anyfg = false;
 #pragma unroll
     for (int j = 0; j < T; ++j) {
         vid[j] = j < ck.n ? a.vis_id[vis_index(a, g.tile, ck.k0 + j, lane)] : kVisOut;
-        anyfg = anyfg || __ballot(gcol && vid[j] >= 0) != 0ull;
+        pend[j] = __ballot(gcol && vid[j] >= 0);
+        anyfg = anyfg || pend[j] != 0ull;
     }
     if (!anyfg) return;
     vt_clear(sh.vt);
     int used = 0;
-    sh.hkey[lane] = -1;
-    sh.hkey[lane + kWave] = -1;
     float tau[T];
     uint32_t xbits;
     chunk_taus<T>(a, ck, tau, xbits);
     const float tc = chunk_centre<T>(tau, ck.n);
 
-    const int64_t beg = a.off[ct];
-    const int n_e = a.cnt[ct];
-    Pref pf = prefetch(a, beg, min(NB, n_e));
-    for (int base = 0; base < n_e; base += NB) {
-        const int nb = min(NB, n_e - base);
-        const Pref cur = pf;
-        if (base + NB < n_e) pf = prefetch(a, beg + base + NB, min(NB, n_e - base - NB));
-        if (used + 3 * nb > kVTLoad) {
-            vt_flush(sh.vt, ck.s, a);
-            used = 0;
-        }
-        lds_sync();
-        int hb = -1;
-        if (lane < nb) {
-            const int f = (int)(cur.ent >> 8);
-            const int *vq = cur.v;
-            FaceRec r;
-            stage_rec(a, f, vq, ck.s, g.ua, g.va, tc, kRecGeom, r);
-            store_rec(sh.it, lane, r);
+    // Only the winning faces are staged (the list is not walked): the first
+    // pending pair's face becomes the next entry and takes every pending pair
+    // of that face, as its per-sub-frame pixel masks; a batch of NB entries
+    // (or the last one) is staged and its items (entry, pixel) are run.
+    uint64_t mown[T];         // masks of entry `lane` of the batch being gathered
 #pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                sh.vslot[lane][q] = vq[q];
+    for (int j = 0; j < T; ++j) mown[j] = 0ull;
+    int sel = 0;              // its face
+    int ne = 0;
+    for (;;) {
+        int j0 = -1, v0 = 0;
 #pragma unroll
-                for (int ch = 0; ch < NCH; ++ch)
-                    sh.at[q * NCH + ch][lane] = ch < a.C ? a.attrs[(size_t)vq[q] * a.C + ch] : 0.0f;
+        for (int j = 0; j < T; ++j)
+            if (j0 < 0 && pend[j] != 0ull) {
+                j0 = j;
+                v0 = vid[j];
             }
-            // faces are unique within a list and NB < kHash: an empty
-            // bucket is always found
-            int h = hash_face(f);
-            for (int probe = 0; probe < kHash; ++probe) {
-                if (atomicCAS(&sh.hkey[h], -1, f) == -1) {
-                    hb = h;
-                    break;
+        if (j0 >= 0) {
+            uint64_t pm = 0;
+#pragma unroll
+            for (int j = 0; j < T; ++j)
+                if (j == j0) pm = pend[j];
+            const int f = __shfl(v0, __builtin_ctzll(pm), 64);
+#pragma unroll
+            for (int j = 0; j < T; ++j) {
+                const uint64_t hit = __ballot(((pend[j] >> lane) & 1ull) && vid[j] == f);
+                pend[j] &= ~hit;
+                if (lane == ne) mown[j] = hit;
+            }
+            if (lane == ne) sel = f;
+            ++ne;
+        }
+        if (ne == NB || (j0 < 0 && ne > 0)) {
+            if (used + 3 * ne > sh.vt.kLoad) {
+                vt_flush(sh.vt, ck.s, a);
+                used = 0;
+            }
+            lds_sync();
+            int cnt = 0;
+            if (lane < ne) {
+                int vq[3];
+                face_verts(a, sel, vq);
+                FaceRec r;
+                stage_rec(a, sel, vq, ck.s, g.ua, g.va, tc, kRecGeom, r);
+                store_rec(sh.it, lane, r);
+                uint64_t U = 0;
+#pragma unroll
+                for (int j = 0; j < T; ++j) {
+                    sh.it.m[j][lane] = mown[j];
+                    U |= mown[j];
                 }
-                h = (h + 1) & (kHash - 1);
-            }
-            if (hb >= 0) sh.hval[hb] = lane;
-        }
-        used += vt_bind(sh.vt, sh.vslot, nb);
-        int qn = 0;
+                sh.it.U[lane] = U;
+                cnt = __popcll(U);
 #pragma unroll
-        for (int j = 0; j < T; ++j) {
-            int sl = -1;
-            if (gcol && vid[j] >= 0) {
-                int h = hash_face(vid[j]);
-                for (int probe = 0; probe < kHash; ++probe) {
-                    const int k = sh.hkey[h];
-                    if (k == vid[j]) {
-                        sl = sh.hval[h];
-                        break;
+                for (int q = 0; q < 3; ++q) {
+                    sh.vslot[lane][q] = vq[q];
+#pragma unroll
+                    for (int ch = 0; ch < NCH; ++ch)
+                        sh.at[q * NCH + ch][lane] = ch < a.C ? a.attrs[(size_t)vq[q] * a.C + ch] : 0.0f;
+                }
+            }
+            const int incl = wave_incl_scan(cnt);
+            const int pre = incl - cnt;
+            if (lane <= ne) sh.it.pre[lane] = pre;
+            const int total = __shfl(incl, 63, 64);
+            used += vt_bind(sh.vt, sh.vslot, ne);
+            float acc[12 + 3 * NCH];
+#pragma unroll
+            for (int k = 0; k < 12 + 3 * NCH; ++k) acc[k] = 0.0f;
+            for_items_seq(
+                sh.it, kSeqFg, total, pre, [&](int e, int p) { fg_item_bwd<T, SOLVER>(a, sh, e, p, tau, tc, acc); },
+                [&](int e) {
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        const int slot = sh.vslot[e][q];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            vt_add(sh.vt, slot, k, acc[q * 4 + k]);
+                            acc[q * 4 + k] = 0.0f;
+                        }
+#pragma unroll
+                        for (int ch = 0; ch < NCH; ++ch) {
+                            vt_add(sh.vt, slot, 4 + ch, acc[12 + q * NCH + ch]);
+                            acc[12 + q * NCH + ch] = 0.0f;
+                        }
                     }
-                    if (k == -1) break;
-                    h = (h + 1) & (kHash - 1);
-                }
-            }
-            const uint64_t bal = __ballot(sl >= 0);
-            if (sl >= 0) sh.q[qn + lane_rank(bal)] = (uint32_t)sl | ((uint32_t)lane << 8) | ((uint32_t)j << 16);
-            qn += __popcll(bal);
+                });
+            lds_sync();
+#pragma unroll
+            for (int j = 0; j < T; ++j) mown[j] = 0ull;
+            ne = 0;
         }
-        lds_sync();
-        for (int rb = 0; rb < qn; rb += kWave) {
-            if (rb + lane < qn) {
-                const uint32_t item = sh.q[rb + lane];
-                int X;
-                const float tj = chunk_tau(a, ck, (int)(item >> 16), X);
-                fg_item_bwd<T, SOLVER>(a, sh, (int)(item & 0xffu), (int)((item >> 8) & 0xffu), tj, tc);
-            }
-        }
-        lds_sync();
-        if (hb >= 0) sh.hkey[hb] = -1;
+        if (j0 < 0) break;
     }
     vt_flush(sh.vt, ck.s, a);
 }
@@ -1688,7 +1793,7 @@ template <int T>
 struct BgBwdShared {
     ItemShared<T> it;
     int vslot[NB][3];         // staged entries' vertices: index, then vertex-table slot
-    VTab<4> vt;
+    VTab<4, 256> vt;
     float P[T][kWave];        // forward product over non-zero factors
     int nz[T][kWave];
     float gal[kWave];         // dL/dalpha of each pixel, already divided by K
@@ -1697,18 +1802,17 @@ struct BgBwdShared {
 // Background adjoint of one item: dalpha/dA_j = prod_{m != j}(1 - A_m),
 // dA/dd = -A/delta, then the chain through d = |p - p*|^2, the closest point
 // (edge parameter where unclamped), q = F(X) w and w(tau) (dw = -F^-1 dF w).
+// Adds dL/d(keyframe s, s+1 positions) of the entry's vertices to gK
+// (vertex q: x_s, y_s, x_s+1, y_s+1 at 4 q).
 template <int T, int SOLVER>
 __device__ __forceinline__ void bg_item_bwd(const Inst &a, BgBwdShared<T> &sh, int e, int p,
-                                            const float tau[T], uint32_t xbits, float tc)
+                                            const float tau[T], uint32_t xbits, float tc, float (&gK)[12])
 {
     const LdsRec r = lds_rec(sh.it, e);
     const float du = pix_du(p, a.inv_w), dv = pix_dv(p, a.inv_h);
     const float galpha = sh.gal[p];
     Bary<SOLVER> bc;
     bc.setup(r, tc, du, dv);
-    float gK[12];
-#pragma unroll
-    for (int q = 0; q < 12; ++q) gK[q] = 0.0f;
 #pragma unroll
     for (int j = 0; j < T; ++j) {
         if (!((sh.it.m[j][e] >> p) & 1ull)) continue;
@@ -1793,12 +1897,6 @@ __device__ __forceinline__ void bg_item_bwd(const Inst &a, BgBwdShared<T> &sh, i
             gK[q * 4 + 3] += fmaf(t1, gty[q], X ? gky[q] : 0.0f);
         }
     }
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        const int slot = sh.vslot[e][q];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) vt_add(sh.vt, slot, k, gK[q * 4 + k]);
-    }
 }
 
 template <int T, int SOLVER>
@@ -1811,7 +1909,7 @@ __global__ __launch_bounds__(64, 3) void k_bg_bwd(const Inst *__restrict__ tab, 
     // gradient drop out), so waves take them from a counter per instance,
     // moving through the instances in order
     for (int ii = 0; ii < n; ++ii) {
-        const Inst a = tab[ii];
+        const Inst &a = tab[ii];
         if (a.hdr->error_bits & kHdrOverflow) continue;
         const int64_t ntasks = min(a.hdr->ntasks, a.maxtasks);
     for (;;) {
@@ -1861,7 +1959,7 @@ __global__ __launch_bounds__(64, 3) void k_bg_bwd(const Inst *__restrict__ tab, 
             const int nb = min(NB, e1 - base);
             const Pref cur = pf;
             if (base + NB < e1) pf = prefetch(a, beg + base + NB, min(NB, e1 - base - NB));
-            if (used + 3 * nb > kVTLoad) {
+            if (used + 3 * nb > sh.vt.kLoad) {
                 vt_flush(sh.vt, ck.s, a);
                 used = 0;
             }
@@ -1869,8 +1967,22 @@ __global__ __launch_bounds__(64, 3) void k_bg_bwd(const Inst *__restrict__ tab, 
             const int total = stage_items<T>(a, sh.it, cur, nb, ck.s, g, tc, tau, kRecBg, a.halo, bgm, nullptr,
                                              sh.vslot, cnt, pre);
             used += vt_bind(sh.vt, sh.vslot, nb);
-            for_items<T>(sh.it, total, cnt, pre,
-                         [&](int e, int p) { bg_item_bwd<T, SOLVER>(a, sh, e, p, tau, xbits, tc); });
+            float gK[12];
+#pragma unroll
+            for (int q = 0; q < 12; ++q) gK[q] = 0.0f;
+            for_items_seq(
+                sh.it, a.seq_bg, total, pre, [&](int e, int p) { bg_item_bwd<T, SOLVER>(a, sh, e, p, tau, xbits, tc, gK); },
+                [&](int e) {
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        const int slot = sh.vslot[e][q];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            vt_add(sh.vt, slot, k, gK[q * 4 + k]);
+                            gK[q * 4 + k] = 0.0f;
+                        }
+                    }
+                });
         }
         if (used > 0) vt_flush(sh.vt, ck.s, a);
     }
@@ -1944,29 +2056,29 @@ static Inst make_inst(const Plan &p, const Io &io, char *base, const Grids &star
 {
     Inst a;
     std::memset(&a, 0, sizeof(a));
-    a.verts = io.verts;
-    a.faces = io.faces;
-    a.attrs = io.attrs;
-    a.model = io.model;
-    a.image = io.image;
-    a.grad_image = io.grad_image;
-    a.grad_verts = io.grad_verts;
-    a.grad_attrs = io.grad_attrs;
-    a.hdr = (DevHeader *)(base + p.o_hdr);
-    a.kf = (double2 *)(base + p.o_kf);
-    a.kfz = (float *)(base + p.o_kfz);
-    a.cnt = (int32_t *)(base + p.o_cnt);
-    a.off = (int64_t *)(base + p.o_off);
-    a.cur = (int32_t *)(base + p.o_cur);
-    a.bsum = (int64_t *)(base + p.o_bsum);
-    a.list = (uint32_t *)(base + p.o_list);
-    a.vis_id = (int32_t *)(base + p.o_vis_id);
-    a.pix = (float *)(base + p.o_pix);
-    a.tsl = (int32_t *)(base + p.o_tsl);
-    a.toff = (int64_t *)(base + p.o_toff);
-    a.tbsum = (int64_t *)(base + p.o_tbsum);
-    a.tasks = (uint64_t *)(base + p.o_tasks);
-    a.gkf = (float *)(base + p.o_gkf);
+    a.verts = (decltype(a.verts))io.verts;
+    a.faces = (decltype(a.faces))io.faces;
+    a.attrs = (decltype(a.attrs))io.attrs;
+    a.model = (decltype(a.model))io.model;
+    a.image = (decltype(a.image))io.image;
+    a.grad_image = (decltype(a.grad_image))io.grad_image;
+    a.grad_verts = (decltype(a.grad_verts))io.grad_verts;
+    a.grad_attrs = (decltype(a.grad_attrs))io.grad_attrs;
+    a.hdr = (decltype(a.hdr))(base + p.o_hdr);
+    a.kf = (decltype(a.kf))(base + p.o_kf);
+    a.kfz = (decltype(a.kfz))(base + p.o_kfz);
+    a.cnt = (decltype(a.cnt))(base + p.o_cnt);
+    a.off = (decltype(a.off))(base + p.o_off);
+    a.cur = (decltype(a.cur))(base + p.o_cur);
+    a.bsum = (decltype(a.bsum))(base + p.o_bsum);
+    a.list = (decltype(a.list))(base + p.o_list);
+    a.vis_id = (decltype(a.vis_id))(base + p.o_vis_id);
+    a.pix = (decltype(a.pix))(base + p.o_pix);
+    a.tsl = (decltype(a.tsl))(base + p.o_tsl);
+    a.toff = (decltype(a.toff))(base + p.o_toff);
+    a.tbsum = (decltype(a.tbsum))(base + p.o_tbsum);
+    a.tasks = (decltype(a.tasks))(base + p.o_tasks);
+    a.gkf = (decltype(a.gkf))(base + p.o_gkf);
     a.V = p.V;
     a.F = p.F;
     a.C = p.C;
@@ -1980,6 +2092,7 @@ static Inst make_inst(const Plan &p, const Io &io, char *base, const Grids &star
     a.CPS = p.CPS;
     a.NC = p.NC;
     a.SL = p.SL;
+    a.seq_bg = p.seq_bg;
     a.NS = p.NS;
     a.nfb = p.nfb;
     a.ntct = (int)p.ntct;
