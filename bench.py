@@ -8,7 +8,9 @@ Workloads (synthetic, seeded; see paper_2602_07860_amd/workloads.py):
     about a seeded axis cut into S = 36 linear segments; L2 loss against the
     render of a second seeded displacement.
   large: nu=64 (40962 V / 81920 F), multi-octave displacement, 1024x1024,
-    K = 512, 5 revolutions + 200 px translation in S = 60 segments.
+    K = 512, 5 revolutions + 200 px translation in S = 60 segments, run as a
+    shape-recovery loop: every step also takes an Adam step on the vertex
+    positions and colours (the loop is timed end to end, --steps steps).
   batch: 32 instances of mixed sizes, resolutions {128, 256, 512}^2,
     K in [32, 256], half translation / half rotation, all in one launch
     sequence captured in a graph and replayed; chunk and slice lengths from
@@ -71,9 +73,10 @@ def kernel_ms(prof):
             "vertex_grad": prof.vertex_grad_ms / b}
 
 
-def timed(fn, steps, B, torch, phases=True):
+def timed(fn, steps, B, torch, phases=True, phase_steps=None):
     """Average ms of fn() over `steps` calls (device events) and, optionally,
-    the per-kernel phases of a second pass of `steps` calls."""
+    the per-kernel phases of a second pass of `phase_steps` (default `steps`)
+    calls."""
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -85,7 +88,7 @@ def timed(fn, steps, B, torch, phases=True):
     if not phases:
         return ms, None
     B.rb_profile_enable(True)
-    for _ in range(steps):
+    for _ in range(phase_steps or steps):
         fn()
     torch.cuda.synchronize()
     prof = B.rb_profile_read()
@@ -93,7 +96,7 @@ def timed(fn, steps, B, torch, phases=True):
     return ms, kernel_ms(prof)
 
 
-def run_single(sc, tg, args, torch, B, R):
+def run_single(sc, tg, args, torch, B, R, adam=False):
     dev = "cuda:0"
     st = R.scene_tensors(sc, dev)
     tt = R.scene_tensors(tg, dev)
@@ -106,16 +109,24 @@ def run_single(sc, tg, args, torch, B, R):
     res = {}
     for solver in ("fast", "recompute"):
         box = {"o": opts(solver, check=True)}
+        # shape recovery: the same start for both solvers; the geometry moves,
+        # so every forward checks its bin lists (one header read)
+        verts, attrs = st.verts.clone(), st.attrs.clone()
+        opt = torch.optim.Adam([verts, attrs], lr=1e-3) if adam else None
 
         def step():
-            img, state = R.render_forward(st.verts, st.faces, st.attrs, st.model, st.camera, box["o"])
-            gv, ga = R.render_backward(st.verts, st.faces, st.attrs, st.model, state, 2.0 * (img - target))
+            img, state = R.render_forward(verts, st.faces, attrs, st.model, st.camera, box["o"])
+            gv, ga = R.render_backward(verts, st.faces, attrs, st.model, state, 2.0 * (img - target))
+            if opt is not None:
+                verts.grad, attrs.grad = gv, ga
+                opt.step()
             box["out"] = (img, gv, ga, state)
 
         for _ in range(max(1, args.warmup)):
             step()
-            box["o"] = opts(solver, check=False)
-        ms, km = timed(step, args.steps, B, torch)
+            if not adam:
+                box["o"] = opts(solver, check=False)
+        ms, km = timed(step, args.steps, B, torch, phase_steps=min(args.steps, 3) if adam else None)
         img, gv, ga, state = box["out"]
         h = B.rb_read_header(state.workspace.data_ptr(), torch.cuda.current_stream().cuda_stream)
         if h.error_bits:
@@ -216,8 +227,10 @@ def main():
         sc = wl.make_workload(wl.MEDIUM if args.workload == "medium" else wl.LARGE)
         scenes = [sc]
         tg = wl.make_target(sc, 2)
-        res = run_single(sc, tg, args, torch, B, R)
-        config = {"workload": f"{sc.name} fwd+bwd L2", "vertices": int(len(sc.verts)),
+        adam = args.workload == "large"
+        res = run_single(sc, tg, args, torch, B, R, adam=adam)
+        config = {"workload": f"{sc.name} fwd+bwd L2" + (f", {args.steps}-step Adam shape-recovery loop" if adam else ""),
+                  "vertices": int(len(sc.verts)),
                   "faces": int(len(sc.faces)), "resolution": f"{sc.width}x{sc.height}",
                   "subframes": sc.num_subframes, "segments": sc.num_segments, "solver": "fast",
                   "chunk_len": args.chunk_len}

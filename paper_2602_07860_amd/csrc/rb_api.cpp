@@ -67,10 +67,14 @@ static rb_status make_plan(int32_t V, int32_t F, int32_t C, const rb_motion *mot
     // (silhouette tiles) spread over many waves, large enough to amortize a
     // task's set-up
     p.SL = opt->slice_len > 0 ? opt->slice_len : 64;
-    // Runs of items per lane in the background adjoint: longer runs share
-    // more of a lane's accumulation (fewer LDS atomics) when faces reach many
-    // pixels, i.e. when the background halo spans many pixels.
-    p.seq_bg = std::sqrt(dmax) * 0.5 * std::max(p.W, p.H) >= 12.0 ? 8 : 4;
+    // When the background halo spans many pixels, faces reach many pixels of
+    // a tile: longer per-lane runs of items pay off in the background adjoint
+    // (fewer LDS atomics per item), and the background forward groups its
+    // items by pixel so that runs add up one pixel's factors (measured on
+    // 256^2 with a 5.5-pixel halo and 1024^2 with a 22-pixel halo).
+    const bool wide_halo = std::sqrt(dmax) * 0.5 * std::max(p.W, p.H) >= 12.0;
+    p.seq_bg = wide_halo ? 8 : 4;
+    p.wide = wide_halo;
     p.NS = std::max(C, 2);
     p.nfb = (F + 255) / 256;
     p.cap = opt->list_capacity > 0 ? opt->list_capacity
@@ -125,6 +129,8 @@ static rb_status make_batch(const std::vector<Plan> &plans, Batch &bt)
     if (bt.n <= 0) return RB_EINVAL;
     bt.T = plans[0].T;
     bt.solver = plans[0].solver;
+    bt.wide = true;
+    for (const Plan &p : plans) bt.wide = bt.wide && p.wide;
     bt.plans = plans;
     bt.base.resize(bt.n);
     Grids g{};

@@ -126,6 +126,7 @@ struct Plan {
     int NC;         // chunks = S * CPS
     int SL;         // background list entries per task
     int seq_bg;     // consecutive items per lane in the background adjoint
+    bool wide;      // background halo of 12 pixels or more (faces reach many pixels of a tile)
     int NS;         // per (pixel, sub-frame) value slots: colour, or log-sum and zero count
     int nfb;        // binning blocks per chunk
     int64_t cap;    // list capacity (entries)
@@ -147,6 +148,7 @@ struct Grids {
 // workspace starts; the table of Inst and the task numbering follow them.
 struct Batch {
     int n, T, solver;
+    bool wide;      // every instance has a wide halo: background kernels built for long item runs
     std::vector<Plan> plans;
     std::vector<size_t> base;
     Grids g;

@@ -222,8 +222,10 @@ __device__ __forceinline__ void face_tiles(const float x[3], const float y[3], c
 // window.  Per-tile counts are gathered with LDS atomics over that window and
 // reach global memory with one atomic per (window tile, list kind); in the
 // fill pass each window tile reserves one contiguous range of its list and
-// the block's entries go there at LDS-atomic ranks.  A block whose window
-// does not fit in LDS uses one global atomic per entry instead.
+// the block's entries go there at LDS-atomic ranks.  A window larger than
+// the LDS counters (fast motion: a chunk's faces sweep far) is taken in bands
+// of rows; only a window whose single row does not fit uses one global atomic
+// per entry.
 constexpr int kBinThreads = 256;
 constexpr int kBinWin = 2048;   // window counters: 2 list kinds x tiles
 
@@ -308,18 +310,15 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const Inst *__restrict__ ta
     }
     __syncthreads();
     const int wx0 = win[0], wy0 = win[2];
-    const int ww = win[1] - wx0 + 1, wh = win[3] - wy0 + 1;
+    const int ww = win[1] - wx0 + 1;
     if (win[0] > win[1]) return;   // no face of the block touches the image (block-uniform)
-    const int nwt = ww * wh;
-    const bool lds = 2 * (int64_t)nwt <= kBinWin;
-    if (lds) {
-        for (int i = threadIdx.x; i < 2 * nwt; i += kBinThreads) lcnt[i] = 0;
-        __syncthreads();
-    }
-    // visit the entries of this thread's face: fn(list kind, tile, mask, window slot)
-    auto visit = [&](auto &&fn) {
+    auto gidx = [&](int L, int tile) { return ((int64_t)L * a.NC + c) * a.ntiles + tile; };
+    const uint32_t fbits = (uint32_t)f << 8;
+    // the entries of this thread's face in window rows [y0, y1]:
+    // fn(list kind, tile, mask, slot of the tile in the band)
+    auto visit = [&](int y0, int y1, int nwt, auto &&fn) {
         if (!has) return;
-        for (int ty = u.uy0; ty <= u.uy1; ++ty) {
+        for (int ty = max(u.uy0, y0); ty <= min(u.uy1, y1); ++ty) {
             for (int tx = u.ux0; tx <= u.ux1; ++tx) {
                 uint32_t fm = 0, bm = 0;
 #pragma unroll
@@ -328,53 +327,54 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const Inst *__restrict__ ta
                     if (tx >= btx0[j] && tx <= btx1[j] && ty >= bty0[j] && ty <= bty1[j]) bm |= 1u << j;
                 }
                 const int tile = ty * a.tiles_x + tx;
-                const int w = (ty - wy0) * ww + (tx - wx0);
+                const int w = (ty - y0) * ww + (tx - wx0);
                 if (fm) fn(0, tile, fm, w);
                 if (bm) fn(1, tile, bm, nwt + w);
             }
         }
     };
-    auto gidx = [&](int L, int tile) { return ((int64_t)L * a.NC + c) * a.ntiles + tile; };
-    if (pass == 0) {
-        if (lds) {
-            visit([&](int, int, uint32_t, int w) { atomicAdd(&lcnt[w], 1); });
-            __syncthreads();
-            for (int i = threadIdx.x; i < 2 * nwt; i += kBinThreads) {
-                const int n = lcnt[i];
-                if (!n) continue;
-                const int L = i >= nwt, w = i - L * nwt;
-                const int tile = (wy0 + w / ww) * a.tiles_x + wx0 + w % ww;
-                atomicAdd(&a.cnt[gidx(L, tile)], n);
-            }
+    if (2 * ww > kBinWin) {
+        // a window row does not fit in LDS: one global atomic per entry
+        if (pass == 0) {
+            visit(u.uy0, u.uy1, 0, [&](int L, int tile, uint32_t, int) { atomicAdd(&a.cnt[gidx(L, tile)], 1); });
         } else {
-            visit([&](int L, int tile, uint32_t, int) { atomicAdd(&a.cnt[gidx(L, tile)], 1); });
-        }
-    } else {
-        const uint32_t fbits = (uint32_t)f << 8;
-        if (lds) {
-            visit([&](int, int, uint32_t, int w) { atomicAdd(&lcnt[w], 1); });
-            __syncthreads();
-            for (int i = threadIdx.x; i < 2 * nwt; i += kBinThreads) {
-                const int n = lcnt[i];
-                if (!n) continue;
-                const int L = i >= nwt, w = i - L * nwt;
-                const int tile = (wy0 + w / ww) * a.tiles_x + wx0 + w % ww;
-                const int64_t g = gidx(L, tile);
-                lbase[i] = a.off[g] + atomicAdd(&a.cur[g], n);
-                lcnt[i] = 0;
-            }
-            __syncthreads();
-            visit([&](int, int, uint32_t m, int w) {
-                const int64_t pos = lbase[w] + atomicAdd(&lcnt[w], 1);
-                if (pos < a.cap) a.list[pos] = fbits | m;
-            });
-        } else {
-            visit([&](int L, int tile, uint32_t m, int) {
+            visit(u.uy0, u.uy1, 0, [&](int L, int tile, uint32_t m, int) {
                 const int64_t g = gidx(L, tile);
                 const int64_t pos = a.off[g] + atomicAdd(&a.cur[g], 1);
                 if (pos < a.cap) a.list[pos] = fbits | m;
             });
         }
+        return;
+    }
+    // bands of window rows whose counters fit in LDS (usually one band)
+    const int band = kBinWin / (2 * ww);
+    for (int y0 = wy0; y0 <= win[3]; y0 += band) {
+        const int y1 = min(win[3], y0 + band - 1);
+        const int nwt = ww * (y1 - y0 + 1);
+        for (int i = threadIdx.x; i < 2 * nwt; i += kBinThreads) lcnt[i] = 0;
+        __syncthreads();
+        visit(y0, y1, nwt, [&](int, int, uint32_t, int w) { atomicAdd(&lcnt[w], 1); });
+        __syncthreads();
+        for (int i = threadIdx.x; i < 2 * nwt; i += kBinThreads) {
+            const int n = lcnt[i];
+            if (!n) continue;
+            const int L = i >= nwt, w = i - L * nwt;
+            const int64_t g = gidx(L, (y0 + w / ww) * a.tiles_x + wx0 + w % ww);
+            if (pass == 0) {
+                atomicAdd(&a.cnt[g], n);
+            } else {
+                lbase[i] = a.off[g] + atomicAdd(&a.cur[g], n);
+                lcnt[i] = 0;
+            }
+        }
+        if (pass == 1) {
+            __syncthreads();
+            visit(y0, y1, nwt, [&](int, int, uint32_t m, int w) {
+                const int64_t pos = lbase[w] + atomicAdd(&lcnt[w], 1);
+                if (pos < a.cap) a.list[pos] = fbits | m;
+            });
+        }
+        __syncthreads();
     }
 }
 
@@ -547,6 +547,7 @@ constexpr int NCH = RB_MAX_CHANNELS;
 constexpr int NB = 32;              // list entries staged per batch
 constexpr int kVisOut = -4;         // vis_id of a pixel outside the image
 constexpr int kSeqFg = 4;           // consecutive items per lane in the foreground adjoint
+constexpr int kSeqBgFwd = 4;        // and in the background forward (grouped by pixel)
 
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
@@ -1111,21 +1112,22 @@ __device__ __forceinline__ void for_items(ItemShared<T> &sh, int total, int cnt,
 }
 
 
-// Deal the batch's items out M consecutive ones per lane (64 M per round):
-// item(e, p) for each item of the lane's range in order, flush(e) after the
-// lane's last item of entry e.  An entry's items are consecutive, so a lane's
-// accumulators hold one entry at a time and reach the shared tables once per
-// (lane, entry) rather than once per item: far fewer LDS atomics, and far
-// fewer lanes adding to the same vertex at once.  pre is the lane's staged
-// entry's first item (the item count for lanes past the last entry);
-// sh.pre[0..nb] and sh.U must be in place.
-template <int T, class Fi, class Ff>
-__device__ __forceinline__ void for_items_seq(ItemShared<T> &sh, int M, int total, int pre, Fi &&item, Ff &&flush)
+// Deal a batch's items out M consecutive ones per lane (64 M per round).
+// Items are grouped by key (a staged entry, or a pixel): key k owns items
+// kpre[k] .. kpre[k+1] - 1, one per set bit of kmask[k] in increasing order.
+// item(k, b) runs for each item of the lane's range in order and flush(k)
+// after the lane's last item of key k, so a lane's accumulators hold one key
+// at a time and reach shared memory once per (lane, key) rather than once
+// per item: far fewer LDS atomics, and far fewer lanes adding to the same
+// address at once.  pre is kpre[lane] (the item count past the last key).
+template <class Fi, class Ff>
+__device__ __forceinline__ void for_runs(int M, int total, int pre, const int *kpre, const uint64_t *kmask, Fi &&item,
+                                         Ff &&flush)
 {
     const int lane = threadIdx.x & 63;
     for (int rb = 0; rb < total; rb += kWave * M) {
         const int i0 = rb + lane * M;
-        // entry holding item i0: the last staged entry whose first item is <= i0
+        // key holding item i0: the last key whose first item is <= i0
         int L = 0;
 #pragma unroll
         for (int st = 32; st >= 1; st >>= 1) {
@@ -1134,30 +1136,31 @@ __device__ __forceinline__ void for_items_seq(ItemShared<T> &sh, int M, int tota
         }
         if (i0 < total) {
             const int i1 = min(i0 + M, total);
-            int e = L;
-            int end = sh.pre[e + 1];
-            uint64_t rem = sh.U[e];
-            int p = select64(rem, i0 - sh.pre[e]);
-            rem = p == 63 ? 0ull : rem & (~0ull << (p + 1));
+            int k = L;
+            int end = kpre[k + 1];
+            uint64_t rem = kmask[k];
+            int b = select64(rem, i0 - kpre[k]);
+            rem = b == 63 ? 0ull : rem & (~0ull << (b + 1));
             for (int i = i0;;) {
-                item(e, p);
+                item(k, b);
                 if (++i == i1) break;
                 if (i == end) {
-                    flush(e);
-                    // the next entry with items (one exists: i < total)
+                    flush(k);
+                    // the next key with items (one exists: i < total)
                     do {
-                        ++e;
-                    } while (sh.pre[e + 1] == sh.pre[e]);
-                    end = sh.pre[e + 1];
-                    rem = sh.U[e];
+                        ++k;
+                    } while (kpre[k + 1] == kpre[k]);
+                    end = kpre[k + 1];
+                    rem = kmask[k];
                 }
-                p = __builtin_ctzll(rem);
+                b = __builtin_ctzll(rem);
                 rem &= rem - 1ull;
             }
-            flush(e);
+            flush(k);
         }
     }
 }
+
 
 // next task of a persistent kernel (wave-uniform)
 __device__ __forceinline__ int64_t next_task(unsigned long long *ctr)
@@ -1349,12 +1352,15 @@ struct BgShared {
     ItemShared<T> it;
     float lsum[T][kWave];   // sum of log2(1 - A) over non-zero factors
     int nz[T][kWave];       // number of zero factors (A == 1)
+    int ppre[kWave + 1];    // items regrouped by pixel: first item of each pixel
+    uint64_t pe[kWave];     // and its staged entries
 };
 
-// background item: eqs 10, 13-15, accumulated as log2(1 - A)
+// background item: eqs 10, 13-15, accumulated as log2(1 - A) per sub-frame
+// of the chunk into ls, with the zero factors (A == 1) counted in nz
 template <int T, int SOLVER>
 __device__ __forceinline__ void bg_item_fwd(const Inst &a, BgShared<T> &sh, int e, int p, const float tau[T],
-                                            uint32_t xbits, float tc)
+                                            uint32_t xbits, float tc, float (&ls)[T], int (&nz)[T])
 {
     const LdsRec r = lds_rec(sh.it, e);
     const float du = pix_du(p, a.inv_w), dv = pix_dv(p, a.inv_h);
@@ -1373,13 +1379,15 @@ __device__ __forceinline__ void bg_item_fwd(const Inst &a, BgShared<T> &sh, int 
         const float A = exp2f(b.d * a.neg_log2e_over_delta);
         const float om = one_minus_exp_neg(b.d * a.inv_delta, A);
         if (om > 0.0f)
-            atomicAdd(&sh.lsum[j][p], log2_one_minus(A, om));
+            ls[j] += log2_one_minus(A, om);
         else
-            atomicAdd(&sh.nz[j][p], 1);
+            ++nz[j];
     }
 }
 
-template <int T, int SOLVER>
+// RUNS: items grouped by pixel in per-lane runs (wide halo) or dealt one per
+// lane in entry order
+template <int T, int SOLVER, bool RUNS>
 __global__ __launch_bounds__(64, 4) void k_bg(const Inst *__restrict__ tab, int n, const int64_t *__restrict__ tprefix)
 {
     __shared__ BgShared<T> sh;
@@ -1425,8 +1433,58 @@ __global__ __launch_bounds__(64, 4) void k_bg(const Inst *__restrict__ tab, int 
             int cnt, pre;
             const int total =
                 stage_items<T>(a, sh.it, cur, nb, ck.s, g, tc, tau, kRecBg, a.halo, unc, nullptr, nullptr, cnt, pre);
-            for_items<T>(sh.it, total, cnt, pre,
-                         [&](int e, int p) { bg_item_fwd<T, SOLVER>(a, sh, e, p, tau, xbits, tc); });
+            if (!RUNS) {
+                // items in entry order, one per lane, each adding its factors
+                // to LDS (few lanes share a pixel: best when faces reach few
+                // pixels)
+                for_items<T>(sh.it, total, cnt, pre, [&](int e, int p) {
+                    float ls[T];
+                    int nzc[T];
+#pragma unroll
+                    for (int j = 0; j < T; ++j) {
+                        ls[j] = 0.0f;
+                        nzc[j] = 0;
+                    }
+                    bg_item_fwd<T, SOLVER>(a, sh, e, p, tau, xbits, tc, ls, nzc);
+#pragma unroll
+                    for (int j = 0; j < T; ++j) {
+                        if (ls[j] != 0.0f) atomicAdd(&sh.lsum[j][p], ls[j]);
+                        if (nzc[j]) atomicAdd(&sh.nz[j][p], nzc[j]);
+                    }
+                });
+                continue;
+            }
+            // regroup the items by pixel: a lane's run then adds up one
+            // pixel's factors over several faces before touching LDS (best
+            // when faces reach many pixels, so that a pixel has many items)
+            uint64_t pe = 0;
+            for (int e = 0; e < nb; ++e) pe |= ((sh.it.U[e] >> lane) & 1ull) << e;
+            const int cp = __popcll(pe);
+            const int inclp = wave_incl_scan(cp);
+            sh.pe[lane] = pe;
+            sh.ppre[lane] = inclp - cp;
+            if (lane == kWave - 1) sh.ppre[kWave] = inclp;
+            lds_sync();
+            float ls[T];
+            int nzc[T];
+#pragma unroll
+            for (int j = 0; j < T; ++j) {
+                ls[j] = 0.0f;
+                nzc[j] = 0;
+            }
+            for_runs(
+                kSeqBgFwd, total, inclp - cp, sh.ppre, sh.pe,
+                [&](int p, int e) { bg_item_fwd<T, SOLVER>(a, sh, e, p, tau, xbits, tc, ls, nzc); },
+                [&](int p) {
+#pragma unroll
+                    for (int j = 0; j < T; ++j) {
+                        if (ls[j] != 0.0f) atomicAdd(&sh.lsum[j][p], ls[j]);
+                        if (nzc[j]) atomicAdd(&sh.nz[j][p], nzc[j]);
+                        ls[j] = 0.0f;
+                        nzc[j] = 0;
+                    }
+                });
+            lds_sync();
         }
         lds_sync();
 #pragma unroll
@@ -1759,8 +1817,8 @@ __global__ __launch_bounds__(64) void k_fg_bwd(const Inst *__restrict__ tab, int
             float acc[12 + 3 * NCH];
 #pragma unroll
             for (int k = 0; k < 12 + 3 * NCH; ++k) acc[k] = 0.0f;
-            for_items_seq(
-                sh.it, kSeqFg, total, pre, [&](int e, int p) { fg_item_bwd<T, SOLVER>(a, sh, e, p, tau, tc, acc); },
+            for_runs(
+                kSeqFg, total, pre, sh.it.pre, sh.it.U, [&](int e, int p) { fg_item_bwd<T, SOLVER>(a, sh, e, p, tau, tc, acc); },
                 [&](int e) {
 #pragma unroll
                     for (int q = 0; q < 3; ++q) {
@@ -1793,9 +1851,9 @@ template <int T>
 struct BgBwdShared {
     ItemShared<T> it;
     int vslot[NB][3];         // staged entries' vertices: index, then vertex-table slot
-    VTab<4, 256> vt;
-    float P[T][kWave];        // forward product over non-zero factors
-    int nz[T][kWave];
+    VTab<4, 128> vt;
+    float P[T][kWave];        // forward product over the non-zero factors if there is none
+                              // of A == 1; minus the product if there is one; -0 if more
     float gal[kWave];         // dL/dalpha of each pixel, already divided by K
 };
 
@@ -1828,9 +1886,10 @@ __device__ __forceinline__ void bg_item_bwd(const Inst &a, BgBwdShared<T> &sh, i
         if (!(b.d <= a.dmax)) continue;
         const float A = exp2f(b.d * a.neg_log2e_over_delta);
         const float om = one_minus_exp_neg(b.d * a.inv_delta, A);
-        const int nzc = sh.nz[j][p];
+        // product over the other factors: the item's own factor divided out,
+        // or the product of the rest when the item holds the one zero factor
         const float P = sh.P[j][p];
-        const float Pe = nzc == 0 ? P / om : (nzc == 1 ? (om > 0.0f ? 0.0f : P) : 0.0f);
+        const float Pe = !signbit(P) ? P / om : (om > 0.0f ? 0.0f : -P);
         const float gd = -galpha * Pe * A * a.inv_delta;
         if (gd == 0.0f) continue;
         const float gpx = 2.0f * gd * (b.psx - du), gpy = 2.0f * gd * (b.psy - dv);
@@ -1899,8 +1958,11 @@ __device__ __forceinline__ void bg_item_bwd(const Inst &a, BgBwdShared<T> &sh, i
     }
 }
 
-template <int T, int SOLVER>
-__global__ __launch_bounds__(64, 3) void k_bg_bwd(const Inst *__restrict__ tab, int n)
+// WPS: waves per SIMD the register allocation targets.  4 spills some
+// registers but hides more latency, which pays off when faces reach many
+// pixels (long item runs); 3 is better otherwise.
+template <int T, int SOLVER, int WPS>
+__global__ __launch_bounds__(64, WPS) void k_bg_bwd(const Inst *__restrict__ tab, int n)
 {
     __shared__ BgBwdShared<T> sh;
     const int lane = threadIdx.x & 63;
@@ -1943,8 +2005,7 @@ __global__ __launch_bounds__(64, 3) void k_bg_bwd(const Inst *__restrict__ tab, 
                     nz = __float_as_int(a.pix[pix_index(a, g.tile, k, 1, lane)]);
                 }
             }
-            sh.P[j][lane] = P;
-            sh.nz[j][lane] = nz;
+            sh.P[j][lane] = nz == 0 ? P : (nz == 1 ? -P : -0.0f);
             bgm[j] = __ballot(vid == -1 && gal != 0.0f);
             anybg = anybg || bgm[j] != 0ull;
         }
@@ -1970,8 +2031,8 @@ __global__ __launch_bounds__(64, 3) void k_bg_bwd(const Inst *__restrict__ tab, 
             float gK[12];
 #pragma unroll
             for (int q = 0; q < 12; ++q) gK[q] = 0.0f;
-            for_items_seq(
-                sh.it, a.seq_bg, total, pre, [&](int e, int p) { bg_item_bwd<T, SOLVER>(a, sh, e, p, tau, xbits, tc, gK); },
+            for_runs(
+                a.seq_bg, total, pre, sh.it.pre, sh.it.U, [&](int e, int p) { bg_item_bwd<T, SOLVER>(a, sh, e, p, tau, xbits, tc, gK); },
                 [&](int e) {
 #pragma unroll
                     for (int q = 0; q < 3; ++q) {
@@ -2176,8 +2237,13 @@ static void forward_T(const Batch &bt, const Inst *tab, void *ws, hipStream_t st
     hipLaunchKernelGGL(k_tasks, dim3((unsigned)g.tscan3), dim3(256), 0, st, tab, n);
     hipLaunchKernelGGL(k_tprefix, dim3(1), dim3(64), 0, st, tab, n, tprefix);
     mark(pe, 3, st);
-    static const unsigned nw = resident_waves(k_bg<T, SOLVER>);
-    hipLaunchKernelGGL((k_bg<T, SOLVER>), dim3(nw), dim3(kWave), 0, st, tab, n, (const int64_t *)tprefix);
+    if (bt.wide) {
+        static const unsigned nw = resident_waves(k_bg<T, SOLVER, true>);
+        hipLaunchKernelGGL((k_bg<T, SOLVER, true>), dim3(nw), dim3(kWave), 0, st, tab, n, (const int64_t *)tprefix);
+    } else {
+        static const unsigned nw = resident_waves(k_bg<T, SOLVER, false>);
+        hipLaunchKernelGGL((k_bg<T, SOLVER, false>), dim3(nw), dim3(kWave), 0, st, tab, n, (const int64_t *)tprefix);
+    }
 }
 
 hipError_t launch_forward(const Batch &bt, const std::vector<Io> &io, void *ws, hipStream_t st, const PhaseEvents *pe)
@@ -2209,8 +2275,13 @@ static void backward_T(const Batch &bt, const Inst *tab, void *ws, hipStream_t s
     hipLaunchKernelGGL((k_fg_bwd<T, SOLVER>), dim3((unsigned)bt.g.fg), dim3(kWave), 0, st, tab, n);
     mark(pe, 1, st);
     // the tasks vary in cost: more waves than fit at once, taking tasks from a counter
-    static const unsigned nw = 3 * resident_waves(k_bg_bwd<T, SOLVER>) / 2;
-    hipLaunchKernelGGL((k_bg_bwd<T, SOLVER>), dim3(nw), dim3(kWave), 0, st, tab, n);
+    if (bt.wide) {
+        static const unsigned nw = 3 * resident_waves(k_bg_bwd<T, SOLVER, 4>) / 2;
+        hipLaunchKernelGGL((k_bg_bwd<T, SOLVER, 4>), dim3(nw), dim3(kWave), 0, st, tab, n);
+    } else {
+        static const unsigned nw = 3 * resident_waves(k_bg_bwd<T, SOLVER, 3>) / 2;
+        hipLaunchKernelGGL((k_bg_bwd<T, SOLVER, 3>), dim3(nw), dim3(kWave), 0, st, tab, n);
+    }
 }
 
 hipError_t launch_backward(const Batch &bt, const std::vector<Io> &io, void *ws, hipStream_t st, const PhaseEvents *pe)
