@@ -723,33 +723,35 @@ struct BgEval {
 
 // keyframe X positions (anchor-local) and edges; closest-point edge e of
 // F(X) (from vertex e to e+1) is the entry's edge (e+2)%3
+struct KEdges {
+    float Ex[3], Ey[3], iee[3], kx[3], ky[3];
+};
+
 template <class R>
-__device__ __forceinline__ void kedges(const R &r, int X, float tc, float Ex[3], float Ey[3], float iee[3], float kx[3],
-                                       float ky[3])
+__device__ __forceinline__ void kedges(const R &r, int X, float tc, KEdges &k)
 {
     const float tx = (X ? 1.0f : 0.0f) - tc;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-        kx[q] = fmaf(tx, r.at(R_DX + q), r.at(R_XC + q));
-        ky[q] = fmaf(tx, r.at(R_DY + q), r.at(R_YC + q));
+        k.kx[q] = fmaf(tx, r.at(R_DX + q), r.at(R_XC + q));
+        k.ky[q] = fmaf(tx, r.at(R_DY + q), r.at(R_YC + q));
     }
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
         const int i = (e + 2) % 3, b = (e + 1) % 3;
-        Ex[e] = kx[b] - kx[e];
-        Ey[e] = ky[b] - ky[e];
-        iee[e] = X ? r.at(R_A1 + i) : r.at(R_A0 + i);
+        k.Ex[e] = k.kx[b] - k.kx[e];
+        k.Ey[e] = k.ky[b] - k.ky[e];
+        k.iee[e] = X ? r.at(R_A1 + i) : r.at(R_A0 + i);
     }
 }
 
 template <class R>
-__device__ __forceinline__ void bg_eval(const R &r, float tc, float tau, int X, const float N[3], float invD, float du,
-                                        float dv, BgEval &b)
+__device__ __forceinline__ void bg_eval(const R &r, const KEdges &k, float tc, float tau, int X, const float N[3],
+                                        float invD, float du, float dv, BgEval &b)
 {
 #pragma unroll
     for (int i = 0; i < 3; ++i) b.w[i] = N[i] * invD;
-    float Ex[3], Ey[3], iee[3], kx[3], ky[3];
-    kedges(r, X, tc, Ex, Ey, iee, kx, ky);
+    const float *Ex = k.Ex, *Ey = k.Ey, *iee = k.iee, *kx = k.kx, *ky = k.ky;
     // q = F(X) w = p + (X - tau) sum_i w_i dv_i (linear motion, sum w = 1):
     // exact at the keyframes and under translation, and free of the
     // |w| * |edge| rounding of sum_i w_i v_i(X) when the face is nearly
@@ -1357,15 +1359,19 @@ struct BgShared {
 };
 
 // background item: eqs 10, 13-15, accumulated as log2(1 - A) per sub-frame
-// of the chunk into ls, with the zero factors (A == 1) counted in nz
-template <int T, int SOLVER>
+// of the chunk, with the zero factors (A == 1) counted: into ls / nz (ACC)
+// or straight into the LDS sums
+// (xk: the keyframe X shared by every sub-frame of the chunk, or -1)
+template <int T, int SOLVER, bool ACC>
 __device__ __forceinline__ void bg_item_fwd(const Inst &a, BgShared<T> &sh, int e, int p, const float tau[T],
-                                            uint32_t xbits, float tc, float (&ls)[T], int (&nz)[T])
+                                            uint32_t xbits, int xk, float tc, float (&ls)[T], int (&nz)[T])
 {
     const LdsRec r = lds_rec(sh.it, e);
     const float du = pix_du(p, a.inv_w), dv = pix_dv(p, a.inv_h);
     Bary<SOLVER> bc;
     bc.setup(r, tc, du, dv);
+    KEdges ke;
+    if (xk >= 0) kedges(r, xk, tc, ke);
 #pragma unroll
     for (int j = 0; j < T; ++j) {
         if (!((sh.it.m[j][e] >> p) & 1ull)) continue;
@@ -1373,15 +1379,24 @@ __device__ __forceinline__ void bg_item_fwd(const Inst &a, BgShared<T> &sh, int 
         bc.eval(r, tau[j] - tc, N);
         const float D = N[0] + N[1] + N[2];
         if (!(fabsf(D) > kTauDet)) continue;
+        const int X = (xbits >> j) & 1u;
+        if (xk < 0) kedges(r, X, tc, ke);
         BgEval b;
-        bg_eval(r, tc, tau[j], (xbits >> j) & 1u, N, rcp(D), du, dv, b);
+        bg_eval(r, ke, tc, tau[j], X, N, rcp(D), du, dv, b);
         if (!(b.d <= a.dmax)) continue;
         const float A = exp2f(b.d * a.neg_log2e_over_delta);
         const float om = one_minus_exp_neg(b.d * a.inv_delta, A);
-        if (om > 0.0f)
-            ls[j] += log2_one_minus(A, om);
-        else
-            ++nz[j];
+        if (ACC) {
+            if (om > 0.0f)
+                ls[j] += log2_one_minus(A, om);
+            else
+                ++nz[j];
+        } else {
+            if (om > 0.0f)
+                atomicAdd(&sh.lsum[j][p], log2_one_minus(A, om));
+            else
+                atomicAdd(&sh.nz[j][p], 1);
+        }
     }
 }
 
@@ -1412,6 +1427,8 @@ __global__ __launch_bounds__(64, 4) void k_bg(const Inst *__restrict__ tab, int 
         uint32_t xbits;
         chunk_taus<T>(a, ck, tau, xbits);
         const float tc = chunk_centre<T>(tau, ck.n);
+        // keyframe X of every sub-frame of the chunk, when they share one
+        const int xk = xbits == 0u ? 0 : (xbits == (1u << ck.n) - 1u ? 1 : -1);
         uint64_t unc[T];
         lds_sync();
 #pragma unroll
@@ -1437,20 +1454,10 @@ __global__ __launch_bounds__(64, 4) void k_bg(const Inst *__restrict__ tab, int 
                 // items in entry order, one per lane, each adding its factors
                 // to LDS (few lanes share a pixel: best when faces reach few
                 // pixels)
+                float ls[T];
+                int nzc[T];
                 for_items<T>(sh.it, total, cnt, pre, [&](int e, int p) {
-                    float ls[T];
-                    int nzc[T];
-#pragma unroll
-                    for (int j = 0; j < T; ++j) {
-                        ls[j] = 0.0f;
-                        nzc[j] = 0;
-                    }
-                    bg_item_fwd<T, SOLVER>(a, sh, e, p, tau, xbits, tc, ls, nzc);
-#pragma unroll
-                    for (int j = 0; j < T; ++j) {
-                        if (ls[j] != 0.0f) atomicAdd(&sh.lsum[j][p], ls[j]);
-                        if (nzc[j]) atomicAdd(&sh.nz[j][p], nzc[j]);
-                    }
+                    bg_item_fwd<T, SOLVER, false>(a, sh, e, p, tau, xbits, xk, tc, ls, nzc);
                 });
                 continue;
             }
@@ -1474,7 +1481,7 @@ __global__ __launch_bounds__(64, 4) void k_bg(const Inst *__restrict__ tab, int 
             }
             for_runs(
                 kSeqBgFwd, total, inclp - cp, sh.ppre, sh.pe,
-                [&](int p, int e) { bg_item_fwd<T, SOLVER>(a, sh, e, p, tau, xbits, tc, ls, nzc); },
+                [&](int p, int e) { bg_item_fwd<T, SOLVER, true>(a, sh, e, p, tau, xbits, xk, tc, ls, nzc); },
                 [&](int p) {
 #pragma unroll
                     for (int j = 0; j < T; ++j) {
@@ -1871,6 +1878,7 @@ __device__ __forceinline__ void bg_item_bwd(const Inst &a, BgBwdShared<T> &sh, i
     const float galpha = sh.gal[p];
     Bary<SOLVER> bc;
     bc.setup(r, tc, du, dv);
+    KEdges ke;
 #pragma unroll
     for (int j = 0; j < T; ++j) {
         if (!((sh.it.m[j][e] >> p) & 1ull)) continue;
@@ -1881,8 +1889,9 @@ __device__ __forceinline__ void bg_item_bwd(const Inst &a, BgBwdShared<T> &sh, i
         if (!(fabsf(D) > kTauDet)) continue;
         const float invD = rcp(D);
         const int X = (xbits >> j) & 1u;
+        kedges(r, X, tc, ke);
         BgEval b;
-        bg_eval(r, tc, tau[j], X, N, invD, du, dv, b);
+        bg_eval(r, ke, tc, tau[j], X, N, invD, du, dv, b);
         if (!(b.d <= a.dmax)) continue;
         const float A = exp2f(b.d * a.neg_log2e_over_delta);
         const float om = one_minus_exp_neg(b.d * a.inv_delta, A);
@@ -1912,8 +1921,7 @@ __device__ __forceinline__ void bg_item_bwd(const Inst &a, BgBwdShared<T> &sh, i
         const bool interior = !(b.sr < 0.0f) && !(b.sr > 1.0f);
         if (interior) {
             const int ea = b.be;
-            float Ex[3], Ey[3], iee3[3], kx[3], ky[3];
-            kedges(r, X, tc, Ex, Ey, iee3, kx, ky);
+            const float *Ex = ke.Ex, *Ey = ke.Ey, *iee3 = ke.iee;
             const float exs = ea == 0 ? Ex[0] : (ea == 1 ? Ex[1] : Ex[2]);
             const float eys = ea == 0 ? Ey[0] : (ea == 1 ? Ey[1] : Ey[2]);
             const float iee = ea == 0 ? iee3[0] : (ea == 1 ? iee3[1] : iee3[2]);
