@@ -260,8 +260,13 @@ def main():
         name = max(KERNEL_COEF, key=lambda k: km[k])
         fl, ms = flops(counters, KERNEL_COEF[name]), km[name]
         ach = fl / (ms * 1e-3) / 1e12
+        # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
+        # when recorded for the kernels as they are now
+        from paper_2602_07860_amd import profiling
+        traffic = profiling.lookup(os.path.join(ROOT, "profiles", "traffic.json"), KERNEL_NAMES[name], args.workload)
         roof = {"bound": "alu", "kernel": KERNEL_NAMES[name], "achieved": round(ach, 4), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 6), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 6),
+                "traffic": round(traffic) if traffic is not None else None,
                 "flop_per_launch": fl, "avg_launch_ms": round(ms, 5),
                 "all_kernels": {KERNEL_NAMES[k]: {"ms": round(km[k], 5),
                                                   "tflops": round(flops(counters, KERNEL_COEF[k]) / (km[k] * 1e-3)

@@ -117,6 +117,8 @@ static rb_status make_plan(int32_t V, int32_t F, int32_t C, const rb_motion *mot
     o = align256(o + (size_t)p.maxtasks * 8);
     p.o_gkf = o;
     o = align256(o + (size_t)(S + 1) * V * 2 * 4);
+    p.o_fgw = o;
+    o = align256(o + (size_t)p.ntct * 4);
     p.total = o;
     return RB_OK;
 }

@@ -101,6 +101,7 @@ struct Inst {
     int64_t RB_G *tbsum;      // task scan block sums
     uint64_t RB_G *tasks;     // (chunk * ntiles + tile) << 32 | slice
     float RB_G *gkf;          // [S+1][V][2] keyframe gradient
+    int32_t RB_G *fgw;        // [NC * ntiles] 1 where the (chunk, tile) has a winner
     // sizes
     int V, F, C, S, K, W, H, tiles_x, tiles_y, ntiles;
     int CPS, NC, SL, NS, nfb;
@@ -134,7 +135,7 @@ struct Plan {
     int64_t maxtasks;
     // workspace byte offsets (from the instance's base)
     size_t o_hdr, o_kf, o_kfz, o_cnt, o_off, o_cur, o_bsum, o_list, o_vis_id, o_pix, o_tsl, o_toff, o_tbsum,
-        o_tasks, o_gkf, total;
+        o_tasks, o_gkf, o_fgw, total;
     int64_t ncounts;  // 2 * NC * ntiles
     int64_t nblocks_scan, nblocks_tscan;
 };

@@ -511,12 +511,13 @@ __global__ void k_scan3(const Inst *__restrict__ tab, int n, int which)
 //    colour, zeroed background accumulators.  It also counts the background
 //    tasks of its (chunk, tile): slices of SL background-list entries, none
 //    if every in-image pixel is covered at every sub-frame of the chunk.
-//  * k_bg, persistent waves taking background tasks from a counter: soft
-//    aggregation (eqs 10, 13-15) of the slice's faces on the uncovered pixels,
-//    accumulated in LDS as sum log2(1 - A) (zero factors counted apart) and
-//    added to the pixel records.  Splitting the long lists of silhouette tiles
-//    into slices keeps every wave's work bounded.
-//  * k_resolve, one wave per tile: the average over the K sub-frames.
+//  * k_bg, persistent waves (one per resident slot; task t to wave t mod G):
+//    soft aggregation (eqs 10, 13-15) of the slice's faces on the uncovered
+//    pixels, accumulated in LDS as sum log2(1 - A) (zero factors counted
+//    apart) and added to the pixel records.  Splitting the long lists of
+//    silhouette tiles into slices keeps every wave's work bounded.
+//  * k_resolve, one block per tile: the average over the K sub-frames (four
+//    waves over interleaved sub-frames, combined in LDS).
 //
 // Inside a wave, a list is walked NB entries at a time:
 //  * staging: lane e gathers entry e's face indices and double keyframes and
@@ -524,8 +525,8 @@ __global__ void k_scan3(const Inst *__restrict__ tab, int n, int which)
 //    chunk's middle time (stored in LDS field-major, so lanes reading different
 //    entries hit different banks).  It also forms, per sub-frame of the chunk,
 //    the 64-bit mask of tile pixels the entry can reach (its box at that
-//    sub-frame, grown by the influence radius for the background, restricted
-//    to the pixels still in question) and their union U_e.
+//    sub-frame; for the background, the pixels within the influence radius of
+//    that box; restricted to the pixels still in question) and their union U_e.
 //  * items: the batch's work is the set of (entry, pixel) pairs with the pixel
 //    in U_e.  An exclusive scan over the entries numbers them and they are
 //    dealt out 64 at a time, one per lane, so a face that reaches 3 pixels of
@@ -534,12 +535,15 @@ __global__ void k_scan3(const Inst *__restrict__ tab, int n, int which)
 //    coefficients are formed once per item and evaluated per sub-frame.
 //  * foreground items update the LDS z-buffer by a 64-bit atomic min of
 //    (depth bits, face index), which keeps the lowest face index on exact
-//    depth ties; background items add log2(1 - A) with LDS float atomics.
+//    depth ties; background items add log2(1 - A) with LDS float atomics,
+//    or, when faces reach many pixels, are regrouped by pixel and dealt in
+//    per-lane runs that add a pixel's factors up before touching LDS.
 //
-// Backward, two kernels: k_fg_bwd per (chunk, tile) stages only the faces
-// that win a (pixel, sub-frame) with a colour gradient, found from the
-// visibility record; k_bg_bwd over the same background tasks as the forward.
-// A vertex-keyed LDS table collects the items' contributions and is added to
+// Backward, two kernels: k_fg_bwd per (chunk, tile) with a winner stages
+// only the faces that win a (pixel, sub-frame) with a colour gradient, found
+// from the visibility record; k_bg_bwd over the same background tasks as the
+// forward.  Items are dealt in per-lane runs whose gradients add up in
+// registers; a vertex-keyed LDS table collects the runs and is added to
 // global memory with one atomic per non-zero value when it fills or the work
 // unit ends.
 
@@ -1250,12 +1254,11 @@ __global__ __launch_bounds__(64) void k_fg(const Inst *__restrict__ tab, int n)
     TileCtx g;
     tile_ctx(a, ct, g);
     const Chunk &ck = g.ck;
-    if (a.hdr->error_bits & kHdrOverflow) {
-        if (lane == 0) a.tsl[ct] = 0;
-        return;
-    }
-    if (ck.n <= 0) {
-        if (lane == 0) a.tsl[ct] = 0;
+    if ((a.hdr->error_bits & kHdrOverflow) || ck.n <= 0) {
+        if (lane == 0) {
+            a.tsl[ct] = 0;
+            a.fgw[ct] = 0;
+        }
         return;
     }
     const uint64_t inimg = __ballot(g.inimg);
@@ -1280,7 +1283,7 @@ __global__ __launch_bounds__(64) void k_fg(const Inst *__restrict__ tab, int n)
         for_items<T>(sh.it, total, cnt, pre, [&](int e, int p) { fg_item<T, SOLVER>(a, sh, e, p, tau, tc); });
     }
     lds_sync();
-    bool anyunc = false;
+    bool anyunc = false, anycov = false;
 #pragma unroll
     for (int j = 0; j < T; ++j) {
         if (j >= ck.n) continue;
@@ -1288,6 +1291,7 @@ __global__ __launch_bounds__(64) void k_fg(const Inst *__restrict__ tab, int n)
         const unsigned long long key = sh.zb[j][lane];
         const int zid = key == ~0ull ? -1 : (int)(uint32_t)key;
         anyunc = anyunc || __ballot(g.inimg && zid < 0) != 0ull;
+        anycov = anycov || __ballot(g.inimg && zid >= 0) != 0ull;
         float rgb[NCH];
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) rgb[ch] = 0.0f;
@@ -1305,6 +1309,8 @@ __global__ __launch_bounds__(64) void k_fg(const Inst *__restrict__ tab, int n)
     if (lane == 0) {
         const int n_bg = a.cnt[(int64_t)a.NC * a.ntiles + ct];
         a.tsl[ct] = anyunc ? (n_bg + a.SL - 1) / a.SL : 0;
+        // whether the (chunk, tile) has a winner, for the foreground adjoint
+        a.fgw[ct] = anycov ? 1 : 0;
     }
 }
 
@@ -1510,31 +1516,47 @@ __global__ __launch_bounds__(64, 4) void k_bg(const Inst *__restrict__ tab, int 
 
 // image = mean over the K sub-frames of the winner's colour (premultiplied,
 // alpha 1) or, where uncovered, alpha = 1 - prod (1 - A) (eq 15)
-__global__ __launch_bounds__(64) void k_resolve(const Inst *__restrict__ tab, int n)
+constexpr int kResWaves = 4;   // waves per tile in the resolve (interleaved sub-frames)
+
+__global__ __launch_bounds__(64 * kResWaves) void k_resolve(const Inst *__restrict__ tab, int n)
 {
-    const Inst a = tab[inst_of<&Inst::b_res>(tab, n, blockIdx.x)];
-    float *__restrict__ image = a.image;
-    const int lane = threadIdx.x & 63;
+    __shared__ double part[kResWaves - 1][NCH + 1][kWave];
+    const Inst &a = tab[inst_of<&Inst::b_res>(tab, n, blockIdx.x)];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int tile = blockIdx.x - a.b_res;
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
     const int px = tx * kTile + (lane & 7), py = ty * kTile + (lane >> 3);
-    if (px >= a.W || py >= a.H) return;
+    const bool in = px < a.W && py < a.H;
+    // wave w sums sub-frames w, w + kResWaves, ... in double
     double acc[NCH + 1];
 #pragma unroll
     for (int ch = 0; ch <= NCH; ++ch) acc[ch] = 0.0;
-    for (int k = 0; k < a.K; ++k) {
-        const int vid = a.vis_id[vis_index(a, tile, k, lane)];
-        if (vid >= 0) {
+    if (in) {
+        for (int k = w; k < a.K; k += kResWaves) {
+            const int vid = a.vis_id[vis_index(a, tile, k, lane)];
+            if (vid >= 0) {
 #pragma unroll
-            for (int ch = 0; ch < NCH; ++ch)
-                if (ch < a.C) acc[ch] += (double)a.pix[pix_index(a, tile, k, ch, lane)];
-            acc[NCH] += 1.0;
-        } else {
-            const float ls = a.pix[pix_index(a, tile, k, 0, lane)];
-            const int nz = __float_as_int(a.pix[pix_index(a, tile, k, 1, lane)]);
-            acc[NCH] += nz > 0 ? 1.0 : (double)(1.0f - exp2f(ls));
+                for (int ch = 0; ch < NCH; ++ch)
+                    if (ch < a.C) acc[ch] += (double)a.pix[pix_index(a, tile, k, ch, lane)];
+                acc[NCH] += 1.0;
+            } else {
+                const float ls = a.pix[pix_index(a, tile, k, 0, lane)];
+                const int nz = __float_as_int(a.pix[pix_index(a, tile, k, 1, lane)]);
+                acc[NCH] += nz > 0 ? 1.0 : (double)(1.0f - exp2f(ls));
+            }
         }
     }
+    if (w > 0) {
+#pragma unroll
+        for (int ch = 0; ch <= NCH; ++ch) part[w - 1][ch][lane] = acc[ch];
+    }
+    __syncthreads();
+    if (w > 0 || !in) return;
+#pragma unroll
+    for (int q = 0; q < kResWaves - 1; ++q)
+#pragma unroll
+        for (int ch = 0; ch <= NCH; ++ch) acc[ch] += part[q][ch][lane];
+    float *__restrict__ image = a.image;
     const bool bad = (a.hdr->error_bits & kHdrOverflow) != 0;
     const double invK = 1.0 / (double)a.K;
     const size_t plane = (size_t)a.H * a.W, at = (size_t)py * a.W + px;
@@ -1724,7 +1746,8 @@ __global__ __launch_bounds__(64) void k_fg_bwd(const Inst *__restrict__ tab, int
     const Inst &a = tab[inst_of<&Inst::b_fg>(tab, n, lb)];
     const int ct = lb - a.b_fg;
     const int lane = threadIdx.x & 63;
-    if (a.hdr->error_bits & kHdrOverflow) return;
+    // (chunk, tile) pairs without a winner end before any other load
+    if (!a.fgw[ct] || (a.hdr->error_bits & kHdrOverflow)) return;
     TileCtx g;
     tile_ctx(a, ct, g);
     const Chunk &ck = g.ck;
@@ -2148,6 +2171,7 @@ static Inst make_inst(const Plan &p, const Io &io, char *base, const Grids &star
     a.tbsum = (decltype(a.tbsum))(base + p.o_tbsum);
     a.tasks = (decltype(a.tasks))(base + p.o_tasks);
     a.gkf = (decltype(a.gkf))(base + p.o_gkf);
+    a.fgw = (decltype(a.fgw))(base + p.o_fgw);
     a.V = p.V;
     a.F = p.F;
     a.C = p.C;
@@ -2271,7 +2295,7 @@ hipError_t launch_forward(const Batch &bt, const std::vector<Io> &io, void *ws, 
     default: fast ? forward_T<8, RB_SOLVER_FAST>(bt, tab, ws, st, pe) : forward_T<8, RB_SOLVER_RECOMPUTE>(bt, tab, ws, st, pe); break;
     }
     mark(pe, 4, st);
-    hipLaunchKernelGGL(k_resolve, dim3((unsigned)g.res), dim3(kWave), 0, st, tab, n);
+    hipLaunchKernelGGL(k_resolve, dim3((unsigned)g.res), dim3(kWave * kResWaves), 0, st, tab, n);
     mark(pe, 5, st);
     return hipGetLastError();
 }

@@ -1,0 +1,16 @@
+"""Recorded HBM traffic is reported only for the kernel sources it was
+measured on (host logic, no GPU)."""
+import json
+
+from paper_2602_07860_amd import profiling
+
+
+def test_traffic_lookup_matches_source_hash(tmp_path):
+    p = tmp_path / "traffic.json"
+    good = {"bytes_per_launch": 123.0, "source_sha256": profiling.source_hash()}
+    stale = {"bytes_per_launch": 456.0, "source_sha256": "0" * 64}
+    p.write_text(json.dumps({"k_bg_bwd@medium": good, "k_bg_bwd@large": stale}))
+    assert profiling.lookup(str(p), "k_bg_bwd", "medium") == 123.0
+    assert profiling.lookup(str(p), "k_bg_bwd", "large") is None
+    assert profiling.lookup(str(p), "k_fg", "medium") is None
+    assert profiling.lookup(str(tmp_path / "missing.json"), "k_bg_bwd", "medium") is None
