@@ -4,7 +4,7 @@
       a plain 1 GiB device-to-device copy, three times: the reference that
       scales rocprofv3's FETCH_SIZE / WRITE_SIZE counters to bytes;
   python -m paper_2602_07860_amd.profiling traffic --kernel K --workload W \\
-          --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR --out FILE
+          [--match NAME] --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR --out FILE
       combine `rocprofv3 --pmc FETCH_SIZE` and `--pmc WRITE_SIZE` runs of the
       benchmark (DIR holds the run's counter_collection.csv) and of the copy
       into HBM bytes per launch of kernel K, and record them in FILE (JSON,
@@ -69,12 +69,13 @@ def _copy() -> None:
 
 
 def _traffic(a) -> None:
-    fetch_kib = _counter_mean(a.fetch, "FETCH_SIZE", a.kernel)
-    write_kib = _counter_mean(a.write, "WRITE_SIZE", a.kernel)
+    match = a.match or a.kernel
+    fetch_kib = _counter_mean(a.fetch, "FETCH_SIZE", match)
+    write_kib = _counter_mean(a.write, "WRITE_SIZE", match)
     # the copy reads and writes COPY_BYTES per dispatch
     cf = COPY_BYTES / (_counter_mean(a.copy_fetch, "FETCH_SIZE", a.copy_kernel) * 1024)
     cw = COPY_BYTES / (_counter_mean(a.copy_write, "WRITE_SIZE", a.copy_kernel) * 1024)
-    rec = {"fetch_kib": fetch_kib, "write_kib": write_kib, "fetch_scale": round(cf, 4), "write_scale": round(cw, 4),
+    rec = {"match": match, "fetch_kib": fetch_kib, "write_kib": write_kib, "fetch_scale": round(cf, 4), "write_scale": round(cw, 4),
            "bytes_per_launch": fetch_kib * 1024 * cf + write_kib * 1024 * cw, "source_sha256": source_hash()}
     data = {}
     if os.path.exists(a.out):
@@ -93,6 +94,7 @@ def main() -> None:
     sub.add_parser("copy")
     t = sub.add_parser("traffic")
     t.add_argument("--kernel", required=True)
+    t.add_argument("--match", default="", help="substring of the profiled kernel names (default: --kernel)")
     t.add_argument("--workload", required=True)
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
