@@ -112,7 +112,7 @@ def run_single(sc, tg, args, torch, B, R, adam=False):
         # shape recovery: the same start for both solvers; the geometry moves,
         # so every forward checks its bin lists (one header read)
         verts, attrs = st.verts.clone(), st.attrs.clone()
-        opt = torch.optim.Adam([verts, attrs], lr=1e-3) if adam else None
+        opt = torch.optim.Adam([{"params": [verts], "lr": 2e-4}, {"params": [attrs], "lr": 1e-3}]) if adam else None
 
         def step():
             img, state = R.render_forward(verts, st.faces, attrs, st.model, st.camera, box["o"])
