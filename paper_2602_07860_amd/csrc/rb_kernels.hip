@@ -1358,7 +1358,8 @@ __device__ __forceinline__ int task_inst(const int64_t *__restrict__ tprefix, in
 template <int T>
 struct BgShared {
     ItemShared<T> it;
-    float lsum[T][kWave];   // sum of log2(1 - A) over non-zero factors
+    double lsum[T][kWave];  // sum of log2(1 - A) over non-zero factors (hundreds of
+                            // factors per pixel near a silhouette: summed in double)
     int nz[T][kWave];       // number of zero factors (A == 1)
     int ppre[kWave + 1];    // items regrouped by pixel: first item of each pixel
     uint64_t pe[kWave];     // and its staged entries
@@ -1370,7 +1371,7 @@ struct BgShared {
 // (xk: the keyframe X shared by every sub-frame of the chunk, or -1)
 template <int T, int SOLVER, bool ACC>
 __device__ __forceinline__ void bg_item_fwd(const Inst &a, BgShared<T> &sh, int e, int p, const float tau[T],
-                                            uint32_t xbits, int xk, float tc, float (&ls)[T], int (&nz)[T])
+                                            uint32_t xbits, int xk, float tc, double (&ls)[T], int (&nz)[T])
 {
     const LdsRec r = lds_rec(sh.it, e);
     const float du = pix_du(p, a.inv_w), dv = pix_dv(p, a.inv_h);
@@ -1394,12 +1395,12 @@ __device__ __forceinline__ void bg_item_fwd(const Inst &a, BgShared<T> &sh, int 
         const float om = one_minus_exp_neg(b.d * a.inv_delta, A);
         if (ACC) {
             if (om > 0.0f)
-                ls[j] += log2_one_minus(A, om);
+                ls[j] += (double)log2_one_minus(A, om);
             else
                 ++nz[j];
         } else {
             if (om > 0.0f)
-                atomicAdd(&sh.lsum[j][p], log2_one_minus(A, om));
+                atomicAdd(&sh.lsum[j][p], (double)log2_one_minus(A, om));
             else
                 atomicAdd(&sh.nz[j][p], 1);
         }
@@ -1441,7 +1442,7 @@ __global__ __launch_bounds__(64, 4) void k_bg(const Inst *__restrict__ tab, int 
         for (int j = 0; j < T; ++j) {
             const int vid = j < ck.n ? a.vis_id[vis_index(a, g.tile, ck.k0 + j, lane)] : kVisOut;
             unc[j] = __ballot(vid == -1);
-            sh.lsum[j][lane] = 0.0f;
+            sh.lsum[j][lane] = 0.0;
             sh.nz[j][lane] = 0;
         }
         const int64_t idx = (int64_t)a.NC * a.ntiles + ct;
@@ -1460,7 +1461,7 @@ __global__ __launch_bounds__(64, 4) void k_bg(const Inst *__restrict__ tab, int 
                 // items in entry order, one per lane, each adding its factors
                 // to LDS (few lanes share a pixel: best when faces reach few
                 // pixels)
-                float ls[T];
+                double ls[T];
                 int nzc[T];
                 for_items<T>(sh.it, total, cnt, pre, [&](int e, int p) {
                     bg_item_fwd<T, SOLVER, false>(a, sh, e, p, tau, xbits, xk, tc, ls, nzc);
@@ -1478,11 +1479,11 @@ __global__ __launch_bounds__(64, 4) void k_bg(const Inst *__restrict__ tab, int 
             sh.ppre[lane] = inclp - cp;
             if (lane == kWave - 1) sh.ppre[kWave] = inclp;
             lds_sync();
-            float ls[T];
+            double ls[T];
             int nzc[T];
 #pragma unroll
             for (int j = 0; j < T; ++j) {
-                ls[j] = 0.0f;
+                ls[j] = 0.0;
                 nzc[j] = 0;
             }
             for_runs(
@@ -1491,9 +1492,9 @@ __global__ __launch_bounds__(64, 4) void k_bg(const Inst *__restrict__ tab, int 
                 [&](int p) {
 #pragma unroll
                     for (int j = 0; j < T; ++j) {
-                        if (ls[j] != 0.0f) atomicAdd(&sh.lsum[j][p], ls[j]);
+                        if (ls[j] != 0.0) atomicAdd(&sh.lsum[j][p], ls[j]);
                         if (nzc[j]) atomicAdd(&sh.nz[j][p], nzc[j]);
-                        ls[j] = 0.0f;
+                        ls[j] = 0.0;
                         nzc[j] = 0;
                     }
                 });
@@ -1503,7 +1504,7 @@ __global__ __launch_bounds__(64, 4) void k_bg(const Inst *__restrict__ tab, int 
 #pragma unroll
         for (int j = 0; j < T; ++j) {
             if (!((unc[j] >> lane) & 1ull)) continue;
-            const float ls = sh.lsum[j][lane];
+            const float ls = (float)sh.lsum[j][lane];
             const int nz = sh.nz[j][lane];
             if (ls != 0.0f) unsafeAtomicAdd(&a.pix[pix_index(a, g.tile, ck.k0 + j, 0, lane)], ls);
             if (nz) atomicAdd((int *)&a.pix[pix_index(a, g.tile, ck.k0 + j, 1, lane)], nz);
