@@ -1577,24 +1577,26 @@ __global__ __launch_bounds__(64 * kResWaves) void k_resolve(const Inst *__restri
 // share vertices, so the table reaches global memory with one atomic per
 // (vertex, value) when it fills up or the task ends, instead of one per
 // (face, vertex, value).
-template <int NV, int NS>
+// V: the accumulator type (double tables measured faster in the foreground
+// adjoint; in the background adjoint their LDS would cost occupancy)
+template <int NV, int NS, class V = float>
 struct VTab {
     static_assert((NS & (NS - 1)) == 0 && NS >= 64 && NS <= 1024, "slot count");
     static constexpr int kSlots = NS;
     static constexpr int kLoad = NS * 3 / 4;   // flush before a batch could push the table past this
     static constexpr int kShift = NS == 64 ? 26 : NS == 128 ? 25 : NS == 256 ? 24 : NS == 512 ? 23 : 22;
     int key[NS];               // vertex index, -1 = empty
-    float g[NV][NS];           // 0-3: keyframe s (x, y), keyframe s + 1 (x, y); 4+: attributes
+    V g[NV][NS];               // 0-3: keyframe s (x, y), keyframe s + 1 (x, y); 4+: attributes
 };
 
-template <int NV, int NS>
-__device__ __forceinline__ void vt_clear(VTab<NV, NS> &vt)
+template <int NV, int NS, class V>
+__device__ __forceinline__ void vt_clear(VTab<NV, NS, V> &vt)
 {
     const int lane = threadIdx.x & 63;
     for (int i = lane; i < NS; i += kWave) {
         vt.key[i] = -1;
 #pragma unroll
-        for (int k = 0; k < NV; ++k) vt.g[k][i] = 0.0f;
+        for (int k = 0; k < NV; ++k) vt.g[k][i] = V(0);
     }
 }
 
@@ -1614,8 +1616,8 @@ __device__ __forceinline__ int wave_sum_int(int x)
 // Replace the staged entries' vertex indices vs[e][q] (e < nb) by their table
 // slots, inserting new vertices; returns the number of new keys.  The caller
 // keeps the table below kLoad of its NS slots, so a free slot is always found.
-template <int NV, int NS>
-__device__ __forceinline__ int vt_bind(VTab<NV, NS> &vt, int (*vs)[3], int nb)
+template <int NV, int NS, class V>
+__device__ __forceinline__ int vt_bind(VTab<NV, NS, V> &vt, int (*vs)[3], int nb)
 {
     const int lane = threadIdx.x & 63;
     int fresh = 0;
@@ -1641,15 +1643,15 @@ __device__ __forceinline__ int vt_bind(VTab<NV, NS> &vt, int (*vs)[3], int nb)
     return wave_sum_int(fresh);
 }
 
-template <int NV, int NS>
-__device__ __forceinline__ void vt_add(VTab<NV, NS> &vt, int slot, int k, float v)
+template <int NV, int NS, class V>
+__device__ __forceinline__ void vt_add(VTab<NV, NS, V> &vt, int slot, int k, float v)
 {
-    if (v != 0.0f && slot >= 0) atomicAdd(&vt.g[k][slot], v);
+    if (v != 0.0f && slot >= 0) atomicAdd(&vt.g[k][slot], (V)v);
 }
 
 // Add the table to the keyframe (and attribute) gradients and clear it.
-template <int NV, int NS>
-__device__ __forceinline__ void vt_flush(VTab<NV, NS> &vt, int s, const Inst &a)
+template <int NV, int NS, class V>
+__device__ __forceinline__ void vt_flush(VTab<NV, NS, V> &vt, int s, const Inst &a)
 {
     const int lane = threadIdx.x & 63;
     lds_sync();
@@ -1658,15 +1660,15 @@ __device__ __forceinline__ void vt_flush(VTab<NV, NS> &vt, int s, const Inst &a)
         if (v < 0) continue;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const float g = vt.g[k][i];
+            const float g = (float)vt.g[k][i];
             if (g != 0.0f) unsafeAtomicAdd(a.gkf + ((size_t)(s + (k >> 1)) * a.V + v) * 2 + (k & 1), g);
-            vt.g[k][i] = 0.0f;
+            vt.g[k][i] = V(0);
         }
 #pragma unroll
         for (int c = 0; c < NV - 4; ++c) {
-            const float g = vt.g[4 + c][i];
+            const float g = (float)vt.g[4 + c][i];
             if (g != 0.0f && c < a.C) unsafeAtomicAdd(a.grad_attrs + (size_t)v * a.C + c, g);
-            vt.g[4 + c][i] = 0.0f;
+            vt.g[4 + c][i] = V(0);
         }
         vt.key[i] = -1;
     }
@@ -1680,7 +1682,7 @@ struct FgBwdShared {
     ItemShared<T> it;         // staged winning faces, their (pixel, sub-frame) masks and items
     float at[3 * NCH][NB];    // their vertex attributes
     int vslot[NB][3];         // their vertices: index, then vertex-table slot
-    VTab<4 + NCH, 128> vt;    // one batch of at most NB faces between flushes
+    VTab<4 + NCH, 128, double> vt;   // one batch of at most NB faces between flushes
     float gI[NCH][kWave];     // dL/dcolour of each pixel, already divided by K
 };
 
