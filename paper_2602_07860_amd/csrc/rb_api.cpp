@@ -149,6 +149,7 @@ static rb_status make_batch(const std::vector<Plan> &plans, Batch &bt)
         g.tscan1 += p.nblocks_tscan;
         g.tscan3 += (p.ntct + 255) / 256;
         g.fg += p.ntct;
+        g.fgb += (int64_t)p.S * p.ntiles;
         g.res += p.ntiles;
         g.bwdinit += ((int64_t)(p.S + 1) * p.V * 2 + (int64_t)p.V * p.C + 255) / 256;
         g.vtx += (p.V + 255) / 256;
@@ -156,7 +157,7 @@ static rb_status make_batch(const std::vector<Plan> &plans, Batch &bt)
     // one launch covers every instance: block counts must fit the grid and
     // the 32-bit block starts of the table
     const int64_t lim = (1LL << 31) - 1;
-    for (int64_t v : {g.init, g.proj, g.bin, g.scan1, g.scan3, g.tscan1, g.tscan3, g.fg, g.res, g.bwdinit, g.vtx})
+    for (int64_t v : {g.init, g.proj, g.bin, g.scan1, g.scan3, g.tscan1, g.tscan3, g.fg, g.fgb, g.res, g.bwdinit, g.vtx})
         if (v > lim) return RB_EUNSUPPORTED;
     bt.g = g;
     bt.o_table = o;

@@ -112,7 +112,7 @@ struct Inst {
     float inv_w, inv_h, dmax, halo, neg_log2e_over_delta, inv_delta, invK;
     ViewArgs vw;
     // first block of this instance in each launch
-    int b_init, b_proj, b_bin, b_scan1, b_scan3, b_tscan1, b_tscan3, b_fg, b_res, b_bwdinit, b_vtx;
+    int b_init, b_proj, b_bin, b_scan1, b_scan3, b_tscan1, b_tscan3, b_fg, b_fgb, b_res, b_bwdinit, b_vtx;
 };
 
 // Host plan of one instance.
@@ -142,7 +142,7 @@ struct Plan {
 
 // Block counts of each launch over a batch.
 struct Grids {
-    int64_t init, proj, bin, scan1, scan3, tscan1, tscan3, fg, res, bwdinit, vtx;
+    int64_t init, proj, bin, scan1, scan3, tscan1, tscan3, fg, fgb, res, bwdinit, vtx;
 };
 
 // Host plan of a batch: per-instance plans and where each instance's

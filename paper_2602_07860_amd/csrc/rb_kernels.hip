@@ -1745,137 +1745,154 @@ template <int T, int SOLVER>
 __global__ __launch_bounds__(64) void k_fg_bwd(const Inst *__restrict__ tab, int n)
 {
     __shared__ FgBwdShared<T> sh;
+    // one wave per (segment, tile): the segment's chunks share the keyframe
+    // pair, so one vertex table (and one flush) serves them all, and the
+    // tile's colour gradient is loaded once
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
-    const Inst &a = tab[inst_of<&Inst::b_fg>(tab, n, lb)];
-    const int ct = lb - a.b_fg;
+    const Inst &a = tab[inst_of<&Inst::b_fgb>(tab, n, lb)];
+    const int sti = lb - a.b_fgb;
+    const int seg = sti / a.ntiles, tile = sti - seg * a.ntiles;
     const int lane = threadIdx.x & 63;
-    // (chunk, tile) pairs without a winner end before any other load
-    if (!a.fgw[ct] || (a.hdr->error_bits & kHdrOverflow)) return;
-    TileCtx g;
-    tile_ctx(a, ct, g);
-    const Chunk &ck = g.ck;
-    if (ck.n <= 0) return;
+    if (a.hdr->error_bits & kHdrOverflow) return;
+    const int c0 = seg * a.CPS, c1 = c0 + a.CPS;
+    bool any = false;
+    for (int c = c0; c < c1 && !any; ++c) any = a.fgw[(int64_t)c * a.ntiles + tile] != 0;
+    if (!any) return;   // no chunk of the segment has a winner here
     bool gcol = false;
+    {
+        const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+        const int px = tx * kTile + (lane & 7), py = ty * kTile + (lane >> 3);
+        const bool inimg = px < a.W && py < a.H;
 #pragma unroll
-    for (int ch = 0; ch < NCH; ++ch) {
-        float v = 0.0f;
-        if (g.inimg && ch < a.C) v = a.grad_image[((size_t)ch * a.H + g.py) * a.W + g.px] * a.invK;
-        sh.gI[ch][lane] = v;
-        gcol = gcol || v != 0.0f;
+        for (int ch = 0; ch < NCH; ++ch) {
+            float v = 0.0f;
+            if (inimg && ch < a.C) v = a.grad_image[((size_t)ch * a.H + py) * a.W + px] * a.invK;
+            sh.gI[ch][lane] = v;
+            gcol = gcol || v != 0.0f;
+        }
     }
-    // (pixel, sub-frame) pairs with a winner and a colour gradient
-    int vid[T];
-    uint64_t pend[T];
-    bool anyfg = false;
-#pragma unroll
-    for (int j = 0; j < T; ++j) {
-        vid[j] = j < ck.n ? a.vis_id[vis_index(a, g.tile, ck.k0 + j, lane)] : kVisOut;
-        pend[j] = __ballot(gcol && vid[j] >= 0);
-        anyfg = anyfg || pend[j] != 0ull;
-    }
-    if (!anyfg) return;
+    if (__ballot(gcol) == 0ull) return;
     vt_clear(sh.vt);
     int used = 0;
-    float tau[T];
-    uint32_t xbits;
-    chunk_taus<T>(a, ck, tau, xbits);
-    const float tc = chunk_centre<T>(tau, ck.n);
+    for (int c = c0; c < c1; ++c) {
+        const int ct = c * a.ntiles + tile;
+        if (!a.fgw[ct]) continue;
+        TileCtx g;
+        tile_ctx(a, ct, g);
+        const Chunk &ck = g.ck;
+        if (ck.n <= 0) continue;
+        // (pixel, sub-frame) pairs with a winner and a colour gradient
+        int vid[T];
+        uint64_t pend[T];
+        bool anyfg = false;
+#pragma unroll
+        for (int j = 0; j < T; ++j) {
+            vid[j] = j < ck.n ? a.vis_id[vis_index(a, g.tile, ck.k0 + j, lane)] : kVisOut;
+            pend[j] = __ballot(gcol && vid[j] >= 0);
+            anyfg = anyfg || pend[j] != 0ull;
+        }
+        if (!anyfg) continue;
+        float tau[T];
+        uint32_t xbits;
+        chunk_taus<T>(a, ck, tau, xbits);
+        const float tc = chunk_centre<T>(tau, ck.n);
 
-    // Only the winning faces are staged (the list is not walked): the first
-    // pending pair's face becomes the next entry and takes every pending pair
-    // of that face, as its per-sub-frame pixel masks; a batch of NB entries
-    // (or the last one) is staged and its items (entry, pixel) are run.
-    uint64_t mown[T];         // masks of entry `lane` of the batch being gathered
+        // Only the winning faces are staged (the list is not walked): the first
+        // pending pair's face becomes the next entry and takes every pending pair
+        // of that face, as its per-sub-frame pixel masks; a batch of NB entries
+        // (or the last one) is staged and its items (entry, pixel) are run.
+        uint64_t mown[T];         // masks of entry `lane` of the batch being gathered
 #pragma unroll
-    for (int j = 0; j < T; ++j) mown[j] = 0ull;
-    int sel = 0;              // its face
-    int ne = 0;
-    for (;;) {
-        int j0 = -1, v0 = 0;
-#pragma unroll
-        for (int j = 0; j < T; ++j)
-            if (j0 < 0 && pend[j] != 0ull) {
-                j0 = j;
-                v0 = vid[j];
-            }
-        if (j0 >= 0) {
-            uint64_t pm = 0;
+        for (int j = 0; j < T; ++j) mown[j] = 0ull;
+        int sel = 0;              // its face
+        int ne = 0;
+        for (;;) {
+            int j0 = -1, v0 = 0;
 #pragma unroll
             for (int j = 0; j < T; ++j)
-                if (j == j0) pm = pend[j];
-            const int f = __shfl(v0, __builtin_ctzll(pm), 64);
+                if (j0 < 0 && pend[j] != 0ull) {
+                    j0 = j;
+                    v0 = vid[j];
+                }
+            if (j0 >= 0) {
+                uint64_t pm = 0;
 #pragma unroll
-            for (int j = 0; j < T; ++j) {
-                const uint64_t hit = __ballot(((pend[j] >> lane) & 1ull) && vid[j] == f);
-                pend[j] &= ~hit;
-                if (lane == ne) mown[j] = hit;
-            }
-            if (lane == ne) sel = f;
-            ++ne;
-        }
-        if (ne == NB || (j0 < 0 && ne > 0)) {
-            if (used + 3 * ne > sh.vt.kLoad) {
-                vt_flush(sh.vt, ck.s, a);
-                used = 0;
-            }
-            lds_sync();
-            int cnt = 0;
-            if (lane < ne) {
-                int vq[3];
-                face_verts(a, sel, vq);
-                FaceRec r;
-                stage_rec(a, sel, vq, ck.s, g.ua, g.va, tc, kRecGeom, r);
-                store_rec(sh.it, lane, r);
-                uint64_t U = 0;
+                for (int j = 0; j < T; ++j)
+                    if (j == j0) pm = pend[j];
+                const int f = __shfl(v0, __builtin_ctzll(pm), 64);
 #pragma unroll
                 for (int j = 0; j < T; ++j) {
-                    sh.it.m[j][lane] = mown[j];
-                    U |= mown[j];
+                    const uint64_t hit = __ballot(((pend[j] >> lane) & 1ull) && vid[j] == f);
+                    pend[j] &= ~hit;
+                    if (lane == ne) mown[j] = hit;
                 }
-                sh.it.U[lane] = U;
-                cnt = __popcll(U);
-#pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    sh.vslot[lane][q] = vq[q];
-#pragma unroll
-                    for (int ch = 0; ch < NCH; ++ch)
-                        sh.at[q * NCH + ch][lane] = ch < a.C ? a.attrs[(size_t)vq[q] * a.C + ch] : 0.0f;
-                }
+                if (lane == ne) sel = f;
+                ++ne;
             }
-            const int incl = wave_incl_scan(cnt);
-            const int pre = incl - cnt;
-            if (lane <= ne) sh.it.pre[lane] = pre;
-            const int total = __shfl(incl, 63, 64);
-            used += vt_bind(sh.vt, sh.vslot, ne);
-            float acc[12 + 3 * NCH];
+            if (ne == NB || (j0 < 0 && ne > 0)) {
+                if (used + 3 * ne > sh.vt.kLoad) {
+                    vt_flush(sh.vt, ck.s, a);
+                    used = 0;
+                }
+                lds_sync();
+                int cnt = 0;
+                if (lane < ne) {
+                    int vq[3];
+                    face_verts(a, sel, vq);
+                    FaceRec r;
+                    stage_rec(a, sel, vq, ck.s, g.ua, g.va, tc, kRecGeom, r);
+                    store_rec(sh.it, lane, r);
+                    uint64_t U = 0;
 #pragma unroll
-            for (int k = 0; k < 12 + 3 * NCH; ++k) acc[k] = 0.0f;
-            for_runs(
-                kSeqFg, total, pre, sh.it.pre, sh.it.U, [&](int e, int p) { fg_item_bwd<T, SOLVER>(a, sh, e, p, tau, tc, acc); },
-                [&](int e) {
+                    for (int j = 0; j < T; ++j) {
+                        sh.it.m[j][lane] = mown[j];
+                        U |= mown[j];
+                    }
+                    sh.it.U[lane] = U;
+                    cnt = __popcll(U);
 #pragma unroll
                     for (int q = 0; q < 3; ++q) {
-                        const int slot = sh.vslot[e][q];
+                        sh.vslot[lane][q] = vq[q];
 #pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            vt_add(sh.vt, slot, k, acc[q * 4 + k]);
-                            acc[q * 4 + k] = 0.0f;
-                        }
-#pragma unroll
-                        for (int ch = 0; ch < NCH; ++ch) {
-                            vt_add(sh.vt, slot, 4 + ch, acc[12 + q * NCH + ch]);
-                            acc[12 + q * NCH + ch] = 0.0f;
-                        }
+                        for (int ch = 0; ch < NCH; ++ch)
+                            sh.at[q * NCH + ch][lane] = ch < a.C ? a.attrs[(size_t)vq[q] * a.C + ch] : 0.0f;
                     }
-                });
-            lds_sync();
+                }
+                const int incl = wave_incl_scan(cnt);
+                const int pre = incl - cnt;
+                if (lane <= ne) sh.it.pre[lane] = pre;
+                const int total = __shfl(incl, 63, 64);
+                used += vt_bind(sh.vt, sh.vslot, ne);
+                float acc[12 + 3 * NCH];
 #pragma unroll
-            for (int j = 0; j < T; ++j) mown[j] = 0ull;
-            ne = 0;
+                for (int k = 0; k < 12 + 3 * NCH; ++k) acc[k] = 0.0f;
+                for_runs(
+                    kSeqFg, total, pre, sh.it.pre, sh.it.U, [&](int e, int p) { fg_item_bwd<T, SOLVER>(a, sh, e, p, tau, tc, acc); },
+                    [&](int e) {
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) {
+                            const int slot = sh.vslot[e][q];
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) {
+                                vt_add(sh.vt, slot, k, acc[q * 4 + k]);
+                                acc[q * 4 + k] = 0.0f;
+                            }
+#pragma unroll
+                            for (int ch = 0; ch < NCH; ++ch) {
+                                vt_add(sh.vt, slot, 4 + ch, acc[12 + q * NCH + ch]);
+                                acc[12 + q * NCH + ch] = 0.0f;
+                            }
+                        }
+                    });
+                lds_sync();
+#pragma unroll
+                for (int j = 0; j < T; ++j) mown[j] = 0ull;
+                ne = 0;
+            }
+            if (j0 < 0) break;
         }
-        if (j0 < 0) break;
     }
-    vt_flush(sh.vt, ck.s, a);
+    vt_flush(sh.vt, seg, a);
 }
 
 // ------------------------------------------------------- backward: k_bg_bwd
@@ -2214,6 +2231,7 @@ static Inst make_inst(const Plan &p, const Io &io, char *base, const Grids &star
     a.b_tscan1 = (int)start.tscan1;
     a.b_tscan3 = (int)start.tscan3;
     a.b_fg = (int)start.fg;
+    a.b_fgb = (int)start.fgb;
     a.b_res = (int)start.res;
     a.b_bwdinit = (int)start.bwdinit;
     a.b_vtx = (int)start.vtx;
@@ -2241,6 +2259,7 @@ static const Inst *write_table(const Batch &bt, const std::vector<Io> &io, void 
         start.tscan1 += p.nblocks_tscan;
         start.tscan3 += grid_for(p.ntct, 256);
         start.fg += p.ntct;
+        start.fgb += (int64_t)p.S * p.ntiles;
         start.res += p.ntiles;
         start.bwdinit += grid_for((int64_t)(p.S + 1) * p.V * 2 + (int64_t)p.V * p.C, 256);
         start.vtx += grid_for(p.V, 256);
@@ -2307,7 +2326,7 @@ template <int T, int SOLVER>
 static void backward_T(const Batch &bt, const Inst *tab, void *ws, hipStream_t st, const PhaseEvents *pe)
 {
     const int n = bt.n;
-    hipLaunchKernelGGL((k_fg_bwd<T, SOLVER>), dim3((unsigned)bt.g.fg), dim3(kWave), 0, st, tab, n);
+    hipLaunchKernelGGL((k_fg_bwd<T, SOLVER>), dim3((unsigned)bt.g.fgb), dim3(kWave), 0, st, tab, n);
     mark(pe, 1, st);
     // the tasks vary in cost: more waves than fit at once, taking tasks from a counter
     if (bt.wide) {
