@@ -23,8 +23,9 @@
  *  - Every pointer argument is a DEVICE pointer unless stated otherwise.
  *  - The caller owns all memory.  The library never allocates and never
  *    synchronizes; work is enqueued on the given stream (a hipStream_t passed
- *    as void*, NULL = the default stream).  rb_read_header is the one call
- *    that waits, and says so.
+ *    as void*, NULL = the default stream).  rb_read_header,
+ *    rb_batch_read_headers and rb_profile_read are the calls that wait, and
+ *    say so.
  *  - Layouts are dense, row-major, float32 / int32.
  *  - Nothing throws across the ABI; failures are negative rb_status codes.
  *    Asynchronous device-side findings (face index out of range, vertex

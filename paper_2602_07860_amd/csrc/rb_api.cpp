@@ -74,6 +74,10 @@ static rb_status make_plan(int32_t V, int32_t F, int32_t C, const rb_motion *mot
     // 256^2 with a 5.5-pixel halo and 1024^2 with a 22-pixel halo).
     const bool wide_halo = std::sqrt(dmax) * 0.5 * std::max(p.W, p.H) >= 12.0;
     p.seq_bg = wide_halo ? 8 : 4;
+    // foreground adjoint: chunks of a segment grouped per wave on large
+    // images (fewer flushes), one per wave otherwise (more waves in flight;
+    // grouping measured slower on the mixed batch of small images)
+    p.fgg = wide_halo ? 3 : 1;
     p.wide = wide_halo;
     p.NS = std::max(C, 2);
     p.nfb = (F + 255) / 256;
@@ -149,7 +153,7 @@ static rb_status make_batch(const std::vector<Plan> &plans, Batch &bt)
         g.tscan1 += p.nblocks_tscan;
         g.tscan3 += (p.ntct + 255) / 256;
         g.fg += p.ntct;
-        g.fgb += (int64_t)p.S * p.ntiles;
+        g.fgb += (int64_t)p.S * ((p.CPS + p.fgg - 1) / p.fgg) * p.ntiles;
         g.res += p.ntiles;
         g.bwdinit += ((int64_t)(p.S + 1) * p.V * 2 + (int64_t)p.V * p.C + 255) / 256;
         g.vtx += (p.V + 255) / 256;

@@ -106,6 +106,7 @@ struct Inst {
     int V, F, C, S, K, W, H, tiles_x, tiles_y, ntiles;
     int CPS, NC, SL, NS, nfb;
     int seq_bg;          // consecutive items per lane in the background adjoint
+    int fgg;             // chunks per wave (at most) in the foreground adjoint
     int ntct;            // (chunk, tile) pairs = NC * ntiles
     int nblocks_scan, nblocks_tscan;
     int64_t cap, maxtasks, ncounts;
@@ -127,6 +128,7 @@ struct Plan {
     int NC;         // chunks = S * CPS
     int SL;         // background list entries per task
     int seq_bg;     // consecutive items per lane in the background adjoint
+    int fgg;        // chunks per wave (at most) in the foreground adjoint
     bool wide;      // background halo of 12 pixels or more (faces reach many pixels of a tile)
     int NS;         // per (pixel, sub-frame) value slots: colour, or log-sum and zero count
     int nfb;        // binning blocks per chunk

@@ -1745,33 +1745,35 @@ template <int T, int SOLVER>
 __global__ __launch_bounds__(64) void k_fg_bwd(const Inst *__restrict__ tab, int n)
 {
     __shared__ FgBwdShared<T> sh;
-    // one wave per (segment, tile): the segment's chunks share the keyframe
-    // pair, so one vertex table (and one flush) serves them all, and the
-    // tile's colour gradient is loaded once
+    // one wave per (group of up to a.fgg consecutive chunks of one segment,
+    // tile): the chunks share the keyframe pair, so one vertex table (and
+    // one flush) serves them, and the tile's colour gradient is loaded once;
+    // groups stay short so that the chunks' latencies are not all serialized
+    // in one wave
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const Inst &a = tab[inst_of<&Inst::b_fgb>(tab, n, lb)];
-    const int sti = lb - a.b_fgb;
-    const int seg = sti / a.ntiles, tile = sti - seg * a.ntiles;
+    const int gti = lb - a.b_fgb;
+    const int grp = gti / a.ntiles, tile = gti - grp * a.ntiles;
+    const int gps = (a.CPS + a.fgg - 1) / a.fgg;   // groups per segment
+    const int seg = grp / gps, gi = grp - seg * gps;
     const int lane = threadIdx.x & 63;
     if (a.hdr->error_bits & kHdrOverflow) return;
-    const int c0 = seg * a.CPS, c1 = c0 + a.CPS;
+    const int c0 = seg * a.CPS + gi * a.fgg, c1 = min(c0 + a.fgg, (seg + 1) * a.CPS);
     bool any = false;
     for (int c = c0; c < c1 && !any; ++c) any = a.fgw[(int64_t)c * a.ntiles + tile] != 0;
     if (!any) return;   // no chunk of the segment has a winner here
-    bool gcol = false;
+    // the tile's colour gradient: loaded here, stored to LDS once the first
+    // chunk's visibility loads are in flight too
+    float gIr[NCH];
+    bool gcol = false, gstored = false;
     {
         const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
         const int px = tx * kTile + (lane & 7), py = ty * kTile + (lane >> 3);
         const bool inimg = px < a.W && py < a.H;
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) {
-            float v = 0.0f;
-            if (inimg && ch < a.C) v = a.grad_image[((size_t)ch * a.H + py) * a.W + px] * a.invK;
-            sh.gI[ch][lane] = v;
-            gcol = gcol || v != 0.0f;
-        }
+        for (int ch = 0; ch < NCH; ++ch)
+            gIr[ch] = inimg && ch < a.C ? a.grad_image[((size_t)ch * a.H + py) * a.W + px] * a.invK : 0.0f;
     }
-    if (__ballot(gcol) == 0ull) return;
     vt_clear(sh.vt);
     int used = 0;
     for (int c = c0; c < c1; ++c) {
@@ -1786,8 +1788,17 @@ __global__ __launch_bounds__(64) void k_fg_bwd(const Inst *__restrict__ tab, int
         uint64_t pend[T];
         bool anyfg = false;
 #pragma unroll
+        for (int j = 0; j < T; ++j) vid[j] = j < ck.n ? a.vis_id[vis_index(a, g.tile, ck.k0 + j, lane)] : kVisOut;
+        if (!gstored) {
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) {
+                sh.gI[ch][lane] = gIr[ch];
+                gcol = gcol || gIr[ch] != 0.0f;
+            }
+            gstored = true;
+        }
+#pragma unroll
         for (int j = 0; j < T; ++j) {
-            vid[j] = j < ck.n ? a.vis_id[vis_index(a, g.tile, ck.k0 + j, lane)] : kVisOut;
             pend[j] = __ballot(gcol && vid[j] >= 0);
             anyfg = anyfg || pend[j] != 0ull;
         }
@@ -2206,6 +2217,7 @@ static Inst make_inst(const Plan &p, const Io &io, char *base, const Grids &star
     a.NC = p.NC;
     a.SL = p.SL;
     a.seq_bg = p.seq_bg;
+    a.fgg = p.fgg;
     a.NS = p.NS;
     a.nfb = p.nfb;
     a.ntct = (int)p.ntct;
@@ -2259,7 +2271,7 @@ static const Inst *write_table(const Batch &bt, const std::vector<Io> &io, void 
         start.tscan1 += p.nblocks_tscan;
         start.tscan3 += grid_for(p.ntct, 256);
         start.fg += p.ntct;
-        start.fgb += (int64_t)p.S * p.ntiles;
+        start.fgb += (int64_t)p.S * ((p.CPS + p.fgg - 1) / p.fgg) * p.ntiles;
         start.res += p.ntiles;
         start.bwdinit += grid_for((int64_t)(p.S + 1) * p.V * 2 + (int64_t)p.V * p.C, 256);
         start.vtx += grid_for(p.V, 256);
