@@ -78,6 +78,7 @@ static rb_status make_plan(int32_t V, int32_t F, int32_t C, const rb_motion *mot
     // images (fewer flushes), one per wave otherwise (more waves in flight;
     // grouping measured slower on the mixed batch of small images)
     p.fgg = wide_halo ? 3 : 1;
+    p.bwd_merge = 2;
     p.wide = wide_halo;
     p.NS = std::max(C, 2);
     p.nfb = (F + 255) / 256;

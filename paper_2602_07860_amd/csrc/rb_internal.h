@@ -107,6 +107,7 @@ struct Inst {
     int CPS, NC, SL, NS, nfb;
     int seq_bg;          // consecutive items per lane in the background adjoint
     int fgg;             // chunks per wave (at most) in the foreground adjoint
+    int bwd_merge;       // background tasks per unit of the background adjoint
     int ntct;            // (chunk, tile) pairs = NC * ntiles
     int nblocks_scan, nblocks_tscan;
     int64_t cap, maxtasks, ncounts;
@@ -129,6 +130,7 @@ struct Plan {
     int SL;         // background list entries per task
     int seq_bg;     // consecutive items per lane in the background adjoint
     int fgg;        // chunks per wave (at most) in the foreground adjoint
+    int bwd_merge;  // background tasks per unit of the background adjoint
     bool wide;      // background halo of 12 pixels or more (faces reach many pixels of a tile)
     int NS;         // per (pixel, sub-frame) value slots: colour, or log-sum and zero count
     int nfb;        // binning blocks per chunk
