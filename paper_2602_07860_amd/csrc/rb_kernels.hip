@@ -49,20 +49,6 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
 
 __device__ __forceinline__ int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
 
-__device__ __forceinline__ float wave_sum(float x)
-{
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
-    return x;
-}
-
-__device__ __forceinline__ uint32_t wave_or(uint32_t x)
-{
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) x |= (uint32_t)__shfl_xor((int)x, m, 64);
-    return x;
-}
-
 // 1 - exp(-x) for x >= 0 without cancellation at small x
 __device__ __forceinline__ float one_minus_exp_neg(float x, float A)
 {
