@@ -78,7 +78,9 @@ static rb_status make_plan(int32_t V, int32_t F, int32_t C, const rb_motion *mot
     // images (fewer flushes), one per wave otherwise (more waves in flight;
     // grouping measured slower on the mixed batch of small images)
     p.fgg = wide_halo ? 3 : 1;
-    p.bwd_merge = 2;
+    // background adjoint: units of two tasks where faces reach few pixels
+    // (per-task steps weigh more there); single tasks on wide halos
+    p.bwd_merge = wide_halo ? 1 : 2;
     p.wide = wide_halo;
     p.NS = std::max(C, 2);
     p.nfb = (F + 255) / 256;

@@ -8,8 +8,9 @@
       combine `rocprofv3 --pmc FETCH_SIZE` and `--pmc WRITE_SIZE` runs of the
       benchmark (DIR holds the run's counter_collection.csv) and of the copy
       into HBM bytes per launch of kernel K, and record them in FILE (JSON,
-      keyed "K@W") with a hash of the kernel source, so that the benchmark
-      reports the figure only while the kernels are the ones measured.
+      keyed "K@W") with a hash of the kernel sources and launch plan, so that
+      the benchmark reports the figure only while the kernels are the ones
+      measured.
 
 Nothing here runs on the rendering path.
 """
@@ -23,12 +24,18 @@ import json
 import os
 
 COPY_BYTES = 1 << 30
-SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "rb_kernels.hip")
+SOURCES = [os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", f)
+           for f in ("rb_kernels.hip", "rb_api.cpp", "rb_internal.h")]
 
 
 def source_hash() -> str:
-    with open(SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    """Hash of the kernel sources and of the host plan that sets their launch
+    parameters."""
+    h = hashlib.sha256()
+    for p in SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def _counter_mean(run_dir: str, counter: str, kernel_substr: str) -> float:
