@@ -56,7 +56,7 @@ enum {
     RB_EBEHIND = -4,       /* (header) a keyframe vertex has camera depth <= 1e-6        */
     RB_EOVERFLOW = -5,     /* (header) bin lists exceeded list_capacity: enlarge, rerun  */
     RB_EDEVICE = -6,       /* a HIP runtime call failed                                  */
-    RB_EUNSUPPORTED = -7   /* channel count, face count or option outside this build     */
+    RB_EUNSUPPORTED = -7   /* channel count, face count or option the library lacks     */
 };
 
 enum { RB_SOLVER_FAST = 0, RB_SOLVER_RECOMPUTE = 1 };
