@@ -53,13 +53,18 @@ static rb_status make_plan(int32_t V, int32_t F, int32_t C, const rb_motion *mot
     p.tiles_x = (p.W + kTile - 1) / kTile;
     p.tiles_y = (p.H + kTile - 1) / kTile;
     p.ntiles = p.tiles_x * p.tiles_y;
-    p.T = T;
     int nmax = 0;
     for (int s = 0; s < S; ++s) {
         int lo = seg_first(s, K, S), hi = (s == S - 1) ? K : seg_first(s + 1, K, S);
         nmax = std::max(nmax, hi - lo);
     }
-    p.CPS = std::max(1, (nmax + T - 1) / T);
+    // chunk_len is an upper bound: when every segment holds fewer sub-frames,
+    // the narrowest power of two that still takes a whole segment keeps the
+    // per-lane sub-frame arrays (and register use) small
+    int Te = T;
+    while (Te > 1 && Te / 2 >= nmax) Te /= 2;
+    p.T = Te;
+    p.CPS = std::max(1, (nmax + Te - 1) / Te);
     p.NC = S * p.CPS;
     // 32-bit chunk and (chunk, tile) index arithmetic on the device
     if ((long long)p.CPS * K >= (1LL << 31) || (long long)p.NC * p.ntiles >= (1LL << 31)) return RB_EUNSUPPORTED;
@@ -136,7 +141,9 @@ static rb_status make_batch(const std::vector<Plan> &plans, Batch &bt)
 {
     bt.n = (int)plans.size();
     if (bt.n <= 0) return RB_EINVAL;
-    bt.T = plans[0].T;
+    // every instance's chunks hold at most its own p.T <= the batch template
+    bt.T = 1;
+    for (const Plan &p : plans) bt.T = std::max(bt.T, p.T);
     bt.solver = plans[0].solver;
     bt.wide = true;
     for (const Plan &p : plans) bt.wide = bt.wide && p.wide;
