@@ -92,7 +92,7 @@ typedef struct {
     int32_t solver;          /* RB_SOLVER_FAST or RB_SOLVER_RECOMPUTE           */
     int32_t flags;           /* reserved, 0                                     */
     int32_t chunk_len;       /* max sub-frames per work chunk: 1, 2, 4 or 8; 0 = 4;
-                                narrowed when every segment is shorter       */
+                                a segment is split into equal chunks         */
     int32_t slice_len;       /* background-list entries per task; 0 = auto (64) */
     int64_t list_capacity;   /* bin-list entries (foreground + background); 0 = auto */
 } rb_options;

@@ -58,13 +58,12 @@ static rb_status make_plan(int32_t V, int32_t F, int32_t C, const rb_motion *mot
         int lo = seg_first(s, K, S), hi = (s == S - 1) ? K : seg_first(s + 1, K, S);
         nmax = std::max(nmax, hi - lo);
     }
-    // chunk_len is an upper bound: when every segment holds fewer sub-frames,
-    // the narrowest power of two that still takes a whole segment keeps the
-    // per-lane sub-frame arrays (and register use) small
-    int Te = T;
-    while (Te > 1 && Te / 2 >= nmax) Te /= 2;
-    p.T = Te;
-    p.CPS = std::max(1, (nmax + Te - 1) / Te);
+    p.CPS = std::max(1, (nmax + T - 1) / T);
+    // chunk_len bounds the chunk; the kernels are built for the longest chunk
+    // the balanced split makes (1, 2, 3, 4 or 8 sub-frames), which keeps the
+    // per-lane sub-frame arrays (and register use) no larger than needed
+    const int lmax = (nmax + p.CPS - 1) / p.CPS;
+    p.T = lmax <= 4 ? std::max(1, lmax) : 8;
     p.NC = S * p.CPS;
     // 32-bit chunk and (chunk, tile) index arithmetic on the device
     if ((long long)p.CPS * K >= (1LL << 31) || (long long)p.NC * p.ntiles >= (1LL << 31)) return RB_EUNSUPPORTED;

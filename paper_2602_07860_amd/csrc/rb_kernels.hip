@@ -2324,6 +2324,7 @@ hipError_t launch_forward(const Batch &bt, const std::vector<Io> &io, void *ws, 
     switch (bt.T) {
     case 1: fast ? forward_T<1, RB_SOLVER_FAST>(bt, tab, ws, st, pe) : forward_T<1, RB_SOLVER_RECOMPUTE>(bt, tab, ws, st, pe); break;
     case 2: fast ? forward_T<2, RB_SOLVER_FAST>(bt, tab, ws, st, pe) : forward_T<2, RB_SOLVER_RECOMPUTE>(bt, tab, ws, st, pe); break;
+    case 3: fast ? forward_T<3, RB_SOLVER_FAST>(bt, tab, ws, st, pe) : forward_T<3, RB_SOLVER_RECOMPUTE>(bt, tab, ws, st, pe); break;
     case 4: fast ? forward_T<4, RB_SOLVER_FAST>(bt, tab, ws, st, pe) : forward_T<4, RB_SOLVER_RECOMPUTE>(bt, tab, ws, st, pe); break;
     default: fast ? forward_T<8, RB_SOLVER_FAST>(bt, tab, ws, st, pe) : forward_T<8, RB_SOLVER_RECOMPUTE>(bt, tab, ws, st, pe); break;
     }
@@ -2359,6 +2360,7 @@ hipError_t launch_backward(const Batch &bt, const std::vector<Io> &io, void *ws,
     switch (bt.T) {
     case 1: fast ? backward_T<1, RB_SOLVER_FAST>(bt, tab, ws, st, pe) : backward_T<1, RB_SOLVER_RECOMPUTE>(bt, tab, ws, st, pe); break;
     case 2: fast ? backward_T<2, RB_SOLVER_FAST>(bt, tab, ws, st, pe) : backward_T<2, RB_SOLVER_RECOMPUTE>(bt, tab, ws, st, pe); break;
+    case 3: fast ? backward_T<3, RB_SOLVER_FAST>(bt, tab, ws, st, pe) : backward_T<3, RB_SOLVER_RECOMPUTE>(bt, tab, ws, st, pe); break;
     case 4: fast ? backward_T<4, RB_SOLVER_FAST>(bt, tab, ws, st, pe) : backward_T<4, RB_SOLVER_RECOMPUTE>(bt, tab, ws, st, pe); break;
     default: fast ? backward_T<8, RB_SOLVER_FAST>(bt, tab, ws, st, pe) : backward_T<8, RB_SOLVER_RECOMPUTE>(bt, tab, ws, st, pe); break;
     }

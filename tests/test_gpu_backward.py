@@ -37,7 +37,9 @@ def test_small_translation_gradients(solver):
     _grad_case(sc, solver)
 
 
-@pytest.mark.parametrize("chunk_len", [1, 4, 8])
+# segments of 4-5 sub-frames: chunk_len 1, 2, 4, 8 run the 1-, 2-, 3- and
+# 8-sub-frame kernel builds
+@pytest.mark.parametrize("chunk_len", [1, 2, 4, 8])
 def test_small_rotation_gradients(chunk_len):
     sc = wl.make_workload(wl.SMALL, motion=wl.Motion("rotate", axis=(0.3, 1.0, -0.2), revs=0.8,
                                                      trans=(0.3, 0.0, 0.0)),
