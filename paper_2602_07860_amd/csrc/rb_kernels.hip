@@ -2340,12 +2340,13 @@ static void backward_T(const Batch &bt, const Inst *tab, void *ws, hipStream_t s
     const int n = bt.n;
     hipLaunchKernelGGL((k_fg_bwd<T, SOLVER>), dim3((unsigned)bt.g.fgb), dim3(kWave), 0, st, tab, n);
     mark(pe, 1, st);
-    // the tasks vary in cost: more waves than fit at once, taking tasks from a counter
+    // the tasks vary in cost: one wave per resident slot, each taking tasks
+    // from a counter until none are left
     if (bt.wide) {
-        static const unsigned nw = 3 * resident_waves(k_bg_bwd<T, SOLVER, 4>) / 2;
+        static const unsigned nw = resident_waves(k_bg_bwd<T, SOLVER, 4>);
         hipLaunchKernelGGL((k_bg_bwd<T, SOLVER, 4>), dim3(nw), dim3(kWave), 0, st, tab, n);
     } else {
-        static const unsigned nw = 3 * resident_waves(k_bg_bwd<T, SOLVER, 3>) / 2;
+        static const unsigned nw = resident_waves(k_bg_bwd<T, SOLVER, 3>);
         hipLaunchKernelGGL((k_bg_bwd<T, SOLVER, 3>), dim3(nw), dim3(kWave), 0, st, tab, n);
     }
 }
