@@ -538,7 +538,9 @@ constexpr int NB = 32;              // list entries staged per batch
 constexpr int kVisOut = -4;         // vis_id of a pixel outside the image
 constexpr int kSeqFg = 4;           // consecutive items per lane in the foreground adjoint
 constexpr int kSeqBgFwd = 4;        // and in the background forward (grouped by pixel)
-constexpr unsigned kBgFwdOversub = 8;  // background-forward grid, in multiples of the resident waves
+// background-forward grid, in multiples of the resident waves: wide-halo
+// tasks vary more in cost and gain from finer dealing
+constexpr unsigned kBgFwdOversubWide = 32, kBgFwdOversubNarrow = 8;
 
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
@@ -2304,13 +2306,13 @@ static void forward_T(const Batch &bt, const Inst *tab, void *ws, hipStream_t st
     hipLaunchKernelGGL(k_tprefix, dim3(1), dim3(64), 0, st, tab, n, tprefix);
     mark(pe, 3, st);
     // tasks are dealt to waves in a fixed stride of the grid size; a grid of
-    // eight times the resident waves lets waves that drew cheap tasks hand
+    // several times the resident waves lets waves that drew cheap tasks hand
     // their slots to fresh ones, which evens out the tail
     if (bt.wide) {
-        static const unsigned nw = kBgFwdOversub * resident_waves(k_bg<T, SOLVER, true>);
+        static const unsigned nw = kBgFwdOversubWide * resident_waves(k_bg<T, SOLVER, true>);
         hipLaunchKernelGGL((k_bg<T, SOLVER, true>), dim3(nw), dim3(kWave), 0, st, tab, n, (const int64_t *)tprefix);
     } else {
-        static const unsigned nw = kBgFwdOversub * resident_waves(k_bg<T, SOLVER, false>);
+        static const unsigned nw = kBgFwdOversubNarrow * resident_waves(k_bg<T, SOLVER, false>);
         hipLaunchKernelGGL((k_bg<T, SOLVER, false>), dim3(nw), dim3(kWave), 0, st, tab, n, (const int64_t *)tprefix);
     }
 }
