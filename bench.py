@@ -3,14 +3,19 @@
 second of one forward + backward step.
 
 Workloads (synthetic, seeded; see paper_2602_07860_amd/workloads.py):
-  medium (default): nu=32 geodesic sphere (10242 V / 20480 F) displaced by
+  large (default): the shape-recovery loop on the nu=64 geodesic sphere
+    (40962 V / 81920 F), 1024x1024, K = 512 sub-frames, 5 revolutions about a
+    seeded axis plus a 200 px translation cut into S = 60 linear segments.
+    The target is the render of the seed-4 multi-octave displaced sphere with
+    seeded colours; the loop starts from the plain sphere with grey colours
+    and every step renders, takes dL/dI of an L2 loss over RGBA, runs the
+    adjoint and takes an Adam step (lr 0.01, betas (0.5, 0.99), the paper's
+    translation settings of App. J) on the vertex positions and colours.  The
+    first --warmup steps of the loop are untimed, the next --steps are timed.
+  medium: nu=32 geodesic sphere (10242 V / 20480 F) displaced by
     0.02 N(0,1), per-vertex RGB, 256x256, K = 64 sub-frames, 3 revolutions
     about a seeded axis cut into S = 36 linear segments; L2 loss against the
-    render of a second seeded displacement.
-  large: nu=64 (40962 V / 81920 F), multi-octave displacement, 1024x1024,
-    K = 512, 5 revolutions + 200 px translation in S = 60 segments, run as a
-    shape-recovery loop: every step also takes an Adam step on the vertex
-    positions and colours (the loop is timed end to end, --steps steps).
+    render of a second seeded displacement (static geometry).
   batch: 32 instances of mixed sizes, resolutions {128, 256, 512}^2,
     K in [32, 256], half translation / half rotation, all in one launch
     sequence captured in a graph and replayed; chunk and slice lengths from
@@ -21,9 +26,10 @@ for the fast solver (eq 8) and for the per-sub-frame recompute (eqs 1-3) on
 the same GPU.
 
 Prints ONE JSON line.  Extra objects: "roofline" for the dominant kernel
-(algorithmic FLOPs from the FP64 reference's exact pair counters, divided by
-the kernel's average duration measured with HIP events on its stream), and
-"cpu_baseline": the FP64 reference renderer timed on this host.
+(algorithmic FLOPs from the FP64 reference's exact pair counters on the
+geometry the profiled steps rendered, divided by the kernel's average
+duration measured with HIP events on its stream), and "cpu_baseline": the
+FP64 reference renderer timed on this host.
 """
 import argparse
 import json
@@ -73,12 +79,15 @@ def kernel_ms(prof):
             "vertex_grad": prof.vertex_grad_ms / b}
 
 
-def timed(fn, steps, B, torch, phases=True, phase_steps=None):
+def timed(fn, steps, B, torch, phases=True, phase_steps=None, phases_in_loop=False):
     """Average ms of fn() over `steps` calls (device events) and, optionally,
-    the per-kernel phases of a second pass of `phase_steps` (default `steps`)
-    calls."""
+    the per-kernel phases: recorded during those same calls (phases_in_loop;
+    the library's phase events cost microseconds per call) or over a second
+    pass of `phase_steps` (default `steps`) calls."""
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    if phases and phases_in_loop:
+        B.rb_profile_enable(True)
     e0.record()
     for _ in range(steps):
         fn()
@@ -87,22 +96,27 @@ def timed(fn, steps, B, torch, phases=True, phase_steps=None):
     ms = e0.elapsed_time(e1) / steps
     if not phases:
         return ms, None
-    B.rb_profile_enable(True)
-    for _ in range(phase_steps or steps):
-        fn()
-    torch.cuda.synchronize()
+    if not phases_in_loop:
+        B.rb_profile_enable(True)
+        for _ in range(phase_steps or steps):
+            fn()
+        torch.cuda.synchronize()
     prof = B.rb_profile_read()
     B.rb_profile_enable(False)
     return ms, kernel_ms(prof)
 
 
-def run_single(sc, tg, args, torch, B, R, adam=False):
+def run_single(start, tg, args, torch, B, R, adam=False):
+    """Time fwd + dL/dI + bwd on `start` against the render of `tg`; with adam,
+    every step also takes an Adam step (the shape-recovery loop).  Returns per
+    solver the ms per step, the per-kernel phases and the geometry the last
+    (phase-profiled) steps rendered."""
     dev = "cuda:0"
-    st = R.scene_tensors(sc, dev)
+    st = R.scene_tensors(start, dev)
     tt = R.scene_tensors(tg, dev)
 
     def opts(solver, check=True):
-        return R.RenderOptions(sc.num_subframes, solver=solver, chunk_len=args.chunk_len,
+        return R.RenderOptions(start.num_subframes, solver=solver, chunk_len=args.chunk_len,
                                slice_len=args.slice_len, check=check)
 
     target, _ = R.render_forward(tt.verts, tt.faces, tt.attrs, tt.model, tt.camera, opts("fast"))
@@ -112,11 +126,19 @@ def run_single(sc, tg, args, torch, B, R, adam=False):
         # shape recovery: the same start for both solvers; the geometry moves,
         # so every forward checks its bin lists (one header read)
         verts, attrs = st.verts.clone(), st.attrs.clone()
-        opt = torch.optim.Adam([{"params": [verts], "lr": 2e-4}, {"params": [attrs], "lr": 1e-3}]) if adam else None
+        opt = torch.optim.Adam([verts, attrs], lr=0.01, betas=(0.5, 0.99)) if adam else None
+
+        box["n"] = 0
+        mid = max(1, args.warmup) + (args.steps + 1) // 2   # the step in the middle of the timed ones
 
         def step():
             img, state = R.render_forward(verts, st.faces, attrs, st.model, st.camera, box["o"])
             gv, ga = R.render_backward(verts, st.faces, attrs, st.model, state, 2.0 * (img - target))
+            box["n"] += 1
+            if box["n"] == mid:
+                # geometry this step rendered: the oracle's pair counters are
+                # taken on it (the shape moves along the loop)
+                box["geom"] = (verts.detach().clone(), attrs.detach().clone())
             if opt is not None:
                 verts.grad, attrs.grad = gv, ga
                 opt.step()
@@ -126,14 +148,20 @@ def run_single(sc, tg, args, torch, B, R, adam=False):
             step()
             if not adam:
                 box["o"] = opts(solver, check=False)
-        ms, km = timed(step, args.steps, B, torch, phase_steps=min(args.steps, 3) if adam else None)
+        if "geom" not in box:
+            box["geom"] = (verts.detach().clone(), attrs.detach().clone())
+        ms, km = timed(step, args.steps, B, torch, phases_in_loop=adam)
         img, gv, ga, state = box["out"]
         h = B.rb_read_header(state.workspace.data_ptr(), torch.cuda.current_stream().cuda_stream)
         if h.error_bits:
             raise RuntimeError(f"device header reports error bits {h.error_bits}")
         if not (torch.isfinite(img).all() and torch.isfinite(gv).all() and torch.isfinite(ga).all()):
             raise RuntimeError("non-finite output")
-        res[solver] = dict(ms=ms, km=km)
+        loss = float(((img - target) ** 2).sum())
+        gv_, ga_ = box["geom"]
+        res[solver] = dict(ms=ms, km=km, loss=loss,
+                           geom=(gv_.cpu().numpy().astype(np.float32), ga_.cpu().numpy().astype(np.float32)))
+        del box, opt, verts, attrs
     return res
 
 
@@ -195,7 +223,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=("medium", "large", "batch"), default="medium")
+    ap.add_argument("--workload", choices=("medium", "large", "batch"), default="large")
     ap.add_argument("--chunk-len", type=int, default=4)
     ap.add_argument("--slice-len", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -224,16 +252,27 @@ def main():
                   "faces_total": int(sum(len(s.faces) for s in scenes)),
                   "chunk_len": res["fast"]["chunk_len"], "slice_len": res["fast"]["slice_len"], "solver": "fast"}
     else:
-        sc = wl.make_workload(wl.MEDIUM if args.workload == "medium" else wl.LARGE)
+        if args.workload == "medium":
+            sc = wl.make_workload(wl.MEDIUM)
+            tg = wl.make_target(sc, 2)
+            start, adam = sc, False
+        else:
+            tg = wl.make_workload(wl.LARGE)
+            start, adam = wl.plain_start(tg), True
+        res = run_single(start, tg, args, torch, B, R, adam=adam)
+        # the geometry of the middle timed step (the shape moves in the loop)
+        gv_, ga_ = res["fast"]["geom"]
+        sc = start.with_(verts=gv_, attrs=ga_)
         scenes = [sc]
-        tg = wl.make_target(sc, 2)
-        adam = args.workload == "large"
-        res = run_single(sc, tg, args, torch, B, R, adam=adam)
-        config = {"workload": f"{sc.name} fwd+bwd L2" + (f", {args.steps}-step Adam shape-recovery loop" if adam else ""),
+        config = {"workload": (f"{tg.name} Adam shape-recovery loop from the plain sphere (lr 0.01, betas 0.5/0.99), "
+                               f"fwd+bwd L2 per step, steps {args.warmup + 1}..{args.warmup + args.steps} timed"
+                               if adam else f"{sc.name} fwd+bwd L2"),
                   "vertices": int(len(sc.verts)),
                   "faces": int(len(sc.faces)), "resolution": f"{sc.width}x{sc.height}",
                   "subframes": sc.num_subframes, "segments": sc.num_segments, "solver": "fast",
                   "chunk_len": args.chunk_len}
+        if adam:
+            config["loss_after_loop"] = round(res["fast"]["loss"], 4)
     units = sum(s.height * s.width * s.num_subframes for s in scenes)
     for solver, r in res.items():
         log(f"{solver}: {r['ms']:.3f} ms/step  {units / (r['ms'] * 1e-3):.3e} px-sub/s  "

@@ -3,6 +3,13 @@
   python -m paper_2602_07860_amd.profiling copy
       a plain 1 GiB device-to-device copy, three times: the reference that
       scales rocprofv3's FETCH_SIZE / WRITE_SIZE counters to bytes;
+  python -m paper_2602_07860_amd.profiling summary DB [--title T] [--command C]
+      per-kernel table (calls, average and total milliseconds, share) of a
+      `rocprofv3 --kernel-trace --stats` run whose results database is DB;
+  python -m paper_2602_07860_amd.profiling counters CSV [--title T] [--command C]
+      per-kernel mean of every counter of a `rocprofv3 --pmc ... --output-format
+      csv` run (CSV = its counter_collection.csv), with the kernels' register,
+      scratch and LDS sizes;
   python -m paper_2602_07860_amd.profiling traffic --kernel K --workload W \\
           [--match NAME] --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR --out FILE
       combine `rocprofv3 --pmc FETCH_SIZE` and `--pmc WRITE_SIZE` runs of the
@@ -65,6 +72,62 @@ def lookup(path: str, kernel: str, workload: str):
     return rec["bytes_per_launch"]
 
 
+def _summary(a) -> None:
+    import sqlite3
+    db = sqlite3.connect(a.db)
+    per: dict = {}
+    for name, start, end in db.execute("select name, start, end from kernels order by start"):
+        per.setdefault(name, []).append(end - start)
+    rows = []
+    for name, d in per.items():
+        d = d[a.skip:]
+        if a.count > 0:
+            d = d[:a.count]
+        if d:
+            rows.append((name, len(d), sum(d) / len(d), sum(d)))
+    rows.sort(key=lambda r: -r[3])
+    tot = sum(r[3] for r in rows) or 1
+    out = ["# rocprofv3 kernel trace summary" + (f": {a.title}" if a.title else "")]
+    if a.command:
+        out.append(f"# command (from the repository root on the GPU box): {a.command}")
+    if a.skip or a.count:
+        out.append(f"# per kernel: its dispatches {a.skip + 1}.." + (f"{a.skip + a.count}" if a.count else "last")
+                   + " in time order")
+    out.append("# durations in milliseconds (avg per dispatch, total), share of total kernel time")
+    out.append("")
+    out.append(f"{'kernel':<72}{'calls':>7}{'avg_ms':>11}{'total_ms':>12}{'share%':>8}")
+    for name, n, avg, total in rows[:a.top]:
+        nm = name if len(name) <= 70 else name[:68] + ".."
+        out.append(f"{nm:<72}{n:>7}{avg / 1e6:>11.3f}{total / 1e6:>12.1f}{100.0 * total / tot:>8.2f}")
+    print("\n".join(out))
+
+
+def _counters(a) -> None:
+    agg: dict = {}
+    meta: dict = {}
+    with open(a.csv) as fh:
+        for r in csv.DictReader(fh):
+            k = r["Kernel_Name"]
+            agg.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+            meta[k] = (r["VGPR_Count"], r["Accum_VGPR_Count"], r["SGPR_Count"], r["Scratch_Size"], r["LDS_Block_Size"])
+    names = sorted({c for d in agg.values() for c in d})
+    out = ["# rocprofv3 counters, mean per dispatch" + (f": {a.title}" if a.title else "")]
+    if a.command:
+        out.append(f"# command (from the repository root on the GPU box): {a.command}")
+    out.append("# vgpr/agpr/sgpr as rocprofv3 reports them (allocation granules), scratch bytes per lane, LDS bytes")
+    out.append("")
+    out.append(f"{'kernel':<48}{'n':>4}" + "".join(f"{c.replace('SQ_', ''):>22}" for c in names)
+               + "   vgpr/agpr/sgpr/scratch/lds")
+    order = sorted(agg, key=lambda k: -max(sum(v) / len(v) for v in agg[k].values()))
+    for k in order[:a.top]:
+        d = agg[k]
+        n = max(len(v) for v in d.values())
+        nm = k if len(k) <= 46 else k[:44] + ".."
+        out.append(f"{nm:<48}{n:>4}" + "".join(f"{(sum(d[c]) / len(d[c])) if c in d else float('nan'):>22.6g}"
+                                               for c in names) + "   " + "/".join(meta[k]))
+    print("\n".join(out))
+
+
 def _copy() -> None:
     import torch
     x = torch.ones(COPY_BYTES // 4, device="cuda")
@@ -99,6 +162,18 @@ def main() -> None:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     sub = ap.add_subparsers(dest="cmd", required=True)
     sub.add_parser("copy")
+    sm = sub.add_parser("summary")
+    sm.add_argument("db")
+    sm.add_argument("--title", default="")
+    sm.add_argument("--command", default="")
+    sm.add_argument("--top", type=int, default=24)
+    sm.add_argument("--skip", type=int, default=0, help="skip each kernel's first N dispatches")
+    sm.add_argument("--count", type=int, default=0, help="then keep N dispatches (0: all)")
+    cn = sub.add_parser("counters")
+    cn.add_argument("csv")
+    cn.add_argument("--title", default="")
+    cn.add_argument("--command", default="")
+    cn.add_argument("--top", type=int, default=16)
     t = sub.add_parser("traffic")
     t.add_argument("--kernel", required=True)
     t.add_argument("--match", default="", help="substring of the profiled kernel names (default: --kernel)")
@@ -112,6 +187,10 @@ def main() -> None:
     a = ap.parse_args()
     if a.cmd == "copy":
         _copy()
+    elif a.cmd == "summary":
+        _summary(a)
+    elif a.cmd == "counters":
+        _counters(a)
     else:
         _traffic(a)
 

@@ -27,7 +27,7 @@ import numpy as np
 
 __all__ = [
     "Motion", "Scene", "geodesic_sphere", "look_at_view", "make_workload",
-    "make_target", "make_batch", "square_scene", "single_triangle_scene",
+    "make_target", "make_batch", "plain_start", "square_scene", "single_triangle_scene",
     "SMALL", "MEDIUM", "LARGE", "BATCH", "WORKLOAD_NAMES",
 ]
 
@@ -281,6 +281,17 @@ def make_target(sc: Scene, seed: int) -> Scene:
     v, f, c, _ = displaced_sphere(nu, seed, sigma=0.02, octaves=octaves)
     assert np.array_equal(f, sc.faces)
     return sc.with_(verts=v, attrs=c)
+
+
+def plain_start(sc: Scene, grey: float = 0.5) -> Scene:
+    """Start of a shape-recovery loop toward ``sc``: the undisplaced geodesic
+    sphere of the same frequency (same faces, unit radius) with every vertex
+    attribute set to ``grey``, under the same motion and camera."""
+    nu = int(round(math.sqrt(len(sc.faces) / 20)))
+    v, f = geodesic_sphere(nu)
+    assert np.array_equal(f, sc.faces)
+    return sc.with_(verts=v.astype(np.float32), attrs=np.full_like(sc.attrs, grey, dtype=np.float32),
+                    name=sc.name + "-plain-start")
 
 
 def make_batch(seed: int = 3, n: int = 32) -> List[Scene]:
