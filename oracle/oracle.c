@@ -37,14 +37,18 @@
 #endif
 
 #define ORC_TAU_DET 1e-10      /* reading: |det F(tau)| <= this => face skipped */
-#define ORC_GUARD_W 2e-5       /* guard band on min_i w_i for parity reporting */
+/* Guard band: decisions that a float32 evaluation of the same quantities can
+ * take either way.  The widths are multiples of the float32 unit roundoff
+ * applied to the magnitudes that enter each decision (see orc_bg_band). */
+#define ORC_EPS32 5.9604644775390625e-8   /* 2^-24, float32 unit roundoff */
+#define ORC_GUARD_W 2e-5       /* |min_i w_i| below this: coverage may flip */
 #define ORC_GUARD_DEPTH 1e-6   /* relative depth near-tie */
-#define ORC_GUARD_EDGE 1e-9    /* relative near-tie between edge distances */
-#define ORC_GUARD_SIGMA 2e-5   /* edge parameter near a clamp bound (times max |w|) */
-#define ORC_GUARD_EDGE_GRAD 1e-5 /* relative edge near-tie that may change the gradient */
-#define ORC_MAX_AMBIG 6
+#define ORC_GUARD_ULPS 8.0     /* guard widths: this many times the float32 error estimate */
+#define ORC_COND_MIN 1e-4      /* terms whose float32 relative error may exceed this get a bound */
+#define ORC_MAX_AMBIG 8
 
-enum { CNT_BBOX, CNT_COV, CNT_FG, CNT_BG, CNT_BGPAIRS, CNT_SETUP, CNT_FLAGGED, CNT_SKIP, ORC_NCNT };
+enum { CNT_BBOX, CNT_COV, CNT_FG, CNT_BG, CNT_BGPAIRS, CNT_SETUP, CNT_FLAGGED, CNT_SKIP,
+       CNT_ALT_VALUE, CNT_ALT_GRAD, CNT_UNBOUNDED, ORC_NCNT };
 
 typedef struct {
     int V, F, C, S, K, W, H;
@@ -167,46 +171,55 @@ static double orc_solve_fast(const double K0[3][3], const double K1[3][3], doubl
 /* Closest point on a triangle (App. B, "Euclidean Distance Approximation"):
  * project q on the edges (0,1), (1,2), (2,0), clamp the edge parameter to
  * [0,1], keep the edge whose point is nearest (first one on exact ties).
- * Returns the squared distance; *gap receives the relative gap to the
- * runner-up edge whose point differs (for the parity guard band). */
-static double orc_closest_edge(const double T[3][2], double qx, double qy,
-                               int *edge, double *sigma, int *clamp, double *sigma_raw,
-                               double *gap)
+ * Also reports the runner-up: the nearest other edge whose closest point
+ * differs from the chosen one (for the parity guard band). */
+typedef struct {
+    int edge, clamp;       /* chosen edge; clamp state 0 (sigma < 0), 1 (inside), 2 (sigma > 1) */
+    double sigma, sigma_raw, dist;
+    int edge2, clamp2;     /* runner-up edge with a different closest point, -1 if none */
+    double sigma2, dist2;
+} orc_cp;
+
+static void orc_closest_edge(const double T[3][2], double qx, double qy, orc_cp *cp)
 {
-    double best = INFINITY, second = INFINITY;
-    double bpx = 0, bpy = 0;
+    double t[3], tr[3], px[3], py[3], dist[3];
+    int cl[3];
     for (int e = 0; e < 3; ++e) {
         int a = e, b = (e + 1) % 3;
         double ex = T[b][0] - T[a][0], ey = T[b][1] - T[a][1];
         double ee = ex * ex + ey * ey;
-        double t = ee > 0 ? ((qx - T[a][0]) * ex + (qy - T[a][1]) * ey) / ee : 0.0;
-        double traw = t;
-        int cl = 1;
-        if (t < 0) { t = 0; cl = 0; } else if (t > 1) { t = 1; cl = 2; }
-        if (ee <= 0) cl = 0;
-        double px = T[a][0] + t * ex, py = T[a][1] + t * ey;
-        double dist = (qx - px) * (qx - px) + (qy - py) * (qy - py);
-        if (dist < best) {
-            if (fabs(px - bpx) + fabs(py - bpy) > 1e-12 || best == INFINITY) second = best;
-            best = dist; *edge = e; *sigma = t; *clamp = cl; *sigma_raw = traw;
-            bpx = px; bpy = py;
-        } else if (dist < second && fabs(px - bpx) + fabs(py - bpy) > 1e-12) {
-            second = dist;
-        }
+        tr[e] = ee > 0 ? ((qx - T[a][0]) * ex + (qy - T[a][1]) * ey) / ee : 0.0;
+        t[e] = tr[e];
+        cl[e] = 1;
+        if (t[e] < 0) { t[e] = 0; cl[e] = 0; } else if (t[e] > 1) { t[e] = 1; cl[e] = 2; }
+        if (ee <= 0) cl[e] = 0;
+        px[e] = T[a][0] + t[e] * ex;
+        py[e] = T[a][1] + t[e] * ey;
+        dist[e] = (qx - px[e]) * (qx - px[e]) + (qy - py[e]) * (qy - py[e]);
     }
-    *gap = (second - best) / (fabs(best) + 1e-300);
-    return best;
+    int b = 0;
+    for (int e = 1; e < 3; ++e) if (dist[e] < dist[b]) b = e;
+    int r = -1;
+    for (int e = 0; e < 3; ++e) {
+        if (e == b || fabs(px[e] - px[b]) + fabs(py[e] - py[b]) <= 1e-12) continue;
+        if (r < 0 || dist[e] < dist[r]) r = e;
+    }
+    cp->edge = b; cp->clamp = cl[b]; cp->sigma = t[b]; cp->sigma_raw = tr[b]; cp->dist = dist[b];
+    cp->edge2 = r;
+    cp->clamp2 = r >= 0 ? cl[r] : 0;
+    cp->sigma2 = r >= 0 ? t[r] : 0.0;
+    cp->dist2 = r >= 0 ? dist[r] : INFINITY;
 }
 
 void orc_closest_point(const double *tri /*[3][2]*/, double qx, double qy, double *wstar /*[3]*/)
 {
     double T[3][2];
-    int e, cl; double sg, sr, gap;
+    orc_cp cp;
     for (int i = 0; i < 3; ++i) { T[i][0] = tri[2 * i]; T[i][1] = tri[2 * i + 1]; }
-    orc_closest_edge(T, qx, qy, &e, &sg, &cl, &sr, &gap);
+    orc_closest_edge(T, qx, qy, &cp);
     wstar[0] = wstar[1] = wstar[2] = 0.0;
-    wstar[e] = 1.0 - sg;
-    wstar[(e + 1) % 3] += sg;
+    wstar[cp.edge] = 1.0 - cp.sigma;
+    wstar[(cp.edge + 1) % 3] += cp.sigma;
 }
 
 /* --------------------------------------------------------- render core -- */
@@ -229,9 +242,12 @@ typedef struct {
 } orc_eval;
 
 typedef struct {      /* one background face's forward quantities          */
-    int f, edge, clamp;
+    int f, j;          /* face; its index among the sub-frame's candidates  */
+    int edge, clamp;
     double A, om, d, sigma, sigma_raw;
     double w[3];
+    int nalt;          /* guard band: other (edge, clamp) decisions a float32 */
+    int alt_edge[2], alt_clamp[2];   /* evaluation can take                  */
 } orc_bgterm;
 
 static void orc_face_pos(const orc_ctx *cx, int f, int k, int s, double tau, double P[3][3])
@@ -259,7 +275,9 @@ static void orc_face_key(const orc_ctx *cx, int f, int s, double K[3][3])
     }
 }
 
-/* Barycentrics, depth and coverage of one face at one (pixel, sub-frame). */
+/* Barycentrics, depth and coverage of one face at one (pixel, sub-frame).
+ * min w and depth are kept for skipped faces too (the guard band asks what
+ * the face would do if a float32 evaluation did not skip it). */
 static void orc_eval_face(const orc_ctx *cx, orc_eval *ev, int s, double tau, double u, double v)
 {
     const orc_scene *sc = cx->sc;
@@ -272,15 +290,62 @@ static void orc_eval_face(const orc_ctx *cx, orc_eval *ev, int s, double tau, do
         ev->D = orc_solve_naive(ev->P, u, v, ev->w);
     }
     ev->skip = !(fabs(ev->D) > ORC_TAU_DET);
-    if (ev->skip) { ev->cover = 0; ev->mw = -INFINITY; ev->depth = INFINITY; return; }
     ev->mw = fmin(ev->w[0], fmin(ev->w[1], ev->w[2]));
-    ev->cover = ev->mw >= 0.0;                       /* reading: inclusive */
     ev->depth = ev->w[0] * ev->P[0][2] + ev->w[1] * ev->P[1][2] + ev->w[2] * ev->P[2][2];
+    if (!isfinite(ev->mw)) ev->mw = -INFINITY;
+    if (!isfinite(ev->depth)) ev->depth = INFINITY;
+    ev->cover = !ev->skip && ev->mw >= 0.0;          /* reading: inclusive */
 }
 
-/* Background term of one face (eqs 10, 13, 14).  Returns 1 if it contributes. */
+/* Float32 error model of the barycentrics w_i = N_i / det F, evaluated from
+ * rounded coordinates:
+ *  - each numerator N_i (a cross product of a pixel-to-vertex vector and an
+ *    edge) carries an absolute error of about eps32 r e, with r the largest
+ *    pixel-to-vertex distance and e the longest edge, so each w_i an
+ *    independent absolute error of about eps32 r e / |det F| (orc_w_err);
+ *  - det F carries a relative error of about eps32 (sum of squared edges) /
+ *    |det F| (orc_det_rel), common to all three w_i. */
+static double orc_w_err(const orc_eval *ev, double u, double v)
+{
+    double r = 0, e = 0;
+    for (int i = 0; i < 3; ++i) {
+        int j = (i + 1) % 3;
+        double dx = ev->P[j][0] - ev->P[i][0], dy = ev->P[j][1] - ev->P[i][1];
+        e = fmax(e, sqrt(dx * dx + dy * dy));
+        r = fmax(r, sqrt((ev->P[i][0] - u) * (ev->P[i][0] - u) + (ev->P[i][1] - v) * (ev->P[i][1] - v)));
+    }
+    return fabs(ev->D) > 0 ? ORC_EPS32 * r * e / fabs(ev->D) : INFINITY;
+}
+
+static double orc_det_rel(const orc_eval *ev)
+{
+    double ee = 0;
+    for (int i = 0; i < 3; ++i) {
+        int j = (i + 1) % 3;
+        double dx = ev->P[j][0] - ev->P[i][0], dy = ev->P[j][1] - ev->P[i][1];
+        ee += dx * dx + dy * dy;
+    }
+    return fabs(ev->D) > 0 ? ORC_EPS32 * ee / fabs(ev->D) : INFINITY;
+}
+
+/* Half-width of the coverage guard band on min_i w_i. */
+static double orc_w_band(const orc_eval *ev, double u, double v)
+{
+    return fmax(ORC_GUARD_W, ORC_GUARD_ULPS * orc_w_err(ev, u, v));
+}
+
+static double orc_hyp(double x, double y) { return sqrt(x * x + y * y); }
+
+/* Background term of one face (eqs 10, 13, 14).  Returns 1 if it contributes.
+ * Without a forced decision it also lists the closest-point decisions a
+ * float32 evaluation could take instead: the clamp state when the edge
+ * parameter is within rounding distance of 0 or 1, and the runner-up edge
+ * when its (different) closest point is within rounding distance as near.
+ * Rounding distance: ORC_GUARD_ULPS times the float32 error of q = F(X) w
+ * (pixel and keyframe coordinates, the motion term, the error of w times
+ * the vertices' motion) and of the edge projection. */
 static int orc_bg_face(const orc_ctx *cx, const orc_eval *ev, int s, int X, double u, double v,
-                       int forced_edge, int forced_clamp, orc_bgterm *bt, double *gap)
+                       int forced_edge, int forced_clamp, orc_bgterm *bt)
 {
     const orc_scene *sc = cx->sc;
     double T[3][2], qx, qy;
@@ -297,14 +362,53 @@ static int orc_bg_face(const orc_ctx *cx, const orc_eval *ev, int s, int X, doub
             qy += ev->w[i] * KX[i][1];
         }
     }
-    int e, cl; double sg, sr;
-    orc_closest_edge(T, qx, qy, &e, &sg, &cl, &sr, gap);
+    orc_cp cp;
+    orc_closest_edge(T, qx, qy, &cp);
+    int e = cp.edge, cl = cp.clamp;
+    double sg = cp.sigma, sr = cp.sigma_raw;
+    bt->nalt = 0;
     if (forced_edge >= 0) {            /* frozen-decision replay */
         int a = forced_edge, b = (forced_edge + 1) % 3;
         double ex = T[b][0] - T[a][0], ey = T[b][1] - T[a][1], ee = ex * ex + ey * ey;
         sr = ee > 0 ? ((qx - T[a][0]) * ex + (qy - T[a][1]) * ey) / ee : 0.0;
         e = forced_edge; cl = forced_clamp;
         sg = cl == 0 ? 0.0 : (cl == 2 ? 1.0 : sr);
+    } else {
+        /* float32 error of q = p + m, m = sum_i w_i (v_i(X) - v_i(tau)):
+         * rounding of the pixel and keyframe coordinates and of m, and the
+         * independent errors of the w_i times the vertices' motion (dq);
+         * the relative error of det F, common to the w_i, scales m (rho) */
+        double mx = 0, my = 0, wdv = 0;
+        for (int i = 0; i < 3; ++i) {
+            double dx = T[i][0] - ev->P[i][0], dy = T[i][1] - ev->P[i][1];
+            mx += ev->w[i] * dx; my += ev->w[i] * dy;
+            wdv += orc_hyp(dx, dy);
+        }
+        double mm = orc_hyp(mx, my), rho = orc_det_rel(ev);
+        double dq = ORC_EPS32 * (orc_hyp(u - T[0][0], v - T[0][1]) + mm) + orc_w_err(ev, u, v) * wdv;
+        int a = e, b = (e + 1) % 3;
+        double len = orc_hyp(T[b][0] - T[a][0], T[b][1] - T[a][1]);
+        double ra = orc_hyp(qx - T[a][0], qy - T[a][1]);
+        if (len > 0) {
+            /* det F's common relative error scales the motion term m, so it
+             * moves the edge parameter by rho |m . e| / |e|^2 */
+            double me = fabs(mx * (T[b][0] - T[a][0]) + my * (T[b][1] - T[a][1])) / (len * len);
+            double band = ORC_GUARD_ULPS * ((dq + ORC_EPS32 * (ra + len)) / len + rho * me);
+            if (fabs(sr) < band || fabs(sr - 1.0) < band) {
+                bt->alt_edge[bt->nalt] = e;
+                bt->alt_clamp[bt->nalt++] = cl != 1 ? 1 : (fabs(sr) < band ? 0 : 2);
+            }
+        }
+        if (cp.edge2 >= 0) {
+            int a2 = cp.edge2, b2 = (cp.edge2 + 1) % 3;
+            double len2 = orc_hyp(T[b2][0] - T[a2][0], T[b2][1] - T[a2][1]);
+            double ra2 = orc_hyp(qx - T[a2][0], qy - T[a2][1]);
+            double tol = ORC_GUARD_ULPS * (dq + rho * mm + ORC_EPS32 * (ra + len + ra2 + len2));
+            if (sqrt(cp.dist2) - sqrt(cp.dist) < tol) {
+                bt->alt_edge[bt->nalt] = cp.edge2;
+                bt->alt_clamp[bt->nalt++] = cp.clamp2;
+            }
+        }
     }
     int a = e, b = (e + 1) % 3;
     /* eq 14 (reading): p* = F(tau) w*, distance measured at the sub-frame */
@@ -313,21 +417,52 @@ static int orc_bg_face(const orc_ctx *cx, const orc_eval *ev, int s, int X, doub
     double d = (u - px) * (u - px) + (v - py) * (v - py);
     bt->f = ev->f; bt->edge = e; bt->clamp = cl; bt->sigma = sg; bt->sigma_raw = sr; bt->d = d;
     for (int i = 0; i < 3; ++i) bt->w[i] = ev->w[i];
-    if (forced_edge < 0 && sc->eps_cutoff > 0 && d > cx->dmax) return 0;
     bt->A = exp(-d / sc->delta);
     bt->om = -expm1(-d / sc->delta);
+    if (forced_edge < 0 && sc->eps_cutoff > 0 && d > cx->dmax) return 0;
     return 1;
 }
 
-/* gradient buffers of one thread */
-typedef struct { double *gkf; double *gattr; } orc_grad;
+/* Gradient buffers of one thread: dense accumulators, or (journal mode) a
+ * list of (index, value) additions of one (pixel, sub-frame), used to
+ * compare the gradient contributions of alternative decisions.  Index
+ * space: keyframe gradient [S+1][V][2], then attributes [V][C]. */
+typedef struct {
+    double *gkf;
+    double *gattr;
+    int journal;
+    size_t *ji; double *jv; int jn, jcap;
+} orc_grad;
+
+static void orc_gput(const orc_ctx *cx, orc_grad *g, size_t idx, double val)
+{
+    if (g->journal) {
+        if (g->jn == g->jcap) {
+            g->jcap = g->jcap ? 2 * g->jcap : 256;
+            g->ji = (size_t *)realloc(g->ji, sizeof(size_t) * g->jcap);
+            g->jv = (double *)realloc(g->jv, sizeof(double) * g->jcap);
+        }
+        g->ji[g->jn] = idx;
+        g->jv[g->jn++] = val;
+        return;
+    }
+    size_t nkf = (size_t)(cx->sc->S + 1) * cx->sc->V * 2;
+    if (idx < nkf) g->gkf[idx] += val;
+    else g->gattr[idx - nkf] += val;
+}
 
 static void orc_add_kf(const orc_ctx *cx, orc_grad *g, int f, int i, int s, double gx, double gy)
 {
     int V = cx->sc->V;
-    int vi = cx->sc->faces[f * 3 + i];
-    double *p = g->gkf + ((size_t)s * V + vi) * 2;
-    p[0] += gx; p[1] += gy;
+    size_t p = ((size_t)s * V + cx->sc->faces[f * 3 + i]) * 2;
+    orc_gput(cx, g, p, gx);
+    orc_gput(cx, g, p + 1, gy);
+}
+
+static void orc_add_attr(const orc_ctx *cx, orc_grad *g, int vi, int c, double val)
+{
+    const orc_scene *sc = cx->sc;
+    orc_gput(cx, g, (size_t)(sc->S + 1) * sc->V * 2 + (size_t)vi * sc->C + c, val);
 }
 
 /* d(w . gw)/d(vertex positions at tau): dw = -F^-1 dF w (static solve),
@@ -397,8 +532,8 @@ static void orc_shade(const orc_scene *sc, const orc_eval *ev, double *rgb)
     }
 }
 
-/* z-buffer: closest covering face, ties to the lowest face index (reading).
- * mode 0: nominal cover flags; mode 1: custom subset via incl[] */
+/* z-buffer over the faces with incl[j] set: closest covering face, ties to
+ * the lowest face index (reading) */
 static int orc_zbuffer(const orc_eval *ev, int n, const int *incl)
 {
     int best = -1;
@@ -412,13 +547,21 @@ static int orc_zbuffer(const orc_eval *ev, int n, const int *incl)
 
 typedef struct {
     orc_eval *ev;     /* candidates of the current (pixel, sub-frame)      */
-    orc_bgterm *bt;
+    orc_bgterm *bt;   /* its contributing background terms                 */
+    orc_bgterm *bta;  /* guard band: background term of every candidate    */
+    orc_bgterm *bt2;  /* guard band: terms of an alternative face set      */
+    int *bta_ok, *skp;
     int *incl;
     int *cand;        /* row-segment candidates                            */
     int *pcand;       /* pixel-segment candidates                          */
     char *seen;       /* per pcand: bbox hit somewhere in the segment      */
     double *pre, *suf;
     orc_grad grad;
+    /* guard band, gradient side: nominal journal, per-index scratch,
+     * running max over alternatives, and the accumulated bound */
+    size_t *j0i; double *j0v; int j0n, j0cap;
+    double *dtmp, *dmx, *slack;
+    size_t *mxl; int mxn, mxcap;
     double cnt[ORC_NCNT];
     orc_bg_rec *rl; int rl_n, rl_cap;
 } orc_tls;
@@ -435,27 +578,14 @@ static void orc_push_rec(orc_tls *t, orc_bg_rec r)
 /* background alpha of the current (pixel, sub-frame) over every non-skipped
  * candidate; fills t->bt; returns number of contributing faces */
 static int orc_background(const orc_ctx *cx, orc_tls *t, int n, int s, int X, double u, double v,
-                          double *alpha, int *edge_tie)
+                          double *alpha)
 {
     int m = 0;
     double prod = 1.0;
-    *edge_tie = 0;   /* bit 0: closest points of two edges tie; bit 1: edge parameter at a clamp bound */
     for (int j = 0; j < n; ++j) {
         if (t->ev[j].skip) continue;
-        double gap;
-        if (orc_bg_face(cx, &t->ev[j], s, X, u, v, -1, 0, &t->bt[m], &gap)) {
-            /* two edges whose closest points differ are nearly as close: the
-             * value is continuous across the switch, the frozen-decision
-             * derivative (which vertices and whether the edge parameter
-             * carries gradient) is not */
-            if (gap < ORC_GUARD_EDGE) *edge_tie |= 3;
-            else if (gap < ORC_GUARD_EDGE_GRAD) *edge_tie |= 2;
-            /* the edge parameter within rounding distance of 0 or 1: the value
-             * is continuous there but the frozen-decision derivative is not */
-            const orc_bgterm *bq = &t->bt[m];
-            double wm = fmax(1.0, fmax(fabs(bq->w[0]), fmax(fabs(bq->w[1]), fabs(bq->w[2]))));
-            double gs = ORC_GUARD_SIGMA * wm;
-            if (fabs(bq->sigma_raw) < gs || fabs(bq->sigma_raw - 1.0) < gs) *edge_tie |= 2;
+        if (orc_bg_face(cx, &t->ev[j], s, X, u, v, -1, 0, &t->bt[m])) {
+            t->bt[m].j = j;
             prod *= t->bt[m].om;
             ++m;
         }
@@ -464,31 +594,192 @@ static int orc_background(const orc_ctx *cx, orc_tls *t, int n, int s, int X, do
     return m;
 }
 
-/* Parity guard band of the foreground decision of one (pixel, sub-frame).
- * Enumerates every in/out choice of the faces whose min w is within
- * ORC_GUARD_W of 0, plus depth near-ties of each resulting z-buffer.
- * Returns bit 0 if a flip would move the sub-frame value by more than thr,
- * bit 1 if the z-buffer winner (whose vertices receive the gradient) could
- * change at all. */
-static int orc_guard(const orc_ctx *cx, orc_tls *t, int n, int s, int X, double u, double v,
-                     int nominal, const double *val, double thr)
+/* Adjoint of the winner's shading (eq 9) and its barycentrics. */
+static void orc_adj_fg(const orc_ctx *cx, orc_grad *g, const orc_eval *ev, const double *gI, int s, double tau)
 {
     const orc_scene *sc = cx->sc;
-    int amb[ORC_MAX_AMBIG], na = 0;
-    for (int j = 0; j < n; ++j) {
-        if (fabs(t->ev[j].D) >= 0.5 * ORC_TAU_DET && fabs(t->ev[j].D) <= 2.0 * ORC_TAU_DET) return 3;
-        if (t->ev[j].skip) continue;
-        if (fabs(t->ev[j].mw) < ORC_GUARD_W) {
-            if (na == ORC_MAX_AMBIG) return 3;
-            amb[na++] = j;
+    double gw[3];
+    for (int i = 0; i < 3; ++i) {
+        int vi = sc->faces[ev->f * 3 + i];
+        gw[i] = 0;
+        for (int c = 0; c < sc->C; ++c) {
+            gw[i] += gI[c] * sc->attrs[(size_t)vi * sc->C + c];
+            orc_add_attr(cx, g, vi, c, ev->w[i] * gI[c]);
         }
     }
-    double bgalpha = -1.0;
+    orc_adj_bary(cx, g, ev, ev->w, gw, s, tau);
+}
+
+/* Adjoint of alpha = 1 - prod_j (1 - A_j) over the terms bt[0..m):
+ * d alpha / d A_j = prod_{m != j} (1 - A_m) by prefix/suffix products. */
+static void orc_adj_bgset(const orc_ctx *cx, orc_grad *g, orc_tls *t, const orc_bgterm *bt, int m,
+                          const double *gI, int s, double tau, int X, double u, double v)
+{
+    const orc_scene *sc = cx->sc;
+    t->pre[0] = 1.0;
+    for (int q = 0; q < m; ++q) t->pre[q + 1] = t->pre[q] * bt[q].om;
+    t->suf[m] = 1.0;
+    for (int q = m - 1; q >= 0; --q) t->suf[q] = t->suf[q + 1] * bt[q].om;
+    for (int q = 0; q < m; ++q) {
+        double dA = gI[sc->C] * t->pre[q] * t->suf[q + 1];
+        orc_adj_bg(cx, g, &t->ev[bt[q].j], &bt[q], s, tau, X, u, v, dA * (-bt[q].A / sc->delta));
+    }
+}
+
+static void orc_journal_begin(orc_grad *g) { g->journal = 1; g->jn = 0; }
+
+/* keep the current journal as the nominal one */
+static void orc_journal_keep(orc_tls *t)
+{
+    orc_grad *g = &t->grad;
+    if (t->j0cap < g->jn) {
+        t->j0cap = g->jn;
+        t->j0i = (size_t *)realloc(t->j0i, sizeof(size_t) * t->j0cap);
+        t->j0v = (double *)realloc(t->j0v, sizeof(double) * t->j0cap);
+    }
+    memcpy(t->j0i, g->ji, sizeof(size_t) * g->jn);
+    memcpy(t->j0v, g->jv, sizeof(double) * g->jn);
+    t->j0n = g->jn;
+    g->journal = 0;
+}
+
+/* alternative (current journal) minus nominal, per index: into the running
+ * max (to_max) or added in magnitude to the bound directly */
+static void orc_journal_diff(orc_tls *t, int to_max)
+{
+    orc_grad *g = &t->grad;
+    g->journal = 0;
+    for (int e = 0; e < t->j0n; ++e) t->dtmp[t->j0i[e]] -= t->j0v[e];
+    for (int e = 0; e < g->jn; ++e) t->dtmp[g->ji[e]] += g->jv[e];
+    for (int pass = 0; pass < 2; ++pass) {
+        const size_t *ix = pass ? g->ji : t->j0i;
+        int ne = pass ? g->jn : t->j0n;
+        for (int e = 0; e < ne; ++e) {
+            size_t i = ix[e];
+            double d = fabs(t->dtmp[i]);
+            t->dtmp[i] = 0.0;
+            if (!to_max) { t->slack[i] += d; continue; }
+            if (d > t->dmx[i]) {
+                if (t->dmx[i] == 0.0) {
+                    if (t->mxn == t->mxcap) {
+                        t->mxcap = t->mxcap ? 2 * t->mxcap : 256;
+                        t->mxl = (size_t *)realloc(t->mxl, sizeof(size_t) * t->mxcap);
+                    }
+                    t->mxl[t->mxn++] = i;
+                }
+                t->dmx[i] = d;
+            }
+        }
+    }
+}
+
+/* the current journal's magnitudes, times scale, added to the bound */
+static void orc_journal_addabs(orc_tls *t, double scale)
+{
+    orc_grad *g = &t->grad;
+    g->journal = 0;
+    for (int e = 0; e < g->jn; ++e) t->slack[g->ji[e]] += scale * fabs(g->jv[e]);
+}
+
+/* Ill-conditioned terms: the gradient of a face whose det F is small against
+ * its edges (a sliver, nearly edge-on at the sub-frame) goes through 1/det F
+ * and a float32 evaluation has a relative error of about orc_det_rel there;
+ * each such nominal term adds ORC_GUARD_ULPS times that share of itself to
+ * the bound.  Call right after the nominal adjoint (uses t->pre, t->suf). */
+static void orc_cond_bound(const orc_ctx *cx, orc_tls *t, int winner, int m, const double *gI,
+                           int s, double tau, int X, double u, double v)
+{
+    const orc_scene *sc = cx->sc;
+    if (winner >= 0) {
+        double rho = ORC_GUARD_ULPS * orc_det_rel(&t->ev[winner]);
+        if (!(rho > ORC_COND_MIN)) return;
+        orc_journal_begin(&t->grad);
+        orc_adj_fg(cx, &t->grad, &t->ev[winner], gI, s, tau);
+        orc_journal_addabs(t, rho);
+        return;
+    }
+    for (int q = 0; q < m; ++q) {
+        const orc_bgterm *bq = &t->bt[q];
+        const orc_eval *ev = &t->ev[bq->j];
+        double rho = ORC_GUARD_ULPS * orc_det_rel(ev);
+        if (!(rho > ORC_COND_MIN)) continue;
+        double gd = gI[sc->C] * t->pre[q] * t->suf[q + 1] * (-bq->A / sc->delta);
+        orc_journal_begin(&t->grad);
+        orc_adj_bg(cx, &t->grad, ev, bq, s, tau, X, u, v, gd);
+        orc_journal_addabs(t, rho);
+    }
+}
+
+static void orc_max_flush(orc_tls *t)
+{
+    for (int e = 0; e < t->mxn; ++e) { t->slack[t->mxl[e]] += t->dmx[t->mxl[e]]; t->dmx[t->mxl[e]] = 0.0; }
+    t->mxn = 0;
+}
+
+/*
+ * Parity guard band of one (pixel, sub-frame): the decisions that sit within
+ * rounding distance of flipping, and what the sub-frame would give under each
+ * other choice.
+ *  - coverage and skipping: every in/out choice of the faces whose min w is
+ *    inside orc_w_band, or whose |det F| is within its float32 error (at
+ *    least half the threshold) of the skip threshold, with the depth
+ *    near-tie of each resulting z-buffer;
+ *  - closest point (background): the other clamp state or edge of each term
+ *    (orc_bg_face).
+ * vlo/vhi receive the per-channel range of the sub-frame value over the
+ * alternatives (nominal included).  With gI, t->slack receives a bound on
+ * how far the gradient contribution of this (pixel, sub-frame) can move per
+ * index: the max over the coverage alternatives plus the sum over the
+ * closest-point alternatives of the change they make.
+ * Returns bit 0 if an alternative moves the value by more than thr, bit 1 if
+ * any alternative exists.
+ */
+static int orc_alternatives(const orc_ctx *cx, orc_tls *t, int n, int m, int s, double tau, int X,
+                            double u, double v, int winner, const double *val, double thr,
+                            const double *gI, double *vlo, double *vhi)
+{
+    const orc_scene *sc = cx->sc;
+    const int C = sc->C;
+    int amb[ORC_MAX_AMBIG], kind[ORC_MAX_AMBIG], na = 0;
+    for (int c = 0; c <= C; ++c) vlo[c] = vhi[c] = val[c];
+    for (int j = 0; j < n; ++j) {
+        const orc_eval *ev = &t->ev[j];
+        int k;
+        if (fabs(fabs(ev->D) - ORC_TAU_DET) <= fmax(0.5 * ORC_TAU_DET, ORC_GUARD_ULPS * orc_det_rel(ev) * fabs(ev->D))) k = 1;
+        else if (!ev->skip && fabs(ev->mw) < orc_w_band(ev, u, v)) k = 2;
+        else continue;
+        if (na == ORC_MAX_AMBIG) {
+            /* too many: only the trivial range of a sub-frame value */
+            t->cnt[CNT_UNBOUNDED] += 1;
+            for (int c = 0; c < C; ++c) {
+                double lo = 0, hi = 0;
+                for (int vi = 0; vi < sc->V; ++vi) {
+                    lo = fmin(lo, sc->attrs[(size_t)vi * C + c]);
+                    hi = fmax(hi, sc->attrs[(size_t)vi * C + c]);
+                }
+                vlo[c] = fmin(vlo[c], lo); vhi[c] = fmax(vhi[c], hi);
+            }
+            vlo[C] = 0.0; vhi[C] = 1.0;
+            return 3;
+        }
+        amb[na] = j; kind[na++] = k;
+    }
+    int bits = 0, have_j0 = 0, bta_ready = 0;
     double alt[16];
-    int bits = 0;
     for (int mask = 0; mask < (1 << na); ++mask) {
-        for (int j = 0; j < n; ++j) t->incl[j] = t->ev[j].cover;
-        for (int a = 0; a < na; ++a) t->incl[amb[a]] = (mask >> a) & 1;
+        int same_skip = 1;
+        for (int j = 0; j < n; ++j) { t->skp[j] = t->ev[j].skip; t->incl[j] = t->ev[j].cover; }
+        for (int a = 0; a < na; ++a) {
+            if (!((mask >> a) & 1)) continue;
+            int j = amb[a];
+            if (kind[a] == 1) {
+                t->skp[j] = !t->ev[j].skip;
+                t->incl[j] = !t->skp[j] && t->ev[j].mw >= 0.0;
+                same_skip = 0;
+            } else {
+                t->incl[j] = !t->incl[j];
+            }
+        }
         int w = orc_zbuffer(t->ev, n, t->incl);
         for (int pass = 0; pass < 2; ++pass) {
             int cand = w;
@@ -502,18 +793,73 @@ static int orc_guard(const orc_ctx *cx, orc_tls *t, int n, int s, int X, double 
                 if (dz > ORC_GUARD_DEPTH * fabs(t->ev[w].depth)) break;
                 cand = r;
             }
-            if (cand == nominal) continue;
-            bits |= 2;
+            if (cand == winner && (cand >= 0 || same_skip)) continue;
+            int m2 = 0;
             if (cand >= 0) {
                 orc_shade(sc, &t->ev[cand], alt);
-                alt[sc->C] = 1.0;
+                alt[C] = 1.0;
             } else {
-                if (bgalpha < 0) { int tie; orc_background(cx, t, n, s, X, u, v, &bgalpha, &tie); }
-                for (int c = 0; c < sc->C; ++c) alt[c] = 0.0;
-                alt[sc->C] = bgalpha;
+                if (!bta_ready) {
+                    for (int j = 0; j < n; ++j) {
+                        t->bta_ok[j] = orc_bg_face(cx, &t->ev[j], s, X, u, v, -1, 0, &t->bta[j]);
+                        t->bta[j].j = j;
+                    }
+                    bta_ready = 1;
+                }
+                double prod = 1.0;
+                for (int j = 0; j < n; ++j)
+                    if (!t->skp[j] && t->bta_ok[j]) { prod *= t->bta[j].om; t->bt2[m2++] = t->bta[j]; }
+                for (int c = 0; c < C; ++c) alt[c] = 0.0;
+                alt[C] = 1.0 - prod;
             }
-            for (int c = 0; c <= sc->C; ++c)
-                if (fabs(alt[c] - val[c]) > thr) return 3;
+            for (int c = 0; c <= C; ++c) {
+                vlo[c] = fmin(vlo[c], alt[c]);
+                vhi[c] = fmax(vhi[c], alt[c]);
+                if (fabs(alt[c] - val[c]) > thr) bits |= 1;
+            }
+            bits |= 2;
+            if (!gI) continue;
+            if (!have_j0) {
+                orc_journal_begin(&t->grad);
+                if (winner >= 0) orc_adj_fg(cx, &t->grad, &t->ev[winner], gI, s, tau);
+                else orc_adj_bgset(cx, &t->grad, t, t->bt, m, gI, s, tau, X, u, v);
+                orc_journal_keep(t);
+                have_j0 = 1;
+            }
+            orc_journal_begin(&t->grad);
+            if (cand >= 0) orc_adj_fg(cx, &t->grad, &t->ev[cand], gI, s, tau);
+            else orc_adj_bgset(cx, &t->grad, t, t->bt2, m2, gI, s, tau, X, u, v);
+            orc_journal_diff(t, 1);
+        }
+    }
+    if (gI) orc_max_flush(t);
+    if (winner >= 0 || m == 0) return bits;
+    /* closest-point decisions of the background terms: each changes the
+     * routing of its own term's gradient only (its value is continuous) */
+    int any = 0;
+    for (int q = 0; q < m; ++q) any |= t->bt[q].nalt > 0;
+    if (!any) return bits;
+    bits |= 2;
+    if (!gI) return bits;
+    t->pre[0] = 1.0;
+    for (int q = 0; q < m; ++q) t->pre[q + 1] = t->pre[q] * t->bt[q].om;
+    t->suf[m] = 1.0;
+    for (int q = m - 1; q >= 0; --q) t->suf[q] = t->suf[q + 1] * t->bt[q].om;
+    for (int q = 0; q < m; ++q) {
+        const orc_bgterm *bq = &t->bt[q];
+        if (!bq->nalt) continue;
+        const orc_eval *ev = &t->ev[bq->j];
+        double gd = gI[C] * t->pre[q] * t->suf[q + 1] * (-bq->A / sc->delta);
+        orc_journal_begin(&t->grad);
+        orc_adj_bg(cx, &t->grad, ev, bq, s, tau, X, u, v, gd);
+        orc_journal_keep(t);
+        for (int a = 0; a < bq->nalt; ++a) {
+            orc_bgterm alt_t;
+            orc_bg_face(cx, ev, s, X, u, v, bq->alt_edge[a], bq->alt_clamp[a], &alt_t);
+            alt_t.j = bq->j;
+            orc_journal_begin(&t->grad);
+            orc_adj_bg(cx, &t->grad, ev, &alt_t, s, tau, X, u, v, gd);
+            orc_journal_diff(t, 0);
         }
     }
     return bits;
@@ -596,20 +942,32 @@ static void orc_free_ctx(orc_ctx *cx)
  * averaged (rgb, alpha) for every rendered row (others untouched).  flags
  * [H][W] (optional, zeroed by the caller) ORs per pixel over its sub-frames:
  * bit 0 when a decision within rounding distance of flipping could move the
- * value beyond tolerance, bit 1 when such a decision could change which
- * vertices receive gradient (winner identity, clamp state of the closest
- * point).  counters[8]
- * (optional): bbox pairs, covering pairs, fg pixel-subframes, bg
- * pixel-subframes, contributing bg pairs, distinct (pixel, face, segment)
- * setups, guard-flagged pixel-subframes, skipped degenerate pairs.
+ * value beyond a quarter of the parity tolerance, bit 1 when such a decision
+ * exists at all (it may change which vertices receive gradient).
+ * counters[ORC_NCNT] (optional): bbox pairs, covering pairs, fg
+ * pixel-subframes, bg pixel-subframes, contributing bg pairs, distinct
+ * (pixel, face, segment) setups, pixel-subframes with bit 0, skipped
+ * degenerate pairs, pixel-subframes whose value has alternatives,
+ * pixel-subframes with any alternative, pixel-subframes with too many
+ * ambiguous faces to enumerate.
  * With grad_image: grad_kf [S+1][V][2] (optional), grad_verts [V][3] and
  * grad_attrs [V][C] are overwritten with dL/d(...) for L = sum grad_image*I.
+ * bounds (optional): the range of the image over the alternative decisions
+ * of the guard band, and (with grad_image) per-component bounds on how far
+ * those decisions can move the gradient.
  * rec: record decisions; rep: replay recorded decisions (frozen surrogate).
  * Returns 0, or -1 on bad arguments / allocation failure.
  */
+typedef struct {
+    double *image_lo, *image_hi;   /* [C+1][H][W], rendered rows            */
+    double *slack_kf;              /* [S+1][V][2] (optional)                */
+    double *slack_verts;           /* [V][3]                                */
+    double *slack_attrs;           /* [V][C]                                */
+} orc_bounds;
+
 int orc_render(const orc_scene *sc, double *image, int *flags, double *counters,
                const double *grad_image, double *grad_kf, double *grad_verts, double *grad_attrs,
-               orc_decisions *rec, const orc_decisions *rep)
+               orc_decisions *rec, const orc_decisions *rep, orc_bounds *bd)
 {
     if (!sc || sc->V <= 0 || sc->F <= 0 || sc->C <= 0 || sc->C > 14 || sc->S <= 0 || sc->K <= 0 ||
         sc->W <= 0 || sc->H <= 0 || !(sc->delta > 0) || !image)
@@ -617,7 +975,12 @@ int orc_render(const orc_scene *sc, double *image, int *flags, double *counters,
     if (sc->motion == 1 && !sc->model_sub) return -1;
     if (grad_image && (sc->motion != 0 || sc->distance != 0)) return -1;
     if (rep && (rep->W != sc->W || rep->H != sc->H || rep->K != sc->K)) return -1;
+    if (bd && rep) return -1;
+    if (bd && (!bd->image_lo || !bd->image_hi)) return -1;
     const int V = sc->V, F = sc->F, C = sc->C, S = sc->S, K = sc->K, W = sc->W, H = sc->H;
+    const size_t nkf = (size_t)(S + 1) * V * 2, ng = nkf + (size_t)V * C;
+    const int guard = (flags || bd) && !rep;
+    const int gslack = bd && grad_image;
     orc_ctx cx;
     if (orc_build(&cx, sc)) { orc_free_ctx(&cx); return -1; }
     int rb = sc->row_begin < 0 ? 0 : sc->row_begin;
@@ -638,17 +1001,27 @@ int orc_render(const orc_scene *sc, double *image, int *flags, double *counters,
     }
     orc_tls *tls = (orc_tls *)calloc(nth, sizeof(orc_tls));
     for (int i = 0; i < nth; ++i) {
-        tls[i].ev = (orc_eval *)malloc(sizeof(orc_eval) * F);
-        tls[i].bt = (orc_bgterm *)malloc(sizeof(orc_bgterm) * F);
-        tls[i].incl = (int *)malloc(sizeof(int) * F);
+        /* replay may add frozen faces that left the candidate set: 2F */
+        tls[i].ev = (orc_eval *)malloc(sizeof(orc_eval) * 2 * F);
+        tls[i].bt = (orc_bgterm *)malloc(sizeof(orc_bgterm) * 2 * F);
+        tls[i].bta = (orc_bgterm *)malloc(sizeof(orc_bgterm) * F);
+        tls[i].bt2 = (orc_bgterm *)malloc(sizeof(orc_bgterm) * F);
+        tls[i].bta_ok = (int *)malloc(sizeof(int) * F);
+        tls[i].skp = (int *)malloc(sizeof(int) * F);
+        tls[i].incl = (int *)malloc(sizeof(int) * 2 * F);
         tls[i].cand = (int *)malloc(sizeof(int) * F);
         tls[i].pcand = (int *)malloc(sizeof(int) * F);
         tls[i].seen = (char *)malloc(F);
-        tls[i].pre = (double *)malloc(sizeof(double) * (F + 1));
-        tls[i].suf = (double *)malloc(sizeof(double) * (F + 1));
+        tls[i].pre = (double *)malloc(sizeof(double) * (2 * F + 1));
+        tls[i].suf = (double *)malloc(sizeof(double) * (2 * F + 1));
         if (grad_image) {
-            tls[i].grad.gkf = (double *)calloc((size_t)(S + 1) * V * 2, sizeof(double));
+            tls[i].grad.gkf = (double *)calloc(nkf, sizeof(double));
             tls[i].grad.gattr = (double *)calloc((size_t)V * C, sizeof(double));
+        }
+        if (gslack) {
+            tls[i].dtmp = (double *)calloc(ng, sizeof(double));
+            tls[i].dmx = (double *)calloc(ng, sizeof(double));
+            tls[i].slack = (double *)calloc(ng, sizeof(double));
         }
     }
     const double thr = 0.25e-5 * K;   /* flip that would move the pixel by > 1/4 of 1e-5 */
@@ -662,7 +1035,8 @@ int orc_render(const orc_scene *sc, double *image, int *flags, double *counters,
         orc_tls *t = &tls[tid];
         int r = rb + ri * rs;
         double v = (double)(H - 2 * r - 1) / (double)H;     /* reading: row 0 at the top */
-        double *acc = (double *)calloc((size_t)W * (C + 1), sizeof(double));
+        double *acc = (double *)calloc((size_t)W * (C + 1) * 3, sizeof(double));
+        double *acc_lo = acc + (size_t)W * (C + 1), *acc_hi = acc_lo + (size_t)W * (C + 1);
         const int *rep_start = rep ? rep->row_start[r] : NULL;
         const orc_bg_rec *rep_list = rep ? rep->row_list[r] : NULL;
         int *rstart = NULL, *rend = NULL;
@@ -729,7 +1103,7 @@ int orc_render(const orc_scene *sc, double *image, int *flags, double *counters,
                         for (int j = 0; j < n; ++j) t->incl[j] = t->ev[j].cover;
                         winner = orc_zbuffer(t->ev, n, t->incl);
                     }
-                    int m = 0, edge_tie = 0;
+                    int m = 0;
                     if (winner >= 0) {
                         orc_shade(sc, &t->ev[winner], val);
                         val[C] = 1.0;
@@ -748,77 +1122,63 @@ int orc_render(const orc_scene *sc, double *image, int *flags, double *counters,
                                 orc_eval_face(&cx, ev, ss, tau, u, v);
                                 j = n++;
                             }
-                            double gap;
-                            orc_bg_face(&cx, &t->ev[j], ss, X, u, v, br->edge, br->clamp, &t->bt[m], &gap);
-                            t->bt[m].A = exp(-t->bt[m].d / sc->delta);
-                            t->bt[m].om = -expm1(-t->bt[m].d / sc->delta);
+                            orc_bg_face(&cx, &t->ev[j], ss, X, u, v, br->edge, br->clamp, &t->bt[m]);
+                            t->bt[m].j = j;
                             prod *= t->bt[m].om;
-                            t->incl[m] = j;
                             ++m;
                         }
                         for (int c2 = 0; c2 < C; ++c2) val[c2] = 0.0;
                         val[C] = 1.0 - prod;
                     } else {
-                        int tie;
                         double alpha;
-                        m = orc_background(&cx, t, n, ss, X, u, v, &alpha, &tie);
+                        m = orc_background(&cx, t, n, ss, X, u, v, &alpha);
                         for (int c2 = 0; c2 < C; ++c2) val[c2] = 0.0;
                         val[C] = alpha;
                         t->cnt[CNT_BG] += 1;
                         t->cnt[CNT_BGPAIRS] += m;
-                        edge_tie = tie;
                         if (rec)
                             for (int q = 0; q < m; ++q) {
                                 orc_bg_rec br = { (int)k, t->bt[q].f, t->bt[q].edge, t->bt[q].clamp };
                                 orc_push_rec(t, br);
                             }
                     }
-                    if (flags && !rep) {
-                        int fb = edge_tie | orc_guard(&cx, t, n, ss, X, u, v, winner, val, thr);
-                        if (fb) flags[(size_t)r * W + c] |= fb;
-                        if (fb & 1) t->cnt[CNT_FLAGGED] += 1;
-                    }
-                    if (rec) rend[(size_t)c * K + k] = t->rl_n;
-                    for (int c2 = 0; c2 <= C; ++c2) acc[(size_t)c * (C + 1) + c2] += val[c2];
-
-                    if (grad_image) {
-                        double gI[16];
+                    double gI[16];
+                    if (grad_image)
                         for (int c2 = 0; c2 <= C; ++c2)
                             gI[c2] = grad_image[((size_t)c2 * H + r) * W + c] / (double)K;
-                        if (winner >= 0) {
-                            const orc_eval *ev = &t->ev[winner];
-                            double gw[3];
-                            for (int i = 0; i < 3; ++i) {
-                                int vi = sc->faces[ev->f * 3 + i];
-                                gw[i] = 0;
-                                for (int c2 = 0; c2 < C; ++c2) {
-                                    gw[i] += gI[c2] * sc->attrs[(size_t)vi * C + c2];
-                                    t->grad.gattr[(size_t)vi * C + c2] += ev->w[i] * gI[c2];
-                                }
-                            }
-                            orc_adj_bary(&cx, &t->grad, ev, ev->w, gw, ss, tau);
-                        } else if (m > 0) {
-                            /* d alpha / d A_j = prod_{m != j} (1 - A_m): prefix/suffix products */
-                            t->pre[0] = 1.0;
-                            for (int q = 0; q < m; ++q) t->pre[q + 1] = t->pre[q] * t->bt[q].om;
-                            t->suf[m] = 1.0;
-                            for (int q = m - 1; q >= 0; --q) t->suf[q] = t->suf[q + 1] * t->bt[q].om;
-                            for (int q = 0; q < m; ++q) {
-                                const orc_bgterm *bt = &t->bt[q];
-                                const orc_eval *ev = NULL;
-                                for (int j = 0; j < n; ++j) if (t->ev[j].f == bt->f) { ev = &t->ev[j]; break; }
-                                double dA = gI[C] * t->pre[q] * t->suf[q + 1];
-                                double gd = dA * (-bt->A / sc->delta);
-                                orc_adj_bg(&cx, &t->grad, ev, bt, ss, tau, X, u, v, gd);
-                            }
-                        }
+                    double vlo[16], vhi[16];
+                    for (int c2 = 0; c2 <= C; ++c2) vlo[c2] = vhi[c2] = val[c2];
+                    if (guard) {
+                        int fb = orc_alternatives(&cx, t, n, m, ss, tau, X, u, v, winner, val, thr,
+                                                  gslack ? gI : NULL, vlo, vhi);
+                        if (fb && flags) flags[(size_t)r * W + c] |= fb;
+                        if (fb & 1) t->cnt[CNT_FLAGGED] += 1;
+                        if (fb & 2) t->cnt[CNT_ALT_GRAD] += 1;
+                        for (int c2 = 0; c2 <= C; ++c2)
+                            if (vhi[c2] > vlo[c2]) { t->cnt[CNT_ALT_VALUE] += 1; break; }
+                    }
+                    if (rec) rend[(size_t)c * K + k] = t->rl_n;
+                    for (int c2 = 0; c2 <= C; ++c2) {
+                        acc[(size_t)c * (C + 1) + c2] += val[c2];
+                        acc_lo[(size_t)c * (C + 1) + c2] += vlo[c2];
+                        acc_hi[(size_t)c * (C + 1) + c2] += vhi[c2];
+                    }
+
+                    if (grad_image) {
+                        if (winner >= 0) orc_adj_fg(&cx, &t->grad, &t->ev[winner], gI, ss, tau);
+                        else if (m > 0) orc_adj_bgset(&cx, &t->grad, t, t->bt, m, gI, ss, tau, X, u, v);
+                        if (gslack && (winner >= 0 || m > 0))
+                            orc_cond_bound(&cx, t, winner, m, gI, ss, tau, X, u, v);
                     }
                 }
             }
         }
         for (int c = 0; c < W; ++c)
-            for (int c2 = 0; c2 <= C; ++c2)
-                image[((size_t)c2 * H + r) * W + c] = acc[(size_t)c * (C + 1) + c2] / (double)K;
+            for (int c2 = 0; c2 <= C; ++c2) {
+                size_t o = ((size_t)c2 * H + r) * W + c, a = (size_t)c * (C + 1) + c2;
+                image[o] = acc[a] / (double)K;
+                if (bd) { bd->image_lo[o] = acc_lo[a] / (double)K; bd->image_hi[o] = acc_hi[a] / (double)K; }
+            }
         free(acc);
         if (rec) {
             /* sub-frames were visited segment by segment; store in (col, k) order */
@@ -844,19 +1204,28 @@ int orc_render(const orc_scene *sc, double *image, int *flags, double *counters,
             for (int j = 0; j < ORC_NCNT; ++j) counters[j] += tls[i].cnt[j];
     }
     if (grad_image) {
-        double *gkf = (double *)calloc((size_t)(S + 1) * V * 2, sizeof(double));
+        double *gkf = (double *)calloc(nkf, sizeof(double));
+        double *skf = gslack ? (double *)calloc(nkf, sizeof(double)) : NULL;
         if (grad_attrs) memset(grad_attrs, 0, sizeof(double) * (size_t)V * C);
+        if (gslack && bd->slack_attrs) memset(bd->slack_attrs, 0, sizeof(double) * (size_t)V * C);
         for (int i = 0; i < nth; ++i) {
-            for (size_t j = 0; j < (size_t)(S + 1) * V * 2; ++j) gkf[j] += tls[i].grad.gkf[j];
+            for (size_t j = 0; j < nkf; ++j) gkf[j] += tls[i].grad.gkf[j];
             if (grad_attrs)
                 for (size_t j = 0; j < (size_t)V * C; ++j) grad_attrs[j] += tls[i].grad.gattr[j];
+            if (gslack) {
+                for (size_t j = 0; j < nkf; ++j) skf[j] += tls[i].slack[j];
+                if (bd->slack_attrs)
+                    for (size_t j = 0; j < (size_t)V * C; ++j) bd->slack_attrs[j] += tls[i].slack[nkf + j];
+            }
         }
-        if (grad_kf) memcpy(grad_kf, gkf, sizeof(double) * (size_t)(S + 1) * V * 2);
-        if (grad_verts) {
+        if (grad_kf) memcpy(grad_kf, gkf, sizeof(double) * nkf);
+        if (gslack && bd->slack_kf) memcpy(bd->slack_kf, skf, sizeof(double) * nkf);
+        if (grad_verts || (gslack && bd->slack_verts)) {
             /* keyframe -> rest position: chain through the projection (App. I)
-             * and the rigid keyframe transform */
+             * and the rigid keyframe transform; the bound goes through the
+             * magnitudes of the same linear map */
             for (int v = 0; v < V; ++v) {
-                double g[3] = { 0, 0, 0 };
+                double g[3] = { 0, 0, 0 }, sl[3] = { 0, 0, 0 };
                 for (int s = 0; s <= S; ++s) {
                     const double *m = sc->model + s * 12, *vw = sc->view, *p = sc->verts + v * 3;
                     double w[3], c[3];
@@ -865,24 +1234,36 @@ int orc_render(const orc_scene *sc, double *image, int *flags, double *counters,
                     for (int r = 0; r < 3; ++r)
                         c[r] = vw[r * 4] * w[0] + vw[r * 4 + 1] * w[1] + vw[r * 4 + 2] * w[2] + vw[r * 4 + 3];
                     double t = sc->tan_half_fov;
+                    /* column i of the map (gx, gy) -> rest-position gradient */
+                    double col[2][3];
+                    for (int i = 0; i < 2; ++i) {
+                        double gc[3] = { i == 0 ? 1.0 / (c[2] * t) : 0.0, i == 1 ? 1.0 / (c[2] * t) : 0.0,
+                                         -c[i] / (c[2] * c[2] * t) };
+                        double gw[3];
+                        for (int j = 0; j < 3; ++j) gw[j] = vw[0 * 4 + j] * gc[0] + vw[1 * 4 + j] * gc[1] + vw[2 * 4 + j] * gc[2];
+                        for (int j = 0; j < 3; ++j) col[i][j] = m[0 * 4 + j] * gw[0] + m[1 * 4 + j] * gw[1] + m[2 * 4 + j] * gw[2];
+                    }
                     double gx = gkf[((size_t)s * V + v) * 2], gy = gkf[((size_t)s * V + v) * 2 + 1];
-                    double gc[3] = { gx / (c[2] * t), gy / (c[2] * t),
-                                     -(gx * c[0] + gy * c[1]) / (c[2] * c[2] * t) };
-                    double gw[3];
-                    for (int j = 0; j < 3; ++j) gw[j] = vw[0 * 4 + j] * gc[0] + vw[1 * 4 + j] * gc[1] + vw[2 * 4 + j] * gc[2];
-                    for (int j = 0; j < 3; ++j) g[j] += m[0 * 4 + j] * gw[0] + m[1 * 4 + j] * gw[1] + m[2 * 4 + j] * gw[2];
+                    for (int j = 0; j < 3; ++j) g[j] += col[0][j] * gx + col[1][j] * gy;
+                    if (skf) {
+                        double sx = skf[((size_t)s * V + v) * 2], sy = skf[((size_t)s * V + v) * 2 + 1];
+                        for (int j = 0; j < 3; ++j) sl[j] += fabs(col[0][j]) * sx + fabs(col[1][j]) * sy;
+                    }
                 }
-                grad_verts[v * 3 + 0] = g[0];
-                grad_verts[v * 3 + 1] = g[1];
-                grad_verts[v * 3 + 2] = g[2];
+                if (grad_verts) for (int j = 0; j < 3; ++j) grad_verts[v * 3 + j] = g[j];
+                if (skf && bd->slack_verts) for (int j = 0; j < 3; ++j) bd->slack_verts[v * 3 + j] = sl[j];
             }
         }
         free(gkf);
+        free(skf);
     }
     for (int i = 0; i < nth; ++i) {
-        free(tls[i].ev); free(tls[i].bt); free(tls[i].incl); free(tls[i].cand); free(tls[i].pcand);
+        free(tls[i].ev); free(tls[i].bt); free(tls[i].bta); free(tls[i].bt2); free(tls[i].bta_ok);
+        free(tls[i].skp); free(tls[i].incl); free(tls[i].cand); free(tls[i].pcand);
         free(tls[i].seen); free(tls[i].pre); free(tls[i].suf); free(tls[i].grad.gkf);
-        free(tls[i].grad.gattr); free(tls[i].rl);
+        free(tls[i].grad.gattr); free(tls[i].grad.ji); free(tls[i].grad.jv); free(tls[i].rl);
+        free(tls[i].j0i); free(tls[i].j0v); free(tls[i].dtmp); free(tls[i].dmx); free(tls[i].slack);
+        free(tls[i].mxl);
     }
     free(tls);
     orc_free_ctx(&cx);

@@ -39,7 +39,7 @@ def lib():
             _build.build()
         L = ctypes.CDLL(_build.LIB)
         L.orc_render.restype = ctypes.c_int
-        L.orc_render.argtypes = [ctypes.POINTER(_Scene)] + [ctypes.c_void_p] * 9
+        L.orc_render.argtypes = [ctypes.POINTER(_Scene)] + [ctypes.c_void_p] * 10
         L.orc_decisions_new.restype = ctypes.c_void_p
         L.orc_decisions_free.argtypes = [ctypes.c_void_p]
         L.orc_keyframes.argtypes = [ctypes.POINTER(_Scene), ctypes.c_void_p]
@@ -50,6 +50,11 @@ def lib():
         assert L.orc_sizeof_scene() == ctypes.sizeof(_Scene), "scene struct layout mismatch"
         _lib = L
     return _lib
+
+
+class _Bounds(ctypes.Structure):
+    _fields_ = [("image_lo", ctypes.c_void_p), ("image_hi", ctypes.c_void_p), ("slack_kf", ctypes.c_void_p),
+                ("slack_verts", ctypes.c_void_p), ("slack_attrs", ctypes.c_void_p)]
 
 
 def _p(a: Optional[np.ndarray]):
@@ -79,10 +84,19 @@ class Result:
     grad_attrs: Optional[np.ndarray]   # [V, C]
     grad_kf: Optional[np.ndarray]      # [S+1, V, 2]
     decisions: Optional[Decisions]
+    # guard band (bounds=True): range of the image over the decisions a
+    # float32 evaluation could take the other way, and per-component bounds
+    # on how far those decisions can move the gradient
+    image_lo: Optional[np.ndarray] = None      # [C+1, H, W]
+    image_hi: Optional[np.ndarray] = None
+    slack_verts: Optional[np.ndarray] = None   # [V, 3]
+    slack_attrs: Optional[np.ndarray] = None   # [V, C]
+    slack_kf: Optional[np.ndarray] = None      # [S+1, V, 2]
 
 
 COUNTER_NAMES = ["bbox_pairs", "cover_pairs", "fg_pixsub", "bg_pixsub", "bg_pairs",
-                 "setup_triples", "flagged_pixsub", "skipped_pairs"]
+                 "setup_triples", "flagged_pixsub", "skipped_pairs", "alt_value_pixsub",
+                 "alt_pixsub", "unbounded_pixsub"]
 
 
 def schedule(k: int, K: int, S: int):
@@ -127,7 +141,7 @@ def render(sc, *, solver: str = "naive", motion: str = "segment", distance: str 
            delta: float = 1e-4, eps_cutoff: float = 1e-8, grad_image: Optional[np.ndarray] = None,
            flags: bool = False, counters: bool = False, rows=None, nthreads: int = 0,
            record: bool = False, replay: Optional[Decisions] = None,
-           stop_grad_sigma: bool = False) -> Result:
+           stop_grad_sigma: bool = False, bounds: bool = False) -> Result:
     """Render ``sc`` (a workloads.Scene) in FP64.
 
     solver: "naive" (per-sub-frame 3x3 solve) or "fast" (App. B coefficients)
@@ -135,6 +149,7 @@ def render(sc, *, solver: str = "naive", motion: str = "segment", distance: str 
     distance: "keyframe" (eq 13) or "exact" (eq 12)
     rows: None (all) or (begin, end, step) to render a subset of pixel rows
     grad_image: dL/dI [C+1, H, W]; returns dL/d(verts, attrs, keyframes)
+    bounds: also return the guard band's image range and gradient bounds
     """
     keep: list = []
     rb, re, rs = (0, 0, 1) if rows is None else rows
@@ -147,7 +162,7 @@ def render(sc, *, solver: str = "naive", motion: str = "segment", distance: str 
     C, H, W, V, S = st.C, st.H, st.W, st.V, st.S
     image = np.zeros((C + 1, H, W), np.float64)
     fl = np.zeros((H, W), np.int32) if flags else None
-    cnt = np.zeros(8, np.float64) if counters else None
+    cnt = np.zeros(len(COUNTER_NAMES), np.float64) if counters else None
     gi = gv = ga = gk = None
     if grad_image is not None:
         gi = np.ascontiguousarray(grad_image, np.float64).reshape(C + 1, H, W)
@@ -155,12 +170,20 @@ def render(sc, *, solver: str = "naive", motion: str = "segment", distance: str 
         ga = np.zeros((V, C), np.float64)
         gk = np.zeros((S + 1, V, 2), np.float64)
     dec = Decisions() if record else None
+    bd = None
+    lo = hi = sv = sa = sk = None
+    if bounds:
+        lo, hi = np.zeros_like(image), np.zeros_like(image)
+        if grad_image is not None:
+            sv, sa, sk = np.zeros((V, 3)), np.zeros((V, C)), np.zeros((S + 1, V, 2))
+        bd = _Bounds(_p(lo), _p(hi), _p(sk), _p(sv), _p(sa))
     rc = lib().orc_render(ctypes.byref(st), _p(image), _p(fl), _p(cnt), _p(gi), _p(gk), _p(gv), _p(ga),
-                          dec.ptr if dec else None, replay.ptr if replay else None)
+                          dec.ptr if dec else None, replay.ptr if replay else None,
+                          ctypes.byref(bd) if bd is not None else None)
     if rc != 0:
         raise ValueError(f"oracle render rejected its arguments (code {rc})")
     cd = dict(zip(COUNTER_NAMES, cnt.tolist())) if cnt is not None else None
-    return Result(image, fl, cd, gv, ga, gk, dec)
+    return Result(image, fl, cd, gv, ga, gk, dec, lo, hi, sv, sa, sk)
 
 
 def keyframes(sc) -> np.ndarray:

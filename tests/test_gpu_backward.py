@@ -1,10 +1,12 @@
 """Gradient parity of the HIP adjoint (through the C ABI) with the FP64
 oracle's adjoint and with central finite differences of the oracle's
 frozen-decision surrogate.  Bar: relative L2 error <= 1e-3, separately for
-vertex positions and attributes.  Pixels the oracle flags (either bit: a
-decision within rounding distance of flipping that moves the value, or that
-changes which vertices receive gradient, e.g. the closest point's edge
-parameter at a clamp bound) get zero upstream gradient."""
+vertex positions and attributes, with an upstream gradient on every pixel.
+Where a (pixel, sub-frame) has a decision within float32 rounding distance
+of flipping (winner identity, coverage, the closest point's edge or clamp
+state), the oracle bounds per component how far the other choice moves the
+gradient, and the residual is shrunk by that bound before its norm is taken;
+the raw residual is printed beside it."""
 import numpy as np
 import pytest
 
@@ -12,22 +14,21 @@ import oracle
 from paper_2602_07860_amd import render as R
 from paper_2602_07860_amd import workloads as wl
 
-from gpu_common import GRAD_RTOL, gpu_backward, gpu_forward, rel_l2, say
+from gpu_common import (GRAD_RTOL, assert_band_small, assert_grad_parity, gpu_backward, gpu_forward,
+                        reference, rel_l2, say)
 
 pytestmark = pytest.mark.gpu
 
 
 def _grad_case(sc, solver="fast", chunk_len=4, seed=0):
-    ref = oracle.render(sc, flags=True)
-    G = np.random.default_rng(seed).normal(size=ref.image.shape)
-    G[:, ref.flags != 0] = 0.0
-    og = oracle.render(sc, grad_image=G)
+    G = np.random.default_rng(seed).normal(size=(sc.attrs.shape[1] + 1, sc.height, sc.width))
+    og = reference(sc, G)
+    assert_band_small(og, sc.name)
     img, state, st = gpu_forward(sc, solver=solver, chunk_len=chunk_len)
     gv, ga = gpu_backward(st, state, G)
-    ev, ea = rel_l2(gv, og.grad_verts), rel_l2(ga, og.grad_attrs)
-    say(f"[{sc.name}/{solver}/T{chunk_len}] grad rel-L2 verts {ev:.2e} attrs {ea:.2e}")
-    assert np.all(np.isfinite(gv)) and np.all(np.isfinite(ga))
-    assert ev <= GRAD_RTOL and ea <= GRAD_RTOL, (ev, ea)
+    lab = f"{sc.name}/{solver}/T{chunk_len}"
+    assert_grad_parity(gv, og.grad_verts, og.slack_verts, label=lab + " verts")
+    assert_grad_parity(ga, og.grad_attrs, og.slack_attrs, label=lab + " attrs")
 
 
 @pytest.mark.parametrize("solver", ["fast", "recompute"])
@@ -59,14 +60,18 @@ def test_medium_gradient_vs_frozen_fd_64_vertices():
     # eps/4) of the oracle's frozen-decision surrogate along a random direction
     # per vertex, for 64 vertices drawn with seed 102 among those the loss
     # depends on.  The perturbed vertices go to the FP64 oracle unrounded.
+    # Six pixel rows across the sphere (its projection spans rows 40-216), the
+    # first one through its motion-blurred top silhouette, all with an
+    # upstream gradient on every pixel.
     sc = wl.make_workload(wl.MEDIUM)
-    rows = (0, sc.height, 128)
+    rows = (40, 216, 32)
     say(f"case: FD {sc.name} rows {rows}")
-    base = oracle.render(sc, rows=rows, flags=True, record=True)
+    base = oracle.render(sc, rows=rows, record=True)
     G = np.zeros_like(base.image)
-    G[:, rows[0]:rows[1]:rows[2]] = np.random.default_rng(7).normal(size=G[:, ::rows[2]].shape)
-    G[:, base.flags != 0] = 0.0
-    og = oracle.render(sc, rows=rows, grad_image=G)
+    G[:, rows[0]:rows[1]:rows[2]] = np.random.default_rng(7).normal(size=G[:, rows[0]:rows[1]:rows[2]].shape)
+    live_rows = [r for r in range(*rows) if np.abs(base.image[:, r]).sum() > 0]
+    assert len(live_rows) >= 4, live_rows
+    og = reference(sc, G, rows=rows)
     img, state, st = gpu_forward(sc)
     gv, _ = gpu_backward(st, state, G)
     live = np.where(np.abs(og.grad_verts).sum(1) > 0)[0]
@@ -79,7 +84,7 @@ def test_medium_gradient_vs_frozen_fd_64_vertices():
         r = oracle.render(sc.with_(verts=v), rows=rows, replay=base.decisions)
         return float(np.sum(G * r.image))
 
-    fds, gpus, adj = [], [], []
+    fds, gpus, adj, slk = [], [], [], []
     eps = 1e-3
     for vi in picks:
         d = rng.normal(size=3)
@@ -89,11 +94,12 @@ def test_medium_gradient_vs_frozen_fd_64_vertices():
         fds.append((16 * R1[1] - R1[0]) / 15)
         gpus.append(float(gv[vi] @ d))
         adj.append(float(og.grad_verts[vi] @ d))
-    fds, gpus, adj = np.array(fds), np.array(gpus), np.array(adj)
-    e, e_or = rel_l2(gpus, fds), rel_l2(adj, fds)
-    say(f"FD rel-L2 over {len(picks)} vertices: GPU {e:.2e}, oracle adjoint {e_or:.2e}")
+        slk.append(float(og.slack_verts[vi] @ np.abs(d)))
+    fds, gpus, adj, slk = np.array(fds), np.array(gpus), np.array(adj), np.array(slk)
+    e_or = rel_l2(adj, fds)
+    say(f"FD over {len(picks)} vertices on live rows {live_rows}: oracle adjoint vs FD {e_or:.2e}")
     assert e_or <= 1e-4      # the FD itself is accurate
-    assert e <= GRAD_RTOL
+    assert_grad_parity(gpus, fds, slk, label="GPU vs FD")
 
 
 def test_autograd_function_matches_adjoint():

@@ -1,19 +1,19 @@
 """Forward parity of the HIP path (through the C ABI) with the FP64 oracle.
 
-Bar: per channel, |I_gpu - I_oracle| <= 1e-5 * max|I_oracle| on every pixel
-the oracle does not flag as within rounding distance of a decision flip
-(guard band); flagged pixels are counted and printed."""
+Bar: per channel and on every pixel, I_gpu within 1e-5 * max|I_oracle| of
+the oracle's value, or of the range the oracle gives for the pixel where one
+of its sub-frames has a decision within float32 rounding distance of
+flipping (guard band)."""
 import ctypes
 
 import numpy as np
 import pytest
 
-import oracle
 from paper_2602_07860_amd import binding as B
 from paper_2602_07860_amd import render as R
 from paper_2602_07860_amd import workloads as wl
 
-from gpu_common import assert_image_parity, gpu_forward, image_errors, say
+from gpu_common import assert_band_small, assert_image_parity, gpu_forward, reference, say
 
 pytestmark = pytest.mark.gpu
 
@@ -22,9 +22,10 @@ pytestmark = pytest.mark.gpu
 def test_small_translation_parity(solver):
     sc = wl.make_workload(wl.SMALL)
     say(f"case: {sc.name} solver={solver}")
-    ref = oracle.render(sc, flags=True)
+    ref = reference(sc)
+    assert_band_small(ref, sc.name)
     img, _, _ = gpu_forward(sc, solver=solver)
-    assert_image_parity(img, ref.image, ref.flags, label=f"small/{solver}")
+    assert_image_parity(img, ref, label=f"small/{solver}")
 
 
 @pytest.mark.parametrize("chunk_len,slice_len", [(1, 1), (2, 3), (8, 1), (8, 2), (4, 5), (4, 64)])
@@ -32,9 +33,9 @@ def test_chunking_does_not_change_the_image(chunk_len, slice_len):
     sc = wl.make_workload(wl.SMALL, motion=wl.Motion("rotate", axis=(0.3, 1.0, -0.2), revs=1.0),
                           num_segments=12, num_subframes=37)
     say(f"case: small rotate chunk_len={chunk_len} slice_len={slice_len}")
-    ref = oracle.render(sc, flags=True)
+    ref = reference(sc)
     img, _, _ = gpu_forward(sc, chunk_len=chunk_len, slice_len=slice_len)
-    assert_image_parity(img, ref.image, ref.flags, label=f"chunk{chunk_len}x{slice_len}")
+    assert_image_parity(img, ref, label=f"chunk{chunk_len}x{slice_len}")
 
 
 @pytest.mark.parametrize("W,H,K,S", [(61, 37, 23, 5), (13, 70, 1, 1), (40, 40, 2, 1), (33, 31, 4, 7)])
@@ -45,23 +46,24 @@ def test_ragged_sizes_and_degenerate_schedules(W, H, K, S):
                                                      trans=(0.5, 0.2, 0.0)),
                           num_segments=S, num_subframes=K, width=W, height=H)
     say(f"case: ragged W={W} H={H} K={K} S={S}")
-    ref = oracle.render(sc, flags=True)
+    ref = reference(sc)
     for solver in ("fast", "recompute"):
         img, _, _ = gpu_forward(sc, solver=solver, chunk_len=2)
-        assert_image_parity(img, ref.image, ref.flags, label=f"ragged{W}x{H}K{K}S{S}/{solver}")
+        assert_image_parity(img, ref, label=f"ragged{W}x{H}K{K}S{S}/{solver}")
 
 
 def test_medium_workload_full_image():
     sc = wl.make_workload(wl.MEDIUM)
     say(f"case: {sc.name} full image vs oracle")
-    ref = oracle.render(sc, flags=True)
+    ref = reference(sc)
+    assert_band_small(ref, sc.name)
     fast, _, _ = gpu_forward(sc, solver="fast")
     rec, _, _ = gpu_forward(sc, solver="recompute")
-    assert_image_parity(fast, ref.image, ref.flags, label="medium/fast")
-    assert_image_parity(rec, ref.image, ref.flags, label="medium/recompute")
+    assert_image_parity(fast, ref, label="medium/fast")
+    assert_image_parity(rec, ref, label="medium/recompute")
     # the two solvers compute the same barycentrics (away from decisions
     # within rounding distance of flipping)
-    ok = (ref.flags & 1) == 0
+    ok = np.all(ref.image_hi == ref.image_lo, axis=0)
     assert np.abs(fast - rec)[:, ok].max() <= 5e-6
 
 
@@ -85,9 +87,9 @@ def test_overflow_is_reported_and_retried():
     assert torch.isnan(img).all()
     # the front end grows the capacity and renders correctly
     R._capacity.clear()
-    ref = oracle.render(sc, flags=True)
+    ref = reference(sc)
     good, _, _ = gpu_forward(sc)
-    assert_image_parity(good, ref.image, ref.flags, label="after-retry")
+    assert_image_parity(good, ref, label="after-retry")
 
 
 def test_device_checks_raise():
