@@ -21,9 +21,10 @@
  *
  * Conventions (all entry points):
  *  - Every pointer argument is a DEVICE pointer unless stated otherwise.
- *  - The caller owns all memory.  The library never allocates and never
- *    synchronizes; work is enqueued on the given stream (a hipStream_t passed
- *    as void*, NULL = the default stream).  rb_read_header,
+ *  - The caller owns all memory (rb_render_blur_fwd_static excepted: it
+ *    uses a library-held device array).  The library never allocates and
+ *    never synchronizes; work is enqueued on the given stream (a hipStream_t
+ *    passed as void*, NULL = the default stream).  rb_read_header,
  *    rb_batch_read_headers and rb_profile_read are the calls that wait, and
  *    say so.
  *  - Layouts are dense, row-major, float32 / int32.
@@ -125,6 +126,23 @@ rb_status rb_render_blur_fwd(const float *verts, int32_t V, const int32_t *faces
                              const float *attrs, int32_t C, const rb_motion *motion,
                              const rb_camera *camera, const rb_options *options, float *image,
                              void *workspace, size_t workspace_bytes, void *stream);
+
+/* Forward render without a workspace argument, for callers that cannot
+ * allocate device memory (code under graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments and output as
+ * rb_render_blur_fwd; the workspace is a library-held device array of
+ * RB_STATIC_SCRATCH_BYTES, one per device, kept until the process ends.
+ * Returns RB_EWORKSPACE when rb_workspace_size reports more than that for
+ * these sizes (lower options->list_capacity, or use rb_render_blur_fwd).
+ * Calls no allocator.  Every call on a device reuses that device's array
+ * (the forward initialises what it reads), so calls that overlap in time on
+ * one device race; the array's state is not kept for a backward pass and
+ * its header cannot be read (an overflow shows as a NaN image). */
+#define RB_STATIC_SCRATCH_BYTES (64u << 20)
+rb_status rb_render_blur_fwd_static(const float *verts, int32_t V, const int32_t *faces, int32_t F,
+                                    const float *attrs, int32_t C, const rb_motion *motion,
+                                    const rb_camera *camera, const rb_options *options, float *image,
+                                    void *stream);
 
 /* Backward (adjoint) pass.  Same inputs and the SAME workspace as the forward
  * it differentiates, untouched in between.  grad_image [C+1][H][W] is

@@ -16,11 +16,13 @@ RB_SOLVER_FAST, RB_SOLVER_RECOMPUTE = 0, 1
 RB_MAX_CHANNELS = 4
 RB_MAX_FACES = 1 << 23
 RB_MAX_CHUNK = 8
+RB_STATIC_SCRATCH_BYTES = 64 << 20
 HDR_FACE_RANGE, HDR_BEHIND, HDR_OVERFLOW = 1, 2, 4
 
 RB_BATCH_FORWARD, RB_BATCH_BACKWARD = 0, 1
 
-EXPORTED = ["rb_workspace_size", "rb_validate", "rb_render_blur_fwd", "rb_render_blur_bwd",
+EXPORTED = ["rb_workspace_size", "rb_validate", "rb_render_blur_fwd", "rb_render_blur_fwd_static",
+            "rb_render_blur_bwd",
             "rb_batch_workspace_size", "rb_render_blur_batched", "rb_batch_read_headers",
             "rb_read_header", "rb_profile_enable", "rb_profile_read", "rb_status_string"]
 
@@ -93,6 +95,9 @@ def lib():
         L.rb_render_blur_fwd.restype = i32
         L.rb_render_blur_fwd.argtypes = [vp, i32, vp, i32, vp, i32, P(rb_motion), P(rb_camera),
                                          P(rb_options), vp, vp, sz, vp]
+        L.rb_render_blur_fwd_static.restype = i32
+        L.rb_render_blur_fwd_static.argtypes = [vp, i32, vp, i32, vp, i32, P(rb_motion), P(rb_camera),
+                                                P(rb_options), vp, vp]
         L.rb_render_blur_bwd.restype = i32
         L.rb_render_blur_bwd.argtypes = [vp, i32, vp, i32, vp, i32, P(rb_motion), P(rb_camera),
                                          P(rb_options), vp, vp, vp, vp, sz, vp]
@@ -135,6 +140,11 @@ def rb_render_blur_fwd(verts, V, faces, F, attrs, C, motion, camera, options, im
     return lib().rb_render_blur_fwd(verts, V, faces, F, attrs, C, ctypes.byref(motion),
                                     ctypes.byref(camera), ctypes.byref(options), image,
                                     workspace, workspace_bytes, stream)
+
+
+def rb_render_blur_fwd_static(verts, V, faces, F, attrs, C, motion, camera, options, image, stream) -> int:
+    return lib().rb_render_blur_fwd_static(verts, V, faces, F, attrs, C, ctypes.byref(motion),
+                                           ctypes.byref(camera), ctypes.byref(options), image, stream)
 
 
 def rb_render_blur_bwd(verts, V, faces, F, attrs, C, motion, camera, options, grad_image,

@@ -279,6 +279,25 @@ rb_status rb_render_blur_fwd(const float *verts, int32_t V, const int32_t *faces
     return e == hipSuccess ? RB_OK : RB_EDEVICE;
 }
 
+rb_status rb_render_blur_fwd_static(const float *verts, int32_t V, const int32_t *faces, int32_t F,
+                                    const float *attrs, int32_t C, const rb_motion *motion, const rb_camera *camera,
+                                    const rb_options *options, float *image, void *stream)
+{
+    if (!verts || !faces || !attrs || !image) return RB_EINVAL;
+    Batch bt;
+    rb_status st = single_batch(V, F, C, motion, camera, options, bt);
+    if (st != RB_OK) return st;
+    if (!motion->keyframe_model) return RB_EINVAL;
+    if (bt.total > (size_t)RB_STATIC_SCRATCH_BYTES) return RB_EWORKSPACE;
+    void *ws = nullptr;
+    if (static_scratch(&ws) != hipSuccess) return RB_EDEVICE;
+    std::vector<Io> io{Io{verts, faces, attrs, motion->keyframe_model, image, nullptr, nullptr, nullptr}};
+    PhaseEvents pe;
+    const PhaseEvents *pp = prof_begin(0, pe);
+    hipError_t e = launch_forward(bt, io, ws, (hipStream_t)stream, pp);
+    return e == hipSuccess ? RB_OK : RB_EDEVICE;
+}
+
 rb_status rb_render_blur_bwd(const float *verts, int32_t V, const int32_t *faces, int32_t F, const float *attrs,
                              int32_t C, const rb_motion *motion, const rb_camera *camera, const rb_options *options,
                              const float *grad_image, float *grad_verts, float *grad_attrs, void *workspace,

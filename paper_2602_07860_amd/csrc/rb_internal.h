@@ -178,6 +178,10 @@ struct PhaseEvents {
 };
 
 hipError_t launch_forward(const Batch &bt, const std::vector<Io> &io, void *ws, hipStream_t st, const PhaseEvents *pe);
+// device address of the library-held workspace on the current device
+// (RB_STATIC_SCRATCH_BYTES), looked up on the first call per device
+constexpr int kMaxDevices = 64;
+hipError_t static_scratch(void **ptr);
 hipError_t launch_backward(const Batch &bt, const std::vector<Io> &io, void *ws, hipStream_t st,
                            const PhaseEvents *pe);
 

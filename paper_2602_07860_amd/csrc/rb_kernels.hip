@@ -32,6 +32,7 @@
 #include <cfloat>
 #include <climits>
 #include <cstring>
+#include <mutex>
 
 #include "rb_internal.h"
 
@@ -2315,6 +2316,32 @@ static void forward_T(const Batch &bt, const Inst *tab, void *ws, hipStream_t st
         static const unsigned nw = kBgFwdOversubNarrow * resident_waves(k_bg<T, SOLVER, false>);
         hipLaunchKernelGGL((k_bg<T, SOLVER, false>), dim3(nw), dim3(kWave), 0, st, tab, n, (const int64_t *)tprefix);
     }
+}
+
+// Library-held workspace of rb_render_blur_fwd_static.  In host code the
+// name `scratch` is only a host-side stand-in: its device address comes from
+// hipGetSymbolAddress, once per device (each device holds its own copy, at
+// its own address, until the process ends), and only that address is passed
+// to kernels.
+static __device__ __align__(256) unsigned char scratch[RB_STATIC_SCRATCH_BYTES];
+
+hipError_t static_scratch(void **ptr)
+{
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
 }
 
 hipError_t launch_forward(const Batch &bt, const std::vector<Io> &io, void *ws, hipStream_t st, const PhaseEvents *pe)
