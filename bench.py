@@ -20,6 +20,10 @@ Workloads (synthetic, seeded; see paper_2602_07860_amd/workloads.py):
     K in [32, 256], half translation / half rotation, all in one launch
     sequence captured in a graph and replayed; chunk and slice lengths from
     the autotuner.
+  sweep: the speed comparison of Sec. 4.2 on stand-in models (50 nu=17
+    spheres, 5780 faces, 128x128, translation) for K in 10..200: the fast
+    solver against the static-frames baseline (K still renders averaged);
+    reports both per K and the per-sub-frame slopes.
 One step = forward render + dL/dI + adjoint into vertex positions and colours.
 Inputs are resident in GPU memory before the timed region.  The step is timed
 for the fast solver (eq 8) and for the per-sub-frame recompute (eqs 1-3) on
@@ -44,6 +48,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "pixel-subframes/sec fwd+bwd, fast solver vs per-subframe recompute"
+SWEEP_KS = (10, 20, 50, 100, 200)
 KERNEL_NAMES = {"fg": "k_fg", "bg": "k_bg", "fg_bwd": "k_fg_bwd", "bg_bwd": "k_bg_bwd"}
 PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (packed); 78.6 without packing
 PEAK_HBM_GBS = 8000.0
@@ -195,6 +200,65 @@ def run_batch(scenes, targets_sc, args, torch, B, R):
     return res
 
 
+def run_sweep(args, torch, B, R):
+    """Paper-shaped speed sweep (stand-in for Sec. 4.2): the 50 sweep models at
+    128^2 under linear translation, fwd + dL/dI + bwd of an L2 loss against a
+    grey image, for K in SWEEP_KS: the fast solver (one render with K
+    sub-frames) against the static-frames baseline (K still renders of the
+    exactly moved mesh in one batched launch sequence, averaged).  Returns
+    per K the mean ms per model of each."""
+    from paper_2602_07860_amd import baseline
+    from paper_2602_07860_amd import workloads as wl
+    dev = "cuda:0"
+    models = wl.make_sweep(n=args.sweep_models)
+    out = {"K": [], "fast_ms": [], "static_frames_ms": []}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for K in SWEEP_KS:
+        t_fast = t_base = 0.0
+        for sc in models:
+            sc = sc.with_(num_subframes=K)
+            st = R.scene_tensors(sc, dev)
+            o = R.RenderOptions(K, check=True)
+
+            def fast():
+                img, state = R.render_forward(st.verts, st.faces, st.attrs, st.model, st.camera, o)
+                R.render_backward(st.verts, st.faces, st.attrs, st.model, state, 2.0 * (img - 0.5))
+
+            b = baseline.for_scene(st, sc.motion, K)
+            b.fit()
+
+            def base():
+                img = b.forward()
+                b.backward(2.0 * (img - 0.5))
+
+            for fn in (fast, base):
+                fn()
+            o.check = False
+            torch.cuda.synchronize()
+            for fn, which in ((fast, 0), (base, 1)):
+                e0.record()
+                for _ in range(args.sweep_reps):
+                    fn()
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / args.sweep_reps
+                if which == 0:
+                    t_fast += ms
+                else:
+                    t_base += ms
+            del b
+        out["K"].append(K)
+        out["fast_ms"].append(round(t_fast / len(models), 4))
+        out["static_frames_ms"].append(round(t_base / len(models), 4))
+        log(f"sweep K={K}: fast {t_fast / len(models):.3f} ms, static frames {t_base / len(models):.3f} ms per model")
+    ks = np.array(out["K"], np.float64)
+    for key in ("fast_ms", "static_frames_ms"):
+        out[key.replace("_ms", "_ms_per_subframe")] = round(float(np.polyfit(ks, np.array(out[key]), 1)[0]), 6)
+    out["speedup"] = [round(b / f, 3) for f, b in zip(out["fast_ms"], out["static_frames_ms"])]
+    out["models"] = len(models)
+    return out
+
+
 def cpu_oracle(scenes, rows_step, nth, label):
     """FP64 oracle fwd+bwd on every rows_step-th pixel row of each scene:
     time, pixel-sub-frames covered and pair counters scaled to all rows."""
@@ -223,7 +287,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=("medium", "large", "batch"), default="large")
+    ap.add_argument("--workload", choices=("medium", "large", "batch", "sweep"), default="large")
+    ap.add_argument("--sweep-models", type=int, default=50)
+    ap.add_argument("--sweep-reps", type=int, default=3)
     ap.add_argument("--chunk-len", type=int, default=4)
     ap.add_argument("--slice-len", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -244,6 +310,20 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "sweep":
+        sw = run_sweep(args, torch, B, R)
+        units = sum(128 * 128 * k for k in sw["K"]) * sw["models"]
+        tot_ms = sum(sw["fast_ms"]) * sw["models"]
+        out = {"metric": METRIC, "value": round(units / (tot_ms * 1e-3), 1), "unit": "pixel-subframes/s",
+               "n_gpus": 1, "steps": args.sweep_reps, "warmup": 1,
+               "ms_per_step": round(tot_ms / (len(sw["K"]) * sw["models"]), 4), "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+               "config": {"workload": f"speed sweep: {sw['models']} nu=17 spheres (5780 faces), 128x128, "
+                                      f"translation, K in {list(sw['K'])}, fwd+bwd L2; fast solver vs "
+                                      f"static-frames baseline"},
+               "sweep": sw, "paper_context": "up to 4.57x vs SoftRas rendering K frames (RTX 4090, Sec. 4.2)"}
+        print(json.dumps(out), flush=True)
+        return
     if args.workload == "batch":
         scenes = wl.make_batch(seed=3, n=32)
         targets = [wl.make_target(sc, 1003 + i) for i, sc in enumerate(scenes)]

@@ -326,6 +326,38 @@ def make_batch(seed: int = 3, n: int = 32) -> List[Scene]:
     return out
 
 
+SWEEP_EYE_DIST = 2.232       # App. I camera distance
+SWEEP_FOV_DEG = 60.0         # App. I half field of view 30 degrees
+
+
+def make_sweep(seed: int = 50, n: int = 50, num_subframes: int = 50) -> List[Scene]:
+    """Stand-in for the speed comparison's models (Sec. 4.2: 50 models of
+    5536 faces on average, 128x128 front view, linear translation): n
+    geodesic spheres nu = 17 (5780 faces) with r = 1 + 0.02 N(0,1) and U[0,1]
+    colours, scaled so that the largest vertex norm is 1 and rotated about
+    the x axis by an angle from U[-90, 90] degrees (App. I object
+    initialisation), moving as x(t) = x0 + (0.5 - t) (App. I translation),
+    seen from distance 2.232 with a 30-degree half field of view; K
+    sub-frames, one linear segment."""
+    view, tanf = _camera(SWEEP_EYE_DIST, SWEEP_FOV_DEG)
+    rng = np.random.default_rng(seed)
+    out = []
+    for b in range(n):
+        v, f, c, _ = displaced_sphere(17, int(rng.integers(0, 2 ** 31 - 1)), sigma=0.02)
+        v = v.astype(np.float64) / np.linalg.norm(v, axis=1).max()
+        a = math.radians(rng.uniform(-90.0, 90.0))
+        rx = np.array([[1, 0, 0], [0, math.cos(a), -math.sin(a)], [0, math.sin(a), math.cos(a)]])
+        v = (v @ rx.T).astype(np.float32)
+        out.append(Scene(v, f, c, Motion("translate", trans=(-1.0, 0.0, 0.0)), 1, view, tanf, 128, 128,
+                         num_subframes, f"sweep-model{b}"))
+    return out
+
+
+def subframe_times(K: int) -> np.ndarray:
+    """t_k = k/(K-1) (Sec. 3.2); a single sub-frame sits at t = 0."""
+    return np.zeros(1) if K == 1 else np.arange(K, dtype=np.float64) / (K - 1)
+
+
 # ------------------------------------------------------- small test scenes
 
 

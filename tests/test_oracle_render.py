@@ -276,3 +276,30 @@ def test_guard_band_flags_edge_on_pixel_centres():
     sc2 = wl.square_scene(center_px=(0.0, 0.25), half_px=3.3, shift_px=0.0, width=W, height=H, k=1)
     r2 = oracle.render(sc2, flags=True)
     assert (r2.flags & 1).sum() == 0
+
+
+def test_exact_mode_is_the_mean_of_still_frames():
+    # the oracle's exact-motion, exact-distance mode (project M(t_k) P0 per
+    # sub-frame, closest point in the sub-frame's own triangle, eq 12) equals
+    # the mean of K separate still renders, each a single keyframe at
+    # M(t_k) where the keyframe closest point (eq 13) is the exact one
+    class Still:
+        def __init__(self, m):
+            self.m = np.asarray(m, np.float64)
+
+        def matrix(self, t):
+            return self.m
+
+        def keyframes(self, num_segments):
+            return np.stack([self.m] * (num_segments + 1))
+
+    sc = wl.make_workload(wl.SMALL, motion=wl.Motion("rotate", axis=(0.3, 1.0, -0.2), revs=0.6,
+                                                     trans=(0.3, 0.0, 0.0)),
+                          num_segments=4, num_subframes=7, width=40, height=36)
+    ex = oracle.render(sc, motion="exact", distance="exact").image
+    acc = np.zeros_like(ex)
+    for t in wl.subframe_times(sc.num_subframes):
+        acc += oracle.render(sc.with_(motion=Still(sc.motion.matrix(t)), num_segments=1, num_subframes=1)).image
+    # (the still frames take their transform rounded to float32, the exact
+    # mode in double: positions differ by ~1e-7 relative)
+    np.testing.assert_allclose(acc / sc.num_subframes, ex, rtol=0, atol=2e-6)
