@@ -76,6 +76,19 @@ class BatchRenderer:
         self.ws_bytes = B.rb_batch_workspace_size(self.inst, self.o)
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.images[0].device)
 
+    def set_cameras(self, cameras: Sequence[B.rb_camera]) -> None:
+        """Give the instances new cameras of the same image sizes (host
+        records only; the workspace is kept unless the plan needs more)."""
+        for st, cam in zip(self.scenes, cameras):
+            if (cam.width, cam.height) != (st.camera.width, st.camera.height):
+                raise ValueError("set_cameras keeps every instance's image size")
+            st.camera = cam
+        self.inst = self._instances()
+        need = B.rb_batch_workspace_size(self.inst, self.o)
+        if need > self.ws_bytes:
+            self.ws_bytes = need
+            self.workspace = torch.empty(need, dtype=torch.uint8, device=self.images[0].device)
+
     def forward(self) -> List[torch.Tensor]:
         st = B.rb_render_blur_batched(self.inst, self.o, B.RB_BATCH_FORWARD, self.workspace.data_ptr(),
                                       self.ws_bytes, _stream_ptr(self.workspace.device))

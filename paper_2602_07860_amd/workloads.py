@@ -353,6 +353,73 @@ def make_sweep(seed: int = 50, n: int = 50, num_subframes: int = 50) -> List[Sce
     return out
 
 
+def uv_sphere(rings: int = 30, segments: int = 45, radius: float = 1.0):
+    """Closed latitude-longitude sphere: two poles plus `rings` rings of
+    `segments` vertices; 30 x 45 gives 1352 vertices and 2700 faces, the size
+    of the paper's deformation template (App. J).  Faces wind outward."""
+    v = [(0.0, 0.0, radius)]
+    for i in range(1, rings + 1):
+        th = math.pi * i / (rings + 1)
+        for j in range(segments):
+            ph = 2.0 * math.pi * j / segments
+            v.append((radius * math.sin(th) * math.cos(ph), radius * math.sin(th) * math.sin(ph),
+                      radius * math.cos(th)))
+    v.append((0.0, 0.0, -radius))
+    south = len(v) - 1
+    ring = lambda i, j: 1 + (i - 1) * segments + (j % segments)
+    f = []
+    for j in range(segments):
+        f.append((0, ring(1, j), ring(1, j + 1)))
+        f.append((south, ring(rings, j + 1), ring(rings, j)))
+    for i in range(1, rings):
+        for j in range(segments):
+            a, b, c, d = ring(i, j), ring(i, j + 1), ring(i + 1, j), ring(i + 1, j + 1)
+            f.append((a, c, d))
+            f.append((a, d, b))
+    return np.asarray(v, np.float32), np.asarray(f, np.int32)
+
+
+MULTIVIEW_ELEVATIONS = (-60.0, -30.0, 0.0, 30.0, 60.0)                      # App. I
+MULTIVIEW_AZIMUTHS = (-315.0, -270.0, -225.0, -180.0, -135.0, -90.0, -45.0, 0.0)
+
+
+def multiview_cameras(dist: float = SWEEP_EYE_DIST):
+    """The 40 viewpoints of the translational recovery (App. I): eye at
+    d (cos phi cos theta, cos phi sin theta, sin phi) for the 5 elevations phi
+    and 8 azimuths theta, looking at the origin.  Reading: the elevation is
+    measured towards +z, so +z is the up direction of every view."""
+    out = []
+    for ph in MULTIVIEW_ELEVATIONS:
+        for th in MULTIVIEW_AZIMUTHS:
+            a, b = math.radians(ph), math.radians(th)
+            eye = (dist * math.cos(a) * math.cos(b), dist * math.cos(a) * math.sin(b), dist * math.sin(a))
+            out.append(look_at_view(eye, up=(0.0, 0.0, 1.0)).astype(np.float32))
+    return out
+
+
+def make_multiview(seed: int = 60, num_subframes: int = 64, res: int = 128):
+    """Translational recovery set-up (Sec. 5.1, App. I-J): the target is a
+    multi-octave displaced nu=17 sphere with U[0,1] colours (stand-in for a
+    ShapeNet object), scaled to largest vertex norm 1 and rotated about x by
+    U[-90, 90] degrees, moving as x(t) = x0 + (0.5 - t), seen from the 40
+    viewpoints at res x res with K sub-frames; the template is the 1352-vertex
+    sphere of radius 0.6 with grey colours.  Returns (target Scene, template
+    Scene, list of 40 view matrices); the Scenes carry the first view."""
+    view0, tanf = _camera(SWEEP_EYE_DIST, SWEEP_FOV_DEG)
+    v, f, c, rng = displaced_sphere(17, seed, octaves=True)
+    v = v.astype(np.float64) / np.linalg.norm(v, axis=1).max()
+    a = math.radians(rng.uniform(-90.0, 90.0))
+    rx = np.array([[1, 0, 0], [0, math.cos(a), -math.sin(a)], [0, math.sin(a), math.cos(a)]])
+    v = (v @ rx.T).astype(np.float32)
+    views = multiview_cameras()
+    mo = Motion("translate", trans=(-1.0, 0.0, 0.0))
+    target = Scene(v, f, c, mo, 1, views[0], tanf, res, res, num_subframes, "multiview-target")
+    tv, tf = uv_sphere(radius=0.6)
+    template = Scene(tv, tf, np.full((len(tv), 3), 0.5, np.float32), mo, 1, views[0], tanf, res, res,
+                     num_subframes, "multiview-template")
+    return target, template, views
+
+
 def subframe_times(K: int) -> np.ndarray:
     """t_k = k/(K-1) (Sec. 3.2); a single sub-frame sits at t = 0."""
     return np.zeros(1) if K == 1 else np.arange(K, dtype=np.float64) / (K - 1)
