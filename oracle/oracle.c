@@ -46,9 +46,10 @@
 #define ORC_GUARD_ULPS 8.0     /* guard widths: this many times the float32 error estimate */
 #define ORC_COND_MIN 1e-4      /* terms whose float32 relative error may exceed this get a bound */
 #define ORC_MAX_AMBIG 8
+#define ORC_ADJ_WMIN 1e-8      /* weight bound of the live-pair counter */
 
 enum { CNT_BBOX, CNT_COV, CNT_FG, CNT_BG, CNT_BGPAIRS, CNT_SETUP, CNT_FLAGGED, CNT_SKIP,
-       CNT_ALT_VALUE, CNT_ALT_GRAD, CNT_UNBOUNDED, ORC_NCNT };
+       CNT_ALT_VALUE, CNT_ALT_GRAD, CNT_UNBOUNDED, CNT_BGLIVE, ORC_NCNT };
 
 typedef struct {
     int V, F, C, S, K, W, H;
@@ -65,6 +66,10 @@ typedef struct {
     int motion;              /* 0 segment-linear keyframes, 1 exact projection per sub-frame */
     int distance;            /* 0 keyframe closest point (eq 13), 1 closest point in F(tau) (eq 12) */
     int stop_grad_sigma;     /* variant: no gradient through the closest-point weights */
+    double adj_wmin;         /* > 0: the adjoint leaves out background terms of weight
+                                prod_{m != j}(1 - A_m) A_j below this, and whole (pixel,
+                                sub-frame)s whose bound prod / min(min (1 - A), 1/2) on the
+                                weights is; 0: exact */
     int nthreads;
     int row_begin, row_end, row_step;
 } orc_scene;
@@ -610,17 +615,33 @@ static void orc_adj_fg(const orc_ctx *cx, orc_grad *g, const orc_eval *ev, const
     orc_adj_bary(cx, g, ev, ev->w, gw, s, tau);
 }
 
+/* Bound on the derivative weights prod_{m != j}(1 - A_m) A_j of a
+ * background (pixel, sub-frame): 0 with two or more zero factors, infinite
+ * with one, else prod_m (1 - A_m) / min(min_m (1 - A_m), 1/2). */
+static double orc_weight_bound(const orc_bgterm *bt, int m)
+{
+    double P = 1.0, lo = 0.5;
+    int nz = 0;
+    for (int q = 0; q < m; ++q) {
+        if (bt[q].om > 0) { P *= bt[q].om; lo = fmin(lo, bt[q].om); }
+        else ++nz;
+    }
+    return nz >= 2 ? 0.0 : (nz == 1 ? INFINITY : P / lo);
+}
+
 /* Adjoint of alpha = 1 - prod_j (1 - A_j) over the terms bt[0..m):
  * d alpha / d A_j = prod_{m != j} (1 - A_m) by prefix/suffix products. */
 static void orc_adj_bgset(const orc_ctx *cx, orc_grad *g, orc_tls *t, const orc_bgterm *bt, int m,
                           const double *gI, int s, double tau, int X, double u, double v)
 {
     const orc_scene *sc = cx->sc;
+    if (sc->adj_wmin > 0 && orc_weight_bound(bt, m) < sc->adj_wmin) return;
     t->pre[0] = 1.0;
     for (int q = 0; q < m; ++q) t->pre[q + 1] = t->pre[q] * bt[q].om;
     t->suf[m] = 1.0;
     for (int q = m - 1; q >= 0; --q) t->suf[q] = t->suf[q + 1] * bt[q].om;
     for (int q = 0; q < m; ++q) {
+        if (sc->adj_wmin > 0 && t->pre[q] * t->suf[q + 1] * bt[q].A < sc->adj_wmin) continue;
         double dA = gI[sc->C] * t->pre[q] * t->suf[q + 1];
         orc_adj_bg(cx, g, &t->ev[bt[q].j], &bt[q], s, tau, X, u, v, dA * (-bt[q].A / sc->delta));
     }
@@ -949,7 +970,8 @@ static void orc_free_ctx(orc_ctx *cx)
  * (pixel, face, segment) setups, pixel-subframes with bit 0, skipped
  * degenerate pairs, pixel-subframes whose value has alternatives,
  * pixel-subframes with any alternative, pixel-subframes with too many
- * ambiguous faces to enumerate.
+ * ambiguous faces to enumerate, contributing bg pairs of (pixel,
+ * sub-frame)s whose derivative weight bound is at least ORC_ADJ_WMIN.
  * With grad_image: grad_kf [S+1][V][2] (optional), grad_verts [V][3] and
  * grad_attrs [V][C] are overwritten with dL/d(...) for L = sum grad_image*I.
  * bounds (optional): the range of the image over the alternative decisions
@@ -1136,6 +1158,7 @@ int orc_render(const orc_scene *sc, double *image, int *flags, double *counters,
                         val[C] = alpha;
                         t->cnt[CNT_BG] += 1;
                         t->cnt[CNT_BGPAIRS] += m;
+                        if (!(orc_weight_bound(t->bt, m) < ORC_ADJ_WMIN)) t->cnt[CNT_BGLIVE] += m;
                         if (rec)
                             for (int q = 0; q < m; ++q) {
                                 orc_bg_rec br = { (int)k, t->bt[q].f, t->bt[q].edge, t->bt[q].clamp };

@@ -27,7 +27,7 @@ class _Scene(ctypes.Structure):
         ("model", ctypes.c_void_p), ("model_sub", ctypes.c_void_p), ("view", ctypes.c_void_p),
         ("tan_half_fov", ctypes.c_double), ("delta", ctypes.c_double), ("eps_cutoff", ctypes.c_double),
         ("solver", ctypes.c_int), ("motion", ctypes.c_int), ("distance", ctypes.c_int),
-        ("stop_grad_sigma", ctypes.c_int), ("nthreads", ctypes.c_int),
+        ("stop_grad_sigma", ctypes.c_int), ("adj_wmin", ctypes.c_double), ("nthreads", ctypes.c_int),
         ("row_begin", ctypes.c_int), ("row_end", ctypes.c_int), ("row_step", ctypes.c_int),
     ]
 
@@ -96,7 +96,7 @@ class Result:
 
 COUNTER_NAMES = ["bbox_pairs", "cover_pairs", "fg_pixsub", "bg_pixsub", "bg_pairs",
                  "setup_triples", "flagged_pixsub", "skipped_pairs", "alt_value_pixsub",
-                 "alt_pixsub", "unbounded_pixsub"]
+                 "alt_pixsub", "unbounded_pixsub", "bg_pairs_live"]
 
 
 def schedule(k: int, K: int, S: int):
@@ -141,7 +141,7 @@ def render(sc, *, solver: str = "naive", motion: str = "segment", distance: str 
            delta: float = 1e-4, eps_cutoff: float = 1e-8, grad_image: Optional[np.ndarray] = None,
            flags: bool = False, counters: bool = False, rows=None, nthreads: int = 0,
            record: bool = False, replay: Optional[Decisions] = None,
-           stop_grad_sigma: bool = False, bounds: bool = False) -> Result:
+           stop_grad_sigma: bool = False, bounds: bool = False, adj_wmin: float = 0.0) -> Result:
     """Render ``sc`` (a workloads.Scene) in FP64.
 
     solver: "naive" (per-sub-frame 3x3 solve) or "fast" (App. B coefficients)
@@ -150,6 +150,9 @@ def render(sc, *, solver: str = "naive", motion: str = "segment", distance: str 
     rows: None (all) or (begin, end, step) to render a subset of pixel rows
     grad_image: dL/dI [C+1, H, W]; returns dL/d(verts, attrs, keyframes)
     bounds: also return the guard band's image range and gradient bounds
+    adj_wmin: leave out of the adjoint the background terms whose derivative
+        weight prod_{m != j}(1 - A_m) A_j is below this, and the (pixel,
+        sub-frame)s whose bound on those weights is (0: exact adjoint)
     """
     keep: list = []
     rb, re, rs = (0, 0, 1) if rows is None else rows
@@ -157,7 +160,7 @@ def render(sc, *, solver: str = "naive", motion: str = "segment", distance: str 
                        motion={"segment": 0, "exact": 1}[motion],
                        distance={"keyframe": 0, "exact": 1}[distance],
                        delta=float(np.float32(delta)), eps_cutoff=float(eps_cutoff),
-                       stop_grad_sigma=int(stop_grad_sigma), nthreads=int(nthreads),
+                       stop_grad_sigma=int(stop_grad_sigma), adj_wmin=float(adj_wmin), nthreads=int(nthreads),
                        row_begin=rb, row_end=re, row_step=rs)
     C, H, W, V, S = st.C, st.H, st.W, st.V, st.S
     image = np.zeros((C + 1, H, W), np.float64)

@@ -86,7 +86,7 @@ static rb_status make_plan(int32_t V, int32_t F, int32_t C, const rb_motion *mot
     // (per-task steps weigh more there); single tasks on wide halos
     p.bwd_merge = wide_halo ? 1 : 2;
     p.wide = wide_halo;
-    p.NS = std::max(C, 2);
+    p.NS = std::max(C, 3);
     p.nfb = (F + 255) / 256;
     p.cap = opt->list_capacity > 0 ? opt->list_capacity
                                    : std::max<int64_t>(1 << 20, (int64_t)64 * F * std::min(p.NC, 64));

@@ -14,6 +14,11 @@ namespace rb {
 constexpr int kTile = 8;                  // tile edge in pixels: one 64-lane wave per tile
 constexpr int kWave = 64;
 constexpr float kTauDet = 1e-10f;         // |det F(tau)| at or below this: face skipped
+// background adjoint: a term whose weight prod_{m != j}(1 - A_m) A_j is below
+// this is left out, and so is a whole (pixel, sub-frame) where the bound
+// prod_m (1 - A_m) / min(min_m (1 - A_m), 1/2) on its weights is (the FP64
+// reference with the same rule: the vertex gradient moves by ~1e-6)
+constexpr float kAdjWMin = 1e-8f;
 constexpr int kHdrFaceRange = 1, kHdrBehind = 2, kHdrOverflow = 4;
 
 // First sub-frame of segment s: the smallest k with floor(k S / (K-1)) >= s,
@@ -95,7 +100,7 @@ struct Inst {
     int64_t RB_G *bsum;       // scan block sums
     uint32_t RB_G *list;      // entries: face << 8 | sub-frame mask
     int32_t RB_G *vis_id;     // [ntiles][K][64] winner face; -1 uncovered; -4 outside the image
-    float RB_G *pix;          // [ntiles][K][NS][64] winner colour, or (sum log2(1 - A), #zero factors)
+    float RB_G *pix;          // [ntiles][K][NS][64] winner colour, or (sum log2(1 - A), #zero factors, min 1 - A)
     int32_t RB_G *tsl;        // [NC][ntiles] background tasks (list slices) per (chunk, tile)
     int64_t RB_G *toff;       // [NC][ntiles] first task
     int64_t RB_G *tbsum;      // task scan block sums
@@ -132,7 +137,7 @@ struct Plan {
     int fgg;        // chunks per wave (at most) in the foreground adjoint
     int bwd_merge;  // background tasks per unit of the background adjoint
     bool wide;      // background halo of 12 pixels or more (faces reach many pixels of a tile)
-    int NS;         // per (pixel, sub-frame) value slots: colour, or log-sum and zero count
+    int NS;         // per (pixel, sub-frame) value slots: colour, or log-sum, zero count, smallest 1 - A
     int nfb;        // binning blocks per chunk
     int64_t cap;    // list capacity (entries)
     int64_t ntct;   // (chunk, tile) pairs = NC * ntiles

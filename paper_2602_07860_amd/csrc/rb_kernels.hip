@@ -1288,8 +1288,10 @@ __global__ __launch_bounds__(64) void k_fg(const Inst *__restrict__ tab, int n)
         if (g.inimg && zid >= 0) shade_gather<SOLVER>(a, zid, ck.s, g, tc, tau[j], rgb);
         a.vis_id[vis_index(a, g.tile, k, lane)] = g.inimg ? zid : kVisOut;
         // colour of a covered pixel; the background accumulators start at 0
+        // (log-sum, zero count) and 1 (smallest non-zero 1 - A)
+        const bool bgpix = !(g.inimg && zid >= 0);
         for (int sl = 0; sl < a.NS; ++sl) {
-            float v = 0.0f;
+            float v = bgpix && sl == 2 ? 1.0f : 0.0f;
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch)
                 if (ch == sl) v = rgb[ch];
@@ -1351,6 +1353,8 @@ struct BgShared {
     double lsum[T][kWave];  // sum of log2(1 - A) over non-zero factors (hundreds of
                             // factors per pixel near a silhouette: summed in double)
     int nz[T][kWave];       // number of zero factors (A == 1)
+    unsigned omin[T][kWave];  // smallest non-zero factor 1 - A below 1/2, else 1 (float bits; min on
+                              // the bits orders non-negative floats)
     int ppre[kWave + 1];    // items regrouped by pixel: first item of each pixel
     uint64_t pe[kWave];     // and its staged entries
 };
@@ -1361,7 +1365,8 @@ struct BgShared {
 // (xk: the keyframe X shared by every sub-frame of the chunk, or -1)
 template <int T, int SOLVER, bool ACC>
 __device__ __forceinline__ void bg_item_fwd(const Inst &a, BgShared<T> &sh, int e, int p, const float tau[T],
-                                            uint32_t xbits, int xk, float tc, double (&ls)[T], int (&nz)[T])
+                                            uint32_t xbits, int xk, float tc, double (&ls)[T], int (&nz)[T],
+                                            float (&om_lo)[T])
 {
     const LdsRec r = lds_rec(sh.it, e);
     const float du = pix_du(p, a.inv_w), dv = pix_dv(p, a.inv_h);
@@ -1384,15 +1389,19 @@ __device__ __forceinline__ void bg_item_fwd(const Inst &a, BgShared<T> &sh, int 
         const float A = exp2f(b.d * a.neg_log2e_over_delta);
         const float om = one_minus_exp_neg(b.d * a.inv_delta, A);
         if (ACC) {
-            if (om > 0.0f)
+            if (om > 0.0f) {
                 ls[j] += (double)log2_one_minus(A, om);
-            else
+                if (om < 0.5f) om_lo[j] = fminf(om_lo[j], om);
+            } else {
                 ++nz[j];
+            }
         } else {
-            if (om > 0.0f)
+            if (om > 0.0f) {
                 atomicAdd(&sh.lsum[j][p], (double)log2_one_minus(A, om));
-            else
+                if (om < 0.5f) atomicMin(&sh.omin[j][p], __float_as_uint(om));
+            } else {
                 atomicAdd(&sh.nz[j][p], 1);
+            }
         }
     }
 }
@@ -1434,6 +1443,7 @@ __global__ __launch_bounds__(64, 4) void k_bg(const Inst *__restrict__ tab, int 
             unc[j] = __ballot(vid == -1);
             sh.lsum[j][lane] = 0.0;
             sh.nz[j][lane] = 0;
+            sh.omin[j][lane] = __float_as_uint(1.0f);
         }
         const int64_t idx = (int64_t)a.NC * a.ntiles + ct;
         const int64_t beg = a.off[idx];
@@ -1453,8 +1463,9 @@ __global__ __launch_bounds__(64, 4) void k_bg(const Inst *__restrict__ tab, int 
                 // pixels)
                 double ls[T];
                 int nzc[T];
+                float oml[T];
                 for_items<T>(sh.it, total, cnt, pre, [&](int e, int p) {
-                    bg_item_fwd<T, SOLVER, false>(a, sh, e, p, tau, xbits, xk, tc, ls, nzc);
+                    bg_item_fwd<T, SOLVER, false>(a, sh, e, p, tau, xbits, xk, tc, ls, nzc, oml);
                 });
                 continue;
             }
@@ -1471,21 +1482,25 @@ __global__ __launch_bounds__(64, 4) void k_bg(const Inst *__restrict__ tab, int 
             lds_sync();
             double ls[T];
             int nzc[T];
+            float oml[T];
 #pragma unroll
             for (int j = 0; j < T; ++j) {
                 ls[j] = 0.0;
                 nzc[j] = 0;
+                oml[j] = 1.0f;
             }
             for_runs(
                 kSeqBgFwd, total, inclp - cp, sh.ppre, sh.pe,
-                [&](int p, int e) { bg_item_fwd<T, SOLVER, true>(a, sh, e, p, tau, xbits, xk, tc, ls, nzc); },
+                [&](int p, int e) { bg_item_fwd<T, SOLVER, true>(a, sh, e, p, tau, xbits, xk, tc, ls, nzc, oml); },
                 [&](int p) {
 #pragma unroll
                     for (int j = 0; j < T; ++j) {
                         if (ls[j] != 0.0) atomicAdd(&sh.lsum[j][p], ls[j]);
                         if (nzc[j]) atomicAdd(&sh.nz[j][p], nzc[j]);
+                        if (oml[j] < 1.0f) atomicMin(&sh.omin[j][p], __float_as_uint(oml[j]));
                         ls[j] = 0.0;
                         nzc[j] = 0;
+                        oml[j] = 1.0f;
                     }
                 });
             lds_sync();
@@ -1496,8 +1511,10 @@ __global__ __launch_bounds__(64, 4) void k_bg(const Inst *__restrict__ tab, int 
             if (!((unc[j] >> lane) & 1ull)) continue;
             const float ls = (float)sh.lsum[j][lane];
             const int nz = sh.nz[j][lane];
+            const unsigned om = sh.omin[j][lane];
             if (ls != 0.0f) unsafeAtomicAdd(&a.pix[pix_index(a, g.tile, ck.k0 + j, 0, lane)], ls);
             if (nz) atomicAdd((int *)&a.pix[pix_index(a, g.tile, ck.k0 + j, 1, lane)], nz);
+            if (om < __float_as_uint(1.0f)) atomicMin((unsigned *)&a.pix[pix_index(a, g.tile, ck.k0 + j, 2, lane)], om);
         }
     }
     }
@@ -1942,9 +1959,10 @@ __device__ __forceinline__ void bg_item_bwd(const Inst &a, BgBwdShared<T> &sh, i
         // product over the other factors: the item's own factor divided out,
         // or the product of the rest when the item holds the one zero factor
         const float P = sh.P[j][p];
-        const float Pe = !signbit(P) ? P / om : (om > 0.0f ? 0.0f : -P);
+        const float Pe = !signbit(P) ? P * rcp(om) : (om > 0.0f ? 0.0f : -P);
+        // a term of weight prod_{m != j}(1 - A_m) A_j below kAdjWMin is left out
+        if (!(Pe * A >= kAdjWMin)) continue;
         const float gd = -galpha * Pe * A * a.inv_delta;
-        if (gd == 0.0f) continue;
         const float gpx = 2.0f * gd * (b.psx - du), gpy = 2.0f * gd * (b.psy - dv);
         float xt[3], yt[3];
 #pragma unroll
@@ -2058,7 +2076,7 @@ __global__ __launch_bounds__(64, WPS) void k_bg_bwd(const Inst *__restrict__ tab
 #pragma unroll
         for (int j = 0; j < T; ++j) {
             int vid = kVisOut;
-            float P = 0.0f;
+            float P = 0.0f, om_lo = 1.0f;
             int nz = 0;
             if (j < ck.n) {
                 const int k = ck.k0 + j;
@@ -2066,10 +2084,15 @@ __global__ __launch_bounds__(64, WPS) void k_bg_bwd(const Inst *__restrict__ tab
                 if (vid == -1) {
                     P = exp2f(a.pix[pix_index(a, g.tile, k, 0, lane)]);
                     nz = __float_as_int(a.pix[pix_index(a, g.tile, k, 1, lane)]);
+                    om_lo = fminf(a.pix[pix_index(a, g.tile, k, 2, lane)], 0.5f);
                 }
             }
             sh.P[j][lane] = nz == 0 ? P : (nz == 1 ? -P : -0.0f);
-            bgm[j] = __ballot(vid == -1 && gal != 0.0f);
+            // every term's weight prod_{m != j}(1 - A_m) A_j is at most
+            // P / min(min(1 - A), 1/2): below kAdjWMin the pixel-sub-frame is
+            // skipped; with two zero factors every weight is 0
+            const bool live = nz == 1 || (nz == 0 && !(P < kAdjWMin * om_lo));
+            bgm[j] = __ballot(vid == -1 && gal != 0.0f && live);
             anybg = anybg || bgm[j] != 0ull;
         }
         if (!anybg) continue;

@@ -122,3 +122,20 @@ def test_closest_point_weights_carry_gradient():
           _loss(sc.with_(verts=vm), G, replay=full.decisions)) / h
     assert abs(fd - full.grad_verts[vi, ci]) < abs(fd - stop.grad_verts[vi, ci])
     assert abs(fd - full.grad_verts[vi, ci]) <= 1e-3 * abs(fd) + 1e-9
+
+
+def test_adjoint_weight_cutoff_is_negligible():
+    # the GPU adjoint leaves out background terms whose derivative weight
+    # prod_{m != j}(1 - A_m) A_j is below 1e-8 (whole (pixel, sub-frame)s
+    # where a bound on the weights is); with the same rule the oracle's vertex
+    # gradient moves by far less than the parity tolerance, and the rule is
+    # not vacuous
+    sc = wl.make_workload(wl.MEDIUM)
+    G = np.random.default_rng(0).normal(size=(4, sc.height, sc.width))
+    exact = oracle.render(sc, grad_image=G, counters=True)
+    cut = oracle.render(sc, grad_image=G, adj_wmin=1e-8)
+    d = np.linalg.norm(cut.grad_verts - exact.grad_verts) / np.linalg.norm(exact.grad_verts)
+    assert 0.0 < d < 2e-6, d
+    c = exact.counters
+    assert 0.0 < c["bg_pairs_live"] < 0.95 * c["bg_pairs"]
+    np.testing.assert_allclose(cut.grad_attrs, exact.grad_attrs, rtol=1e-9, atol=1e-15)   # background terms carry no colour gradient
