@@ -1,34 +1,55 @@
-// HIP kernels (gfx950) of the motion-blur differentiable rasterizer.
+// HIP kernels (gfx950) of the motion-blur differentiable rasterizer and the
+// launch sequences of its forward and backward passes.
 //
-// Work decomposition
-//   * keyframes: one thread per (keyframe, vertex) projects M_s P0 (App. I)
-//     in double precision and keeps (x, y) in double, depth in float.  A face
-//     seen almost edge-on has a tiny area, so its barycentrics move by
-//     (position error)/(height); float32 keyframes alone would cost ~1e-5 of
-//     the image there.  Each list entry turns the doubles into float32
-//     coordinates relative to the tile anchor at the chunk's middle time,
-//     where they are small and exact to ~1e-9.
-//   * chunks: the sub-frames t_k = k/(K-1) (Sec. 3.2) of each linear segment
-//     (Sec. 3.3) are cut into chunks of at most T consecutive sub-frames that
-//     share one segment, hence one pair of keyframes and one set of
-//     fast-solver coefficients (eq 8, "computed only once").
-//   * binning: one thread per (face, chunk) computes the face's exact
-//     screen bounding box at every sub-frame of the chunk and emits, for every
-//     8x8 tile the chunk's boxes touch, one entry face << 8 | mask where bit j
-//     says "touches this tile at sub-frame j".  Two lists per (chunk, tile):
-//     foreground (exact box) and background (box grown by the influence
-//     radius sqrt(d_max)).  Count, exclusive scan, fill.
-//   * raster: one 64-lane wave per (8x8 tile, group of chunks); lane = pixel.
-//     List entries are staged in LDS a batch at a time (one entry per lane);
-//     foreground faces are tested by every lane (z-buffer in registers);
-//     background (pixel, face) pairs are filtered by a distance lower bound
-//     and compacted into an LDS queue so that all 64 lanes evaluate useful
-//     pairs (details above k_raster_fwd).
-//   * backward: same walks over the lists, reading the forward's per
-//     (pixel, sub-frame) visibility; per-entry LDS gradient slots collect the
-//     lanes' contributions and are added atomically to per-keyframe vertex
-//     gradients; a last kernel maps those through the projection to
-//     rest-vertex gradients.
+// Every kernel covers all instances of a batch (a single render is a batch of
+// one); blocks find their instance in a table written by k_set_table.
+//
+// Forward (launch_forward):
+//   k_init, k_project  clear the workspace's counters; project the S+1
+//                      keyframes M_s P0 (App. I), (x, y) in double, depth in
+//                      float (a nearly edge-on face's barycentrics move by
+//                      position error / height, so float32 keyframes would
+//                      cost ~1e-5 of the image).
+//   k_bin (x2), k_scan1..3
+//                      one thread per (face, chunk of at most T sub-frames of
+//                      one segment) takes the face's exact box at each of the
+//                      chunk's sub-frames and, for every 8x8 tile the union
+//                      touches, emits face << 8 | sub-frame mask into the
+//                      foreground list (exact box) and the background list
+//                      (box grown by the influence radius); counts and fill
+//                      ranks go through LDS window counters.
+//   k_fg               one 64-lane wave per (chunk, tile), lane = pixel: list
+//                      entries are staged in LDS 32 at a time (anchor-local
+//                      float32 records) and dealt out as (entry, pixel)
+//                      items; coverage by the fast solver (eq 8: quadratic
+//                      numerators per (pixel, face, chunk), Horner per
+//                      sub-frame) or the per-sub-frame recompute; an LDS
+//                      64-bit z-buffer (depth bits, face) picks the winner,
+//                      which is shaded (eq 9); visibility and winner colours
+//                      go to the per (pixel, sub-frame) records; the
+//                      (chunk, tile)'s background tasks are counted.
+//   k_tasks, k_tprefix number the background tasks (slices of a list).
+//   k_bg               persistent waves over the background tasks: items of
+//                      the uncovered (pixel, sub-frame)s accumulate
+//                      log2(1 - A) (eqs 10, 13-15, App. B closest point),
+//                      the zero factors and the smallest 1 - A in LDS, then
+//                      in the records.
+//   k_resolve          mean over the K sub-frames (double).
+// Backward (launch_backward):
+//   k_bwd_init         clears the keyframe and attribute gradients.
+//   k_fg_bwd           one wave per (group of chunks of a segment, tile):
+//                      gathers the distinct winners from the visibility,
+//                      stages them and runs the shading / barycentric
+//                      adjoint into an LDS table keyed by vertex.
+//   k_bg_bwd           persistent waves over the background tasks, with a
+//                      task counter: re-walks the list slices for the
+//                      (pixel, sub-frame)s with gradient (leaving out terms
+//                      of negligible weight) and runs the closest-point /
+//                      barycentric adjoint into the vertex table.
+//   k_kf_to_vertex     maps keyframe gradients through the projection and
+//                      the keyframe transforms to the rest vertices.
+// The adjoints deal items to lanes in runs (for_runs) so that a lane adds a
+// run's contributions to the vertex table once per (lane, entry).
 #include <cfloat>
 #include <climits>
 #include <cstring>
