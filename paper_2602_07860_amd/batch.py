@@ -172,16 +172,61 @@ def batch_signature(scenes: Sequence[SceneTensors], solver: str) -> tuple:
                               st.num_subframes, st.camera.width, st.camera.height) for st in scenes)
 
 
+def batch_class(scenes: Sequence[SceneTensors], solver: str) -> str:
+    """Coarse class of a batch for the on-disk cache: solver, instance count,
+    the count of each image size, and the total faces, the median sub-frame
+    count and the median segment count rounded to powers of two."""
+    import math
+    res: Dict[str, int] = {}
+    for st in scenes:
+        k = f"{st.camera.width}x{st.camera.height}"
+        res[k] = res.get(k, 0) + 1
+    p2 = lambda x: int(round(math.log2(max(1, x))))
+    faces = sum(int(st.faces.shape[0]) for st in scenes)
+    ks = sorted(int(st.num_subframes) for st in scenes)
+    ss = sorted(int(st.model.shape[0]) - 1 for st in scenes)
+    return (f"{solver}|n{len(scenes)}|" + ",".join(f"{k}:{v}" for k, v in sorted(res.items()))
+            + f"|F2^{p2(faces)}|K2^{p2(ks[len(ks) // 2])}|S2^{p2(ss[len(ss) // 2])}")
+
+
+def _load_cache(path: str) -> Dict[str, list]:
+    import json
+    import os
+    if not path or not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
+
+
+def _store_cache(path: str, key: str, value: Tuple[int, int]) -> None:
+    import json
+    import os
+    data = _load_cache(path)
+    data[key] = list(value)
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
 def autotune(scenes: Sequence[SceneTensors], targets: Sequence[torch.Tensor], solver: str = "fast",
              chunk_lens=(1, 2, 4, 8), slice_lens=(32, 64, 128, 256), reps: int = 3,
-             log=None) -> Tuple[int, int]:
+             log=None, cache_path: Optional[str] = None) -> Tuple[int, int]:
     """Chunk length and background slice length with the shortest fwd+bwd L2
     step on this batch (each candidate timed with device events over `reps`
     eager steps after one warm-up that also sizes its lists).  Results are
-    remembered per batch signature."""
+    remembered per batch signature in memory and, with cache_path, per batch
+    class (batch_class) in a JSON file that later runs read instead of
+    timing."""
     key = batch_signature(scenes, solver)
     if key in _tuned:
         return _tuned[key]
+    if cache_path:
+        hit = _load_cache(cache_path).get(batch_class(scenes, solver))
+        if hit is not None and hit[0] in chunk_lens and hit[1] in slice_lens:
+            _tuned[key] = (int(hit[0]), int(hit[1]))
+            return _tuned[key]
     best, best_ms = None, float("inf")
     caps = None
     for T in chunk_lens:
@@ -206,4 +251,6 @@ def autotune(scenes: Sequence[SceneTensors], targets: Sequence[torch.Tensor], so
                 best, best_ms = (T, SL), ms
             del r, step
     _tuned[key] = best
+    if cache_path:
+        _store_cache(cache_path, batch_class(scenes, solver), best)
     return best

@@ -98,6 +98,15 @@ def test_autotuner_picks_a_valid_configuration(case):
     say("case: autotuner on a batch of 4")
     sts = [R.scene_tensors(sc, "cuda") for sc in scs]
     targets = [torch.as_tensor(ref.image, dtype=torch.float32, device="cuda") for ref in refs]
-    T, SL = BT.autotune(sts, targets, chunk_lens=(2, 4), slice_lens=(32, 64), reps=2, log=say)
+    import os
+    import tempfile
+    cache = os.path.join(tempfile.mkdtemp(), "autotune.json")
+    T, SL = BT.autotune(sts, targets, chunk_lens=(2, 4), slice_lens=(32, 64), reps=2, log=say, cache_path=cache)
     assert T in (2, 4) and SL in (32, 64)
     assert BT.autotune(sts, targets, chunk_lens=(2, 4), slice_lens=(32, 64)) == (T, SL)
+    # a fresh process state reads the batch class from the file without timing
+    BT._tuned.clear()
+    timed = []
+    assert BT.autotune(sts, targets, chunk_lens=(2, 4), slice_lens=(32, 64), log=timed.append,
+                       cache_path=cache) == (T, SL)
+    assert not timed

@@ -14,3 +14,16 @@ def test_traffic_lookup_matches_source_hash(tmp_path):
     assert profiling.lookup(str(p), "k_bg_bwd", "large") is None
     assert profiling.lookup(str(p), "k_fg", "medium") is None
     assert profiling.lookup(str(tmp_path / "missing.json"), "k_bg_bwd", "medium") is None
+
+
+def test_batch_class_is_coarse_and_stable():
+    import torch
+    from paper_2602_07860_amd import batch as BT
+    from paper_2602_07860_amd import render as R
+    from paper_2602_07860_amd import workloads as wl
+    scs = wl.make_batch(seed=3, n=4)
+    sts = [R.scene_tensors(sc, "cpu") for sc in scs]
+    c1 = BT.batch_class(sts, "fast")
+    assert c1 == BT.batch_class(list(reversed(sts)), "fast")
+    assert c1 != BT.batch_class(sts, "recompute")
+    assert c1.startswith("fast|n4|")
