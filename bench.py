@@ -129,7 +129,7 @@ def run_single(start, tg, args, torch, B, R, adam=False):
 
     def opts(solver, check=True):
         return R.RenderOptions(start.num_subframes, solver=solver, chunk_len=args.chunk_len,
-                               slice_len=args.slice_len, check=check)
+                               slice_len=args.slice_len, check=check, deterministic=args.deterministic)
 
     target, _ = R.render_forward(tt.verts, tt.faces, tt.attrs, tt.model, tt.camera, opts("fast"))
     res = {}
@@ -346,11 +346,17 @@ def main():
     ap.add_argument("--slice-len", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--deterministic", action="store_true",
+                    help="render with RB_FLAG_DETERMINISTIC (large and medium workloads)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    if args.deterministic and args.workload not in ("large", "medium"):
+        print("--deterministic applies to the large and medium workloads", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -418,6 +424,8 @@ def main():
                   "faces": int(len(sc.faces)), "resolution": f"{sc.width}x{sc.height}",
                   "subframes": sc.num_subframes, "segments": sc.num_segments, "solver": "fast",
                   "chunk_len": args.chunk_len}
+        if args.deterministic:
+            config["deterministic"] = True
         if adam:
             config["loss_after_loop"] = round(res["fast"]["loss"], 4)
     units = sum(s.height * s.width * s.num_subframes for s in scenes)

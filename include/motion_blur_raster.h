@@ -62,6 +62,21 @@ enum {
 
 enum { RB_SOLVER_FAST = 0, RB_SOLVER_RECOMPUTE = 1 };
 
+/* rb_options.flags.
+ * RB_FLAG_DETERMINISTIC: image and gradients are bitwise the same on every
+ * run with the same inputs, options and device, whatever order the GPU's
+ * waves run in (the default mode adds partial sums with floating-point
+ * atomics, whose order varies, so its results vary in the last bits).  The
+ * library then (1) sorts every bin list into face order, (2) gives each
+ * (chunk, tile) a single background task, so that one wave adds up each
+ * (pixel, sub-frame)'s factors, and (3) adds the gradient partial sums as
+ * 64-bit integers in units of 2^(e - 32), where 2^(e-1) <= max |dL/dI| < 2^e,
+ * converting them to float at the end.  Slower; results agree with the
+ * default mode to float rounding and the unit above.  A partial sum of
+ * 2^30 max |dL/dI| or more (or a NaN) sets header bit 8 and fills that
+ * instance's gradients with NaN. */
+#define RB_FLAG_DETERMINISTIC 1
+
 #define RB_MAX_CHANNELS 4          /* attributes per vertex (C)            */
 #define RB_MAX_FACES (1 << 23)     /* faces per mesh                       */
 #define RB_MAX_CHUNK 8             /* sub-frames per work chunk            */
@@ -91,7 +106,7 @@ typedef struct {
     float delta;             /* softness of the background probability (1e-4)  */
     float eps_cutoff;        /* probabilities A < eps are dropped: 0 < eps < 1  */
     int32_t solver;          /* RB_SOLVER_FAST or RB_SOLVER_RECOMPUTE           */
-    int32_t flags;           /* reserved, 0                                     */
+    int32_t flags;           /* 0 or RB_FLAG_DETERMINISTIC                      */
     int32_t chunk_len;       /* max sub-frames per work chunk: 1, 2, 4 or 8; 0 = 4;
                                 a segment is split into equal chunks         */
     int32_t slice_len;       /* background-list entries per task; 0 = auto (64) */
@@ -100,7 +115,8 @@ typedef struct {
 
 /* Device-side findings of the last call on a workspace (rb_read_header). */
 typedef struct {
-    int32_t error_bits;      /* 1: face index out of range, 2: vertex behind camera, 4: overflow */
+    int32_t error_bits;      /* 1: face index out of range, 2: vertex behind camera, 4: overflow,
+                                8: deterministic gradient sum out of range (RB_FLAG_DETERMINISTIC) */
     int32_t reserved;
     int64_t list_entries;    /* entries the last forward needed (fg + bg)        */
     int64_t list_capacity;   /* entries available                                */

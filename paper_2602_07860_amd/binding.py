@@ -17,7 +17,8 @@ RB_MAX_CHANNELS = 4
 RB_MAX_FACES = 1 << 23
 RB_MAX_CHUNK = 8
 RB_STATIC_SCRATCH_BYTES = 64 << 20
-HDR_FACE_RANGE, HDR_BEHIND, HDR_OVERFLOW = 1, 2, 4
+HDR_FACE_RANGE, HDR_BEHIND, HDR_OVERFLOW, HDR_DET_RANGE = 1, 2, 4, 8
+RB_FLAG_DETERMINISTIC = 1
 
 RB_BATCH_FORWARD, RB_BATCH_BACKWARD = 0, 1
 

@@ -28,6 +28,7 @@ static rb_status make_plan(int32_t V, int32_t F, int32_t C, const rb_motion *mot
         if (!std::isfinite(cam->view[i])) return RB_EINVAL;
     if (opt->solver != RB_SOLVER_FAST && opt->solver != RB_SOLVER_RECOMPUTE) return RB_EINVAL;
     if (opt->chunk_len < 0 || opt->slice_len < 0 || opt->list_capacity < 0) return RB_EINVAL;
+    if (opt->flags & ~RB_FLAG_DETERMINISTIC) return RB_EINVAL;
     if (C > RB_MAX_CHANNELS) return RB_EUNSUPPORTED;
     if (F >= RB_MAX_FACES) return RB_EUNSUPPORTED;
     const int T = opt->chunk_len == 0 ? 4 : opt->chunk_len;
@@ -70,7 +71,8 @@ static rb_status make_plan(int32_t V, int32_t F, int32_t C, const rb_motion *mot
     // background list entries per task: small enough that the longest lists
     // (silhouette tiles) spread over many waves, large enough to amortize a
     // task's set-up
-    p.SL = opt->slice_len > 0 ? opt->slice_len : 64;
+    p.det = (opt->flags & RB_FLAG_DETERMINISTIC) != 0;
+    p.SL = p.det ? kDetSliceLen : (opt->slice_len > 0 ? opt->slice_len : 64);
     // When the background halo spans many pixels, faces reach many pixels of
     // a tile: longer per-lane runs of items pay off in the background adjoint
     // (fewer LDS atomics per item), and the background forward groups its
@@ -130,6 +132,8 @@ static rb_status make_plan(int32_t V, int32_t F, int32_t C, const rb_motion *mot
     o = align256(o + (size_t)(S + 1) * V * 2 * 4);
     p.o_fgw = o;
     o = align256(o + (size_t)p.ntct * 4);
+    p.o_gfx = o;
+    if (p.det) o = align256(o + ((size_t)(S + 1) * V * 2 + (size_t)V * C) * 8);
     p.total = o;
     return RB_OK;
 }
@@ -146,6 +150,7 @@ static rb_status make_batch(const std::vector<Plan> &plans, Batch &bt)
     bt.solver = plans[0].solver;
     bt.wide = true;
     for (const Plan &p : plans) bt.wide = bt.wide && p.wide;
+    bt.det = plans[0].det;
     bt.plans = plans;
     bt.base.resize(bt.n);
     Grids g{};
@@ -154,23 +159,27 @@ static rb_status make_batch(const std::vector<Plan> &plans, Batch &bt)
         const Plan &p = plans[i];
         bt.base[i] = o;
         o = align256(o + p.total);
-        g.init += (p.ncounts + 255) / 256;
-        g.proj += ((int64_t)(p.S + 1) * p.V + p.F + 255) / 256;
-        g.bin += (int64_t)p.NC * p.nfb;
-        g.scan1 += p.nblocks_scan;
-        g.scan3 += (p.ncounts + 255) / 256;
-        g.tscan1 += p.nblocks_tscan;
-        g.tscan3 += (p.ntct + 255) / 256;
-        g.fg += p.ntct;
-        g.fgb += (int64_t)p.S * ((p.CPS + p.fgg - 1) / p.fgg) * p.ntiles;
-        g.res += p.ntiles;
-        g.bwdinit += ((int64_t)(p.S + 1) * p.V * 2 + (int64_t)p.V * p.C + 255) / 256;
-        g.vtx += (p.V + 255) / 256;
+        const Grids q = plan_grids(p);
+        g.init += q.init;
+        g.proj += q.proj;
+        g.bin += q.bin;
+        g.scan1 += q.scan1;
+        g.scan3 += q.scan3;
+        g.tscan1 += q.tscan1;
+        g.tscan3 += q.tscan3;
+        g.fg += q.fg;
+        g.fgb += q.fgb;
+        g.res += q.res;
+        g.bwdinit += q.bwdinit;
+        g.vtx += q.vtx;
+        g.sort += q.sort;
+        g.detp += q.detp;
     }
     // one launch covers every instance: block counts must fit the grid and
     // the 32-bit block starts of the table
     const int64_t lim = (1LL << 31) - 1;
-    for (int64_t v : {g.init, g.proj, g.bin, g.scan1, g.scan3, g.tscan1, g.tscan3, g.fg, g.fgb, g.res, g.bwdinit, g.vtx})
+    for (int64_t v : {g.init, g.proj, g.bin, g.scan1, g.scan3, g.tscan1, g.tscan3, g.fg, g.fgb, g.res, g.bwdinit, g.vtx,
+                      g.sort, g.detp})
         if (v > lim) return RB_EUNSUPPORTED;
     bt.g = g;
     bt.o_table = o;

@@ -2,6 +2,7 @@
 // (rb_kernels.hip).  Not part of the public ABI.
 #pragma once
 #include <cstddef>
+#include <algorithm>
 #include <cstdint>
 #include <vector>
 
@@ -19,7 +20,10 @@ constexpr float kTauDet = 1e-10f;         // |det F(tau)| at or below this: face
 // prod_m (1 - A_m) / min(min_m (1 - A_m), 1/2) on its weights is (the FP64
 // reference with the same rule: the vertex gradient moves by ~1e-6)
 constexpr float kAdjWMin = 1e-8f;
-constexpr int kHdrFaceRange = 1, kHdrBehind = 2, kHdrOverflow = 4;
+constexpr int kHdrFaceRange = 1, kHdrBehind = 2, kHdrOverflow = 4, kHdrDetRange = 8;
+// deterministic mode: one background task per (chunk, tile) (lists hold
+// distinct faces, fewer than RB_MAX_FACES < this)
+constexpr int kDetSliceLen = 1 << 24;
 
 // First sub-frame of segment s: the smallest k with floor(k S / (K-1)) >= s,
 // i.e. sub-frame t_k = k/(K-1) falls in segment min(floor(t_k S), S-1).
@@ -59,7 +63,9 @@ struct DevHeader {
     int64_t list_capacity;
     int64_t ntasks;       // background tasks of the current forward
     unsigned long long bwd_task_ctr;   // next background-adjoint task
-    int64_t pad[3];
+    uint32_t gmax;        // deterministic mode: bits of max |dL/dI| (non-negative floats order as integers)
+    int32_t pad32;
+    int64_t pad[2];
 };
 
 // The device pass sees an instance's buffers as global-memory pointers, so
@@ -107,6 +113,7 @@ struct Inst {
     uint64_t RB_G *tasks;     // (chunk * ntiles + tile) << 32 | slice
     float RB_G *gkf;          // [S+1][V][2] keyframe gradient
     int32_t RB_G *fgw;        // [NC * ntiles] 1 where the (chunk, tile) has a winner
+    int64_t RB_G *gfx;        // deterministic mode: [S+1][V][2] then [V][C] gradient sums in fixed point
     // sizes
     int V, F, C, S, K, W, H, tiles_x, tiles_y, ntiles;
     int CPS, NC, SL, NS, nfb;
@@ -114,12 +121,14 @@ struct Inst {
     int fgg;             // chunks per wave (at most) in the foreground adjoint
     int bwd_merge;       // background tasks per unit of the background adjoint
     int ntct;            // (chunk, tile) pairs = NC * ntiles
+    int det;             // RB_FLAG_DETERMINISTIC
     int nblocks_scan, nblocks_tscan;
     int64_t cap, maxtasks, ncounts;
     float inv_w, inv_h, dmax, halo, neg_log2e_over_delta, inv_delta, invK;
     ViewArgs vw;
     // first block of this instance in each launch
-    int b_init, b_proj, b_bin, b_scan1, b_scan3, b_tscan1, b_tscan3, b_fg, b_fgb, b_res, b_bwdinit, b_vtx;
+    int b_init, b_proj, b_bin, b_scan1, b_scan3, b_tscan1, b_tscan3, b_fg, b_fgb, b_res, b_bwdinit, b_vtx,
+        b_sort, b_detp;
 };
 
 // Host plan of one instance.
@@ -137,6 +146,7 @@ struct Plan {
     int fgg;        // chunks per wave (at most) in the foreground adjoint
     int bwd_merge;  // background tasks per unit of the background adjoint
     bool wide;      // background halo of 12 pixels or more (faces reach many pixels of a tile)
+    bool det;       // RB_FLAG_DETERMINISTIC
     int NS;         // per (pixel, sub-frame) value slots: colour, or log-sum, zero count, smallest 1 - A
     int nfb;        // binning blocks per chunk
     int64_t cap;    // list capacity (entries)
@@ -144,20 +154,44 @@ struct Plan {
     int64_t maxtasks;
     // workspace byte offsets (from the instance's base)
     size_t o_hdr, o_kf, o_kfz, o_cnt, o_off, o_cur, o_bsum, o_list, o_vis_id, o_pix, o_tsl, o_toff, o_tbsum,
-        o_tasks, o_gkf, o_fgw, total;
+        o_tasks, o_gkf, o_fgw, o_gfx, total;
     int64_t ncounts;  // 2 * NC * ntiles
     int64_t nblocks_scan, nblocks_tscan;
 };
 
 // Block counts of each launch over a batch.
 struct Grids {
-    int64_t init, proj, bin, scan1, scan3, tscan1, tscan3, fg, fgb, res, bwdinit, vtx;
+    int64_t init, proj, bin, scan1, scan3, tscan1, tscan3, fg, fgb, res, bwdinit, vtx, sort, detp;
 };
+
+// Blocks of one instance in each launch (256-thread blocks unless noted).
+inline Grids plan_grids(const Plan &p)
+{
+    auto div = [](int64_t n, int64_t b) { return (n + b - 1) / b; };
+    const int64_t ngrad = (int64_t)(p.S + 1) * p.V * 2 + (int64_t)p.V * p.C;
+    Grids g;
+    g.init = div(p.ncounts, 256);
+    g.proj = div((int64_t)(p.S + 1) * p.V + p.F, 256);
+    g.bin = (int64_t)p.NC * p.nfb;
+    g.scan1 = p.nblocks_scan;
+    g.scan3 = div(p.ncounts, 256);
+    g.tscan1 = p.nblocks_tscan;
+    g.tscan3 = div(p.ntct, 256);
+    g.fg = p.ntct;                                                   // one wave per (chunk, tile)
+    g.fgb = (int64_t)p.S * div(p.CPS, p.fgg) * p.ntiles;             // one wave per chunk group and tile
+    g.res = p.ntiles;
+    g.bwdinit = div(ngrad, 256);                                     // also the deterministic finish
+    g.vtx = div(p.V, 256);
+    g.sort = p.det ? p.ncounts : 0;                                  // one block per bin list
+    g.detp = p.det ? div(std::max<int64_t>(ngrad, (int64_t)(p.C + 1) * p.H * p.W), 256) : 0;
+    return g;
+}
 
 // Host plan of a batch: per-instance plans and where each instance's
 // workspace starts; the table of Inst and the task numbering follow them.
 struct Batch {
     int n, T, solver;
+    bool det;       // RB_FLAG_DETERMINISTIC (batch-wide: one options record)
     bool wide;      // every instance has a wide halo: background kernels built for long item runs
     std::vector<Plan> plans;
     std::vector<size_t> base;

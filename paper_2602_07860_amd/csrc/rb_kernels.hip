@@ -147,12 +147,69 @@ __global__ void k_bwd_init(const Inst *__restrict__ tab, int n)
 {
     const Inst a = tab[inst_of<&Inst::b_bwdinit>(tab, n, blockIdx.x)];
     const int64_t i = (int64_t)(blockIdx.x - a.b_bwdinit) * blockDim.x + threadIdx.x;
-    if (i == 0) a.hdr->bwd_task_ctr = 0;
+    if (i == 0) {
+        a.hdr->bwd_task_ctr = 0;
+        a.hdr->gmax = 0;
+    }
     const int64_t n1 = (int64_t)(a.S + 1) * a.V * 2, n2 = (int64_t)a.V * a.C;
     if (i < n1)
         a.gkf[i] = 0.0f;
     else if (i < n1 + n2)
         a.grad_attrs[i - n1] = 0.0f;
+}
+
+// Deterministic mode: gradient partial sums are added as 64-bit integers in
+// units of 2^-det_shift, det_shift = 32 - e with 2^(e-1) <= max |dL/dI| < 2^e
+// (integer addition does not depend on the order the atomics resolve in).
+__device__ __forceinline__ int det_shift(const Inst &a)
+{
+    const float g = __uint_as_float(a.hdr->gmax);
+    int e = 0;
+    if (g > 0.0f && g <= 3.4028235e38f) (void)frexpf(g, &e);
+    return 32 - e;
+}
+
+__device__ __forceinline__ void det_add(const Inst &a, int64_t RB_G *acc, double v, int shift)
+{
+    const double q = rint(ldexp(v, shift));
+    if (!(fabs(q) < 0x1p62)) {
+        atomicOr(&a.hdr->error_bits, kHdrDetRange);
+        return;
+    }
+    atomicAdd((unsigned long long RB_G *)acc, (unsigned long long)(long long)q);
+}
+
+// deterministic mode, before the adjoint: max |dL/dI| (as float bits) and
+// cleared fixed-point gradient sums
+__global__ void k_det_prep(const Inst *__restrict__ tab, int n)
+{
+    const Inst a = tab[inst_of<&Inst::b_detp>(tab, n, blockIdx.x)];
+    const int64_t i = (int64_t)(blockIdx.x - a.b_detp) * blockDim.x + threadIdx.x;
+    const int64_t ngrad = (int64_t)(a.S + 1) * a.V * 2 + (int64_t)a.V * a.C;
+    const int64_t nimg = (int64_t)(a.C + 1) * a.H * a.W;
+    if (i < ngrad) a.gfx[i] = 0;
+    uint32_t b = i < nimg ? __float_as_uint(fabsf(a.grad_image[i])) : 0u;
+    // one atomic per wave (unsigned max on the bits orders non-negative
+    // floats; a NaN's bits exceed every finite value's)
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) b = max(b, (uint32_t)__shfl_xor((int)b, d));
+    if ((threadIdx.x & 63) == 0 && b) atomicMax(&a.hdr->gmax, b);
+}
+
+// deterministic mode, after the adjoint: fixed-point sums to the float
+// keyframe and attribute gradients (NaN if a sum left the integer range)
+__global__ void k_det_finish(const Inst *__restrict__ tab, int n)
+{
+    const Inst a = tab[inst_of<&Inst::b_bwdinit>(tab, n, blockIdx.x)];
+    const int64_t i = (int64_t)(blockIdx.x - a.b_bwdinit) * blockDim.x + threadIdx.x;
+    const int64_t n1 = (int64_t)(a.S + 1) * a.V * 2, n2 = (int64_t)a.V * a.C;
+    if (i >= n1 + n2) return;
+    const bool bad = (a.hdr->error_bits & kHdrDetRange) != 0;
+    const float v = bad ? __builtin_nanf("") : (float)ldexp((double)a.gfx[i], -det_shift(a));
+    if (i < n1)
+        a.gkf[i] = v;
+    else
+        a.grad_attrs[i - n1] = v;
 }
 
 // Keyframe projection (App. I): X = view (M_s P0), x = X.x/(X.z tan), y = X.y/(X.z tan)
@@ -508,6 +565,97 @@ __global__ void k_scan3(const Inst *__restrict__ tab, int n, int which)
     const ScanIo io = scan_io(a, which);
     const int64_t i = (int64_t)(blockIdx.x - io.first3) * blockDim.x + threadIdx.x;
     if (i < io.n) io.off[i] += io.bsum[i / kScanBlock];
+}
+
+// ------------------------------------------------- deterministic list order
+// Deterministic mode: the binning appends entries in whatever order its
+// atomics resolve; sorting each list by entry (face << 8 | mask, faces
+// distinct within a list) makes every later pass see the same order.
+// Bitonic sorting network in the variant without direction changes: merging
+// blocks of size k starts by comparing i with its mirror k - 1 - i in the
+// block, then halves the distance.  Positions past the list's end act as
+// +infinity and never take part (a compare-exchange keeps the minimum at the
+// lower index, so such a pair is a no-op).  Stages whose pairs lie within one
+// block of kSortB entries run in LDS; longer lists do the wider stages in
+// global memory.
+
+constexpr int kSortThreads = 256, kSortB = 4096;
+
+// compare-exchange over pair q of a stage of distance j (j == 0: the mirror
+// step of block size k), indices relative to the buffer
+template <class P>
+__device__ __forceinline__ void cx_pair(P buf, int64_t q, int64_t k, int64_t j, int64_t len)
+{
+    int64_t i, pq;
+    if (j == 0) {
+        const int64_t h = k >> 1, b = q / h, o = q - b * h;
+        i = b * k + o;
+        pq = b * k + k - 1 - o;
+    } else {
+        const int64_t b = q / j;
+        i = b * 2 * j + (q - b * j);
+        pq = i + j;
+    }
+    if (pq >= len) return;
+    const uint32_t x = buf[i], y = buf[pq];
+    if (x > y) {
+        buf[i] = y;
+        buf[pq] = x;
+    }
+}
+
+// LDS pass over block [b0, b0 + blk) of the list (blk a power of two, at
+// most kSortB): the mirror steps of block sizes 2 .. blk, each followed by
+// its halving steps, or (full == false) only the halving steps from distance
+// blk / 2 down to 1
+__device__ __forceinline__ void lds_pass(uint32_t RB_G *L, int64_t len, int64_t b0, int blk, bool full, uint32_t *sh)
+{
+    const int m = (int)min<int64_t>(blk, len - b0);
+    for (int t = threadIdx.x; t < blk; t += kSortThreads) sh[t] = t < m ? L[b0 + t] : 0xffffffffu;
+    __syncthreads();
+    auto halve = [&](int j) {
+        for (; j >= 1; j >>= 1) {
+            for (int q = threadIdx.x; q < blk / 2; q += kSortThreads) cx_pair(sh, q, 0, j, blk);
+            __syncthreads();
+        }
+    };
+    if (!full) {
+        halve(blk >> 1);
+    } else {
+        for (int k = 2; k <= blk; k <<= 1) {
+            for (int q = threadIdx.x; q < blk / 2; q += kSortThreads) cx_pair(sh, q, k, 0, blk);
+            __syncthreads();
+            halve(k >> 2);
+        }
+    }
+    for (int t = threadIdx.x; t < m; t += kSortThreads) L[b0 + t] = sh[t];
+    __syncthreads();
+}
+
+// one block per list (foreground and background lists of every chunk and tile)
+__global__ __launch_bounds__(kSortThreads) void k_sort_lists(const Inst *__restrict__ tab, int n)
+{
+    __shared__ uint32_t sh[kSortB];
+    const Inst &a = tab[inst_of<&Inst::b_sort>(tab, n, blockIdx.x)];
+    const int64_t g = blockIdx.x - a.b_sort;
+    const int64_t len = a.cnt[g], beg = a.off[g];
+    if (len <= 1 || beg + len > a.cap) return;   // (an overflowed forward is reported, not used)
+    uint32_t RB_G *L = a.list + beg;
+    // network size: the smallest power of two >= len
+    int64_t P = 2;
+    while (P < len) P <<= 1;
+    const int blk = (int)min<int64_t>(P, kSortB);
+    // blocks sorted in LDS, then the wider merges
+    for (int64_t b0 = 0; b0 < len; b0 += blk) lds_pass(L, len, b0, blk, true, sh);
+    for (int64_t k = 2 * (int64_t)kSortB; k <= P; k <<= 1) {
+        for (int64_t q = threadIdx.x; q < P / 2; q += kSortThreads) cx_pair(L, q, k, 0, len);
+        __syncthreads();
+        for (int64_t j = k >> 2; j >= kSortB; j >>= 1) {
+            for (int64_t q = threadIdx.x; q < P / 2; q += kSortThreads) cx_pair(L, q, 0, j, len);
+            __syncthreads();
+        }
+        for (int64_t b0 = 0; b0 < len; b0 += kSortB) lds_pass(L, len, b0, kSortB, false, sh);
+    }
 }
 
 // ----------------------------------------------------------------- raster
@@ -1682,20 +1830,34 @@ template <int NV, int NS, class V>
 __device__ __forceinline__ void vt_flush(VTab<NV, NS, V> &vt, int s, const Inst &a)
 {
     const int lane = threadIdx.x & 63;
+    const int shift = a.det ? det_shift(a) : 0;
+    const int64_t n1 = (int64_t)(a.S + 1) * a.V * 2;
     lds_sync();
     for (int i = lane; i < NS; i += kWave) {
         const int v = vt.key[i];
         if (v < 0) continue;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const float g = (float)vt.g[k][i];
-            if (g != 0.0f) unsafeAtomicAdd(a.gkf + ((size_t)(s + (k >> 1)) * a.V + v) * 2 + (k & 1), g);
+            const size_t at = ((size_t)(s + (k >> 1)) * a.V + v) * 2 + (k & 1);
+            if (a.det) {
+                if (vt.g[k][i] != V(0)) det_add(a, a.gfx + at, (double)vt.g[k][i], shift);
+            } else {
+                const float g = (float)vt.g[k][i];
+                if (g != 0.0f) unsafeAtomicAdd(a.gkf + at, g);
+            }
             vt.g[k][i] = V(0);
         }
 #pragma unroll
         for (int c = 0; c < NV - 4; ++c) {
-            const float g = (float)vt.g[4 + c][i];
-            if (g != 0.0f && c < a.C) unsafeAtomicAdd(a.grad_attrs + (size_t)v * a.C + c, g);
+            if (c < a.C) {
+                const size_t at = (size_t)v * a.C + c;
+                if (a.det) {
+                    if (vt.g[4 + c][i] != V(0)) det_add(a, a.gfx + n1 + at, (double)vt.g[4 + c][i], shift);
+                } else {
+                    const float g = (float)vt.g[4 + c][i];
+                    if (g != 0.0f) unsafeAtomicAdd(a.grad_attrs + at, g);
+                }
+            }
             vt.g[4 + c][i] = V(0);
         }
         vt.key[i] = -1;
@@ -2201,8 +2363,6 @@ __global__ void k_kf_to_vertex(const Inst *__restrict__ tab, int n)
 
 // ---------------------------------------------------------------- launches
 
-static inline int64_t grid_for(int64_t n, int b) { return (n + b - 1) / b; }
-
 // Waves a persistent kernel keeps resident on the current device: its
 // occupancy (registers, LDS) times the compute units.
 template <class K>
@@ -2249,6 +2409,8 @@ static Inst make_inst(const Plan &p, const Io &io, char *base, const Grids &star
     a.tasks = (decltype(a.tasks))(base + p.o_tasks);
     a.gkf = (decltype(a.gkf))(base + p.o_gkf);
     a.fgw = (decltype(a.fgw))(base + p.o_fgw);
+    a.gfx = p.det ? (decltype(a.gfx))(base + p.o_gfx) : nullptr;
+    a.det = p.det ? 1 : 0;
     a.V = p.V;
     a.F = p.F;
     a.C = p.C;
@@ -2294,6 +2456,8 @@ static Inst make_inst(const Plan &p, const Io &io, char *base, const Grids &star
     a.b_res = (int)start.res;
     a.b_bwdinit = (int)start.bwdinit;
     a.b_vtx = (int)start.vtx;
+    a.b_sort = (int)start.sort;
+    a.b_detp = (int)start.detp;
     return a;
 }
 
@@ -2310,18 +2474,21 @@ static const Inst *write_table(const Batch &bt, const std::vector<Io> &io, void 
     for (int i = 0; i < bt.n; ++i) {
         const Plan &p = bt.plans[i];
         c.v[c.count++] = make_inst(p, io[i], w + bt.base[i], start);
-        start.init += grid_for(p.ncounts, 256);
-        start.proj += grid_for((int64_t)(p.S + 1) * p.V + p.F, 256);
-        start.bin += (int64_t)p.NC * p.nfb;
-        start.scan1 += p.nblocks_scan;
-        start.scan3 += grid_for(p.ncounts, 256);
-        start.tscan1 += p.nblocks_tscan;
-        start.tscan3 += grid_for(p.ntct, 256);
-        start.fg += p.ntct;
-        start.fgb += (int64_t)p.S * ((p.CPS + p.fgg - 1) / p.fgg) * p.ntiles;
-        start.res += p.ntiles;
-        start.bwdinit += grid_for((int64_t)(p.S + 1) * p.V * 2 + (int64_t)p.V * p.C, 256);
-        start.vtx += grid_for(p.V, 256);
+        const Grids q = plan_grids(p);
+        start.init += q.init;
+        start.proj += q.proj;
+        start.bin += q.bin;
+        start.scan1 += q.scan1;
+        start.scan3 += q.scan3;
+        start.tscan1 += q.tscan1;
+        start.tscan3 += q.tscan3;
+        start.fg += q.fg;
+        start.fgb += q.fgb;
+        start.res += q.res;
+        start.bwdinit += q.bwdinit;
+        start.vtx += q.vtx;
+        start.sort += q.sort;
+        start.detp += q.detp;
         if (c.count == kTabChunk || i == bt.n - 1) {
             hipLaunchKernelGGL(k_set_table, dim3(c.count), dim3(64), 0, st, c, tab);
             c.first = i + 1;
@@ -2342,6 +2509,7 @@ static void forward_T(const Batch &bt, const Inst *tab, void *ws, hipStream_t st
     hipLaunchKernelGGL(k_scan2, dim3((unsigned)n), dim3(kScanThreads), 0, st, tab, 0);
     hipLaunchKernelGGL(k_scan3, dim3((unsigned)g.scan3), dim3(256), 0, st, tab, n, 0);
     hipLaunchKernelGGL(k_bin<T>, dim3((unsigned)g.bin), dim3(kBinThreads), 0, st, tab, n, 1);
+    if (bt.det) hipLaunchKernelGGL(k_sort_lists, dim3((unsigned)g.sort), dim3(kSortThreads), 0, st, tab, n);
     mark(pe, 2, st);
     hipLaunchKernelGGL((k_fg<T, SOLVER>), dim3((unsigned)g.fg), dim3(kWave), 0, st, tab, n);
     hipLaunchKernelGGL(k_scan1, dim3((unsigned)g.tscan1), dim3(kScanThreads), 0, st, tab, n, 1);
@@ -2434,6 +2602,7 @@ hipError_t launch_backward(const Batch &bt, const std::vector<Io> &io, void *ws,
     mark(pe, 0, st);
     const Inst *tab = write_table(bt, io, ws, st);
     hipLaunchKernelGGL(k_bwd_init, dim3((unsigned)bt.g.bwdinit), dim3(256), 0, st, tab, n);
+    if (bt.det) hipLaunchKernelGGL(k_det_prep, dim3((unsigned)bt.g.detp), dim3(256), 0, st, tab, n);
     const bool fast = bt.solver == RB_SOLVER_FAST;
     switch (bt.T) {
     case 1: fast ? backward_T<1, RB_SOLVER_FAST>(bt, tab, ws, st, pe) : backward_T<1, RB_SOLVER_RECOMPUTE>(bt, tab, ws, st, pe); break;
@@ -2443,6 +2612,7 @@ hipError_t launch_backward(const Batch &bt, const std::vector<Io> &io, void *ws,
     default: fast ? backward_T<8, RB_SOLVER_FAST>(bt, tab, ws, st, pe) : backward_T<8, RB_SOLVER_RECOMPUTE>(bt, tab, ws, st, pe); break;
     }
     mark(pe, 2, st);
+    if (bt.det) hipLaunchKernelGGL(k_det_finish, dim3((unsigned)bt.g.bwdinit), dim3(256), 0, st, tab, n);
     hipLaunchKernelGGL(k_kf_to_vertex, dim3((unsigned)bt.g.vtx), dim3(256), 0, st, tab, n);
     mark(pe, 3, st);
     return hipGetLastError();

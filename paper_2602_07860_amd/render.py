@@ -26,6 +26,7 @@ class RenderOptions:
     chunk_len: int = 4           # sub-frames per work chunk (1, 2, 4, 8)
     slice_len: int = 0           # background-list entries per task (0: automatic)
     check: bool = True           # read the device header after each forward (one sync)
+    deterministic: bool = False  # bitwise-reproducible results (RB_FLAG_DETERMINISTIC; slower)
 
     def c_struct(self, capacity: int) -> B.rb_options:
         o = B.rb_options()
@@ -33,7 +34,7 @@ class RenderOptions:
         o.delta = float(self.delta)
         o.eps_cutoff = float(self.eps_cutoff)
         o.solver = {"fast": B.RB_SOLVER_FAST, "recompute": B.RB_SOLVER_RECOMPUTE}[self.solver]
-        o.flags = 0
+        o.flags = B.RB_FLAG_DETERMINISTIC if self.deterministic else 0
         o.chunk_len = int(self.chunk_len)
         o.slice_len = int(self.slice_len)
         o.list_capacity = int(capacity)

@@ -89,6 +89,21 @@ def test_workspace_size_and_validate_ok(L):
     assert B.rb_workspace_size(V, F, C, mo, cam, op2) > n
 
 
+def test_deterministic_flag_adds_the_fixed_point_sums(L):
+    # RB_FLAG_DETERMINISTIC keeps [S+1][V][2] keyframe and [V][C] attribute
+    # gradient sums as 64-bit integers in the workspace; its background tasks
+    # are whole lists, so the task array holds capacity / slice_len fewer
+    V, F, C, mo, cam, op = _args()
+    op.list_capacity, op.slice_len = 1 << 20, 64
+    n = B.rb_workspace_size(V, F, C, mo, cam, op)
+    op.flags = B.RB_FLAG_DETERMINISTIC
+    nd = B.rb_workspace_size(V, F, C, mo, cam, op)
+    need = ((mo.num_segments + 1) * V * 2 + V * C) * 8 - (1 << 20) // 64 * 8
+    assert abs((nd - n) - need) < 512
+    assert B.rb_validate(V, F, C, mo, cam, op, nd) == B.RB_OK
+    assert B.rb_validate(V, F, C, mo, cam, op, nd - 1) == B.RB_EWORKSPACE
+
+
 @pytest.mark.parametrize("mutate,code", [
     (lambda a: a.update(V=0), B.RB_EINVAL),
     (lambda a: a.update(F=-1), B.RB_EINVAL),
@@ -104,6 +119,8 @@ def test_workspace_size_and_validate_ok(L):
     (lambda a: setattr(a["op"], "chunk_len", 3), B.RB_EUNSUPPORTED),
     (lambda a: setattr(a["op"], "chunk_len", 16), B.RB_EUNSUPPORTED),
     (lambda a: setattr(a["op"], "list_capacity", -5), B.RB_EINVAL),
+    (lambda a: setattr(a["op"], "flags", 2), B.RB_EINVAL),
+    (lambda a: setattr(a["op"], "flags", -1), B.RB_EINVAL),
     (lambda a: setattr(a["cam"], "width", 0), B.RB_EINVAL),
     (lambda a: setattr(a["cam"], "tan_half_fov", -1.0), B.RB_EINVAL),
     (lambda a: a["cam"].view.__setitem__(3, float("inf")), B.RB_EINVAL),
