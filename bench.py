@@ -129,7 +129,8 @@ def run_single(start, tg, args, torch, B, R, adam=False):
 
     def opts(solver, check=True):
         return R.RenderOptions(start.num_subframes, solver=solver, chunk_len=args.chunk_len,
-                               slice_len=args.slice_len, check=check, deterministic=args.deterministic)
+                               slice_len=args.slice_len, check=check, deterministic=args.deterministic,
+                               tile_w=args.tile_w)
 
     target, _ = R.render_forward(tt.verts, tt.faces, tt.attrs, tt.model, tt.camera, opts("fast"))
     res = {}
@@ -187,9 +188,9 @@ def run_batch(scenes, targets_sc, args, torch, B, R):
     del tr
     res = {}
     for solver in ("fast", "recompute"):
-        T, SL = BT.autotune(sts, targets, solver=solver, log=log)
-        log(f"autotuned {solver}: chunk_len {T} slice_len {SL}")
-        r = BT.BatchRenderer(sts, R.RenderOptions(0, solver=solver, chunk_len=T, slice_len=SL))
+        T, SL, TW = BT.autotune(sts, targets, solver=solver, log=log)
+        log(f"autotuned {solver}: chunk_len {T} slice_len {SL} tile {TW}x{64 // TW}")
+        r = BT.BatchRenderer(sts, R.RenderOptions(0, solver=solver, chunk_len=T, slice_len=SL, tile_w=TW))
         r.fit()
         step = BT.L2Step(r, targets)
         step.capture()
@@ -202,7 +203,7 @@ def run_batch(scenes, targets_sc, args, torch, B, R):
             raise RuntimeError("device header reports errors")
         if not all(bool(torch.isfinite(x).all()) for x in r.images + r.grad_verts + r.grad_attrs):
             raise RuntimeError("non-finite output")
-        res[solver] = dict(ms=ms, km=km, chunk_len=T, slice_len=SL)
+        res[solver] = dict(ms=ms, km=km, chunk_len=T, slice_len=SL, tile_w=TW)
         del step, r
     return res
 
@@ -346,6 +347,8 @@ def main():
     ap.add_argument("--slice-len", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--tile-w", type=int, default=0, choices=(0, 4, 8, 16),
+                    help="tile width in pixels for the large and medium workloads (0: 8)")
     ap.add_argument("--deterministic", action="store_true",
                     help="render with RB_FLAG_DETERMINISTIC (large and medium workloads)")
     args = ap.parse_args()
@@ -403,7 +406,8 @@ def main():
         res = run_batch(scenes, targets, args, torch, B, R)
         config = {"workload": "batch32-mixed fwd+bwd L2, one graph replay", "instances": len(scenes),
                   "faces_total": int(sum(len(s.faces) for s in scenes)),
-                  "chunk_len": res["fast"]["chunk_len"], "slice_len": res["fast"]["slice_len"], "solver": "fast"}
+                  "chunk_len": res["fast"]["chunk_len"], "slice_len": res["fast"]["slice_len"],
+                  "tile": f"{res['fast']['tile_w']}x{64 // res['fast']['tile_w']}", "solver": "fast"}
     else:
         if args.workload == "medium":
             sc = wl.make_workload(wl.MEDIUM)
@@ -423,7 +427,7 @@ def main():
                   "vertices": int(len(sc.verts)),
                   "faces": int(len(sc.faces)), "resolution": f"{sc.width}x{sc.height}",
                   "subframes": sc.num_subframes, "segments": sc.num_segments, "solver": "fast",
-                  "chunk_len": args.chunk_len}
+                  "chunk_len": args.chunk_len, "tile": f"{args.tile_w or 8}x{64 // (args.tile_w or 8)}"}
         if args.deterministic:
             config["deterministic"] = True
         if adam:

@@ -111,6 +111,9 @@ typedef struct {
                                 a segment is split into equal chunks         */
     int32_t slice_len;       /* background-list entries per task; 0 = auto (64) */
     int64_t list_capacity;   /* bin-list entries (foreground + background); 0 = auto */
+    int32_t tile_w;          /* tile width in pixels: 4, 8 or 16 (height 64 / tile_w,
+                                one 64-lane wave per tile); 0 = 8              */
+    int32_t reserved;        /* 0                                               */
 } rb_options;
 
 /* Device-side findings of the last call on a workspace (rb_read_header). */

@@ -2,8 +2,8 @@
 resolution through one sequence of launches of the HIP library (every kernel
 covers all instances; the background passes are persistent kernels over the
 tasks of all instances), optionally captured once in a hipGraph and replayed,
-with the chunk length and the background slice length chosen by a small
-autotuner that times the candidates on the batch itself.
+with the chunk length, the background slice length and the tile shape
+chosen by a small autotuner that times the candidates on the batch itself.
 
 Argument marshalling only: all rendering work runs in the library.
 """
@@ -198,7 +198,7 @@ def _load_cache(path: str) -> Dict[str, list]:
         return json.load(f)
 
 
-def _store_cache(path: str, key: str, value: Tuple[int, int]) -> None:
+def _store_cache(path: str, key: str, value: Tuple[int, ...]) -> None:
     import json
     import os
     data = _load_cache(path)
@@ -211,45 +211,53 @@ def _store_cache(path: str, key: str, value: Tuple[int, int]) -> None:
 
 
 def autotune(scenes: Sequence[SceneTensors], targets: Sequence[torch.Tensor], solver: str = "fast",
-             chunk_lens=(1, 2, 4, 8), slice_lens=(32, 64, 128, 256), reps: int = 3,
-             log=None, cache_path: Optional[str] = None) -> Tuple[int, int]:
-    """Chunk length and background slice length with the shortest fwd+bwd L2
-    step on this batch (each candidate timed with device events over `reps`
-    eager steps after one warm-up that also sizes its lists).  Results are
-    remembered per batch signature in memory and, with cache_path, per batch
-    class (batch_class) in a JSON file that later runs read instead of
-    timing."""
+             chunk_lens=(1, 2, 4, 8), slice_lens=(32, 64, 128, 256), tile_ws=(8, 16, 4), reps: int = 3,
+             log=None, cache_path: Optional[str] = None) -> Tuple[int, int, int]:
+    """Chunk length, background slice length and tile width with the shortest
+    fwd+bwd L2 step on this batch (each candidate timed with device events
+    over `reps` eager steps after one warm-up that also sizes its lists):
+    every (chunk, slice) pair on the first tile shape, then the other tile
+    shapes at the best pair.  Results are remembered per batch signature in
+    memory and, with cache_path, per batch class (batch_class) in a JSON file
+    that later runs read instead of timing."""
     key = batch_signature(scenes, solver)
     if key in _tuned:
         return _tuned[key]
     if cache_path:
         hit = _load_cache(cache_path).get(batch_class(scenes, solver))
-        if hit is not None and hit[0] in chunk_lens and hit[1] in slice_lens:
-            _tuned[key] = (int(hit[0]), int(hit[1]))
+        if hit is not None and len(hit) == 3 and hit[0] in chunk_lens and hit[1] in slice_lens and hit[2] in tile_ws:
+            _tuned[key] = (int(hit[0]), int(hit[1]), int(hit[2]))
             return _tuned[key]
-    best, best_ms = None, float("inf")
-    caps = None
-    for T in chunk_lens:
-        caps = None   # list sizes depend on the chunk length
-        for SL in slice_lens:
-            r = BatchRenderer(scenes, RenderOptions(0, solver=solver, chunk_len=T, slice_len=SL), caps)
-            r.fit()
-            caps = r.caps
-            step = L2Step(r, targets)
+
+    def time_one(T, SL, TW, caps):
+        r = BatchRenderer(scenes, RenderOptions(0, solver=solver, chunk_len=T, slice_len=SL, tile_w=TW), caps)
+        r.fit()
+        step = L2Step(r, targets)
+        step.eager()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
             step.eager()
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(reps):
-                step.eager()
-            e1.record()
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / reps
-            if log:
-                log(f"autotune T={T} SL={SL}: {ms:.3f} ms")
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        if log:
+            log(f"autotune T={T} SL={SL} tile={TW}x{64 // TW}: {ms:.3f} ms")
+        return ms, r.caps
+
+    best, best_ms = None, float("inf")
+    TW0 = tile_ws[0]
+    for T in chunk_lens:
+        caps = None   # list sizes depend on the chunk length and the tiles
+        for SL in slice_lens:
+            ms, caps = time_one(T, SL, TW0, caps)
             if ms < best_ms:
-                best, best_ms = (T, SL), ms
-            del r, step
+                best, best_ms = (T, SL, TW0), ms
+    for TW in tile_ws[1:]:
+        ms, _ = time_one(best[0], best[1], TW, None)
+        if ms < best_ms:
+            best, best_ms = (best[0], best[1], TW), ms
     _tuned[key] = best
     if cache_path:
         _store_cache(cache_path, batch_class(scenes, solver), best)

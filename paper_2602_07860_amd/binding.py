@@ -41,7 +41,8 @@ class rb_options(ctypes.Structure):
     _fields_ = [("num_subframes", ctypes.c_int32), ("delta", ctypes.c_float),
                 ("eps_cutoff", ctypes.c_float), ("solver", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("chunk_len", ctypes.c_int32),
-                ("slice_len", ctypes.c_int32), ("list_capacity", ctypes.c_int64)]
+                ("slice_len", ctypes.c_int32), ("list_capacity", ctypes.c_int64),
+                ("tile_w", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class rb_header(ctypes.Structure):

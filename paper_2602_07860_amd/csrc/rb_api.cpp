@@ -29,6 +29,8 @@ static rb_status make_plan(int32_t V, int32_t F, int32_t C, const rb_motion *mot
     if (opt->solver != RB_SOLVER_FAST && opt->solver != RB_SOLVER_RECOMPUTE) return RB_EINVAL;
     if (opt->chunk_len < 0 || opt->slice_len < 0 || opt->list_capacity < 0) return RB_EINVAL;
     if (opt->flags & ~RB_FLAG_DETERMINISTIC) return RB_EINVAL;
+    if (opt->tile_w < 0 || opt->reserved != 0) return RB_EINVAL;
+    if (opt->tile_w != 0 && opt->tile_w != 4 && opt->tile_w != 8 && opt->tile_w != 16) return RB_EUNSUPPORTED;
     if (C > RB_MAX_CHANNELS) return RB_EUNSUPPORTED;
     if (F >= RB_MAX_FACES) return RB_EUNSUPPORTED;
     const int T = opt->chunk_len == 0 ? 4 : opt->chunk_len;
@@ -51,8 +53,10 @@ static rb_status make_plan(int32_t V, int32_t F, int32_t C, const rb_motion *mot
     p.halo = (float)(std::sqrt(dmax) * (1.0 + 1e-6));
     std::memcpy(p.view, cam->view, sizeof(p.view));
     p.solver = opt->solver;
-    p.tiles_x = (p.W + kTile - 1) / kTile;
-    p.tiles_y = (p.H + kTile - 1) / kTile;
+    p.tw = opt->tile_w ? opt->tile_w : kTileWDefault;
+    p.th = kWave / p.tw;
+    p.tiles_x = (p.W + p.tw - 1) / p.tw;
+    p.tiles_y = (p.H + p.th - 1) / p.th;
     p.ntiles = p.tiles_x * p.tiles_y;
     int nmax = 0;
     for (int s = 0; s < S; ++s) {
@@ -151,6 +155,7 @@ static rb_status make_batch(const std::vector<Plan> &plans, Batch &bt)
     bt.wide = true;
     for (const Plan &p : plans) bt.wide = bt.wide && p.wide;
     bt.det = plans[0].det;
+    bt.tw = plans[0].tw;
     bt.plans = plans;
     bt.base.resize(bt.n);
     Grids g{};

@@ -12,8 +12,10 @@
 
 namespace rb {
 
-constexpr int kTile = 8;                  // tile edge in pixels: one 64-lane wave per tile
+// A tile is tw x th = 64 pixels, one 64-lane wave (lane = th-row * tw + column):
+// 8 x 8 by default, 16 x 4 or 4 x 16 on request
 constexpr int kWave = 64;
+constexpr int kTileWDefault = 8;
 constexpr float kTauDet = 1e-10f;         // |det F(tau)| at or below this: face skipped
 // background adjoint: a term whose weight prod_{m != j}(1 - A_m) A_j is below
 // this is left out, and so is a whole (pixel, sub-frame) where the bound
@@ -116,6 +118,8 @@ struct Inst {
     int64_t RB_G *gfx;        // deterministic mode: [S+1][V][2] then [V][C] gradient sums in fixed point
     // sizes
     int V, F, C, S, K, W, H, tiles_x, tiles_y, ntiles;
+    int tw, th, lw, lh;  // tile width and height in pixels and their log2
+    uint64_t rep;        // bit 0 of every tile row: sum over rows r of 2^(tw r)
     int CPS, NC, SL, NS, nfb;
     int seq_bg;          // consecutive items per lane in the background adjoint
     int fgg;             // chunks per wave (at most) in the foreground adjoint
@@ -138,6 +142,7 @@ struct Plan {
     float view[12];
     int solver;
     int tiles_x, tiles_y, ntiles;
+    int tw, th;     // tile shape (pixels)
     int T;          // chunk length (template)
     int CPS;        // chunks per segment
     int NC;         // chunks = S * CPS
@@ -192,6 +197,7 @@ inline Grids plan_grids(const Plan &p)
 struct Batch {
     int n, T, solver;
     bool det;       // RB_FLAG_DETERMINISTIC (batch-wide: one options record)
+    int tw;         // tile width (batch-wide)
     bool wide;      // every instance has a wide halo: background kernels built for long item runs
     std::vector<Plan> plans;
     std::vector<size_t> base;

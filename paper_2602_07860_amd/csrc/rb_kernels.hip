@@ -258,6 +258,7 @@ __device__ __forceinline__ void pixel_range(float lo, float hi, float scale, flo
 
 // Tile ranges of one face at one sub-frame: foreground (exact box) and
 // background (box grown by halo).  Empty ranges come back with lo > hi.
+template <int TW>
 __device__ __forceinline__ void face_tiles(const float x[3], const float y[3], const Inst &a, float grow,
                                            int &tx0, int &tx1, int &ty0, int &ty1)
 {
@@ -276,10 +277,11 @@ __device__ __forceinline__ void face_tiles(const float x[3], const float y[3], c
         tx1 = ty1 = 0;
         return;
     }
-    tx0 = c0 / kTile;
-    tx1 = c1 / kTile;
-    ty0 = r0 / kTile;
-    ty1 = r1 / kTile;
+    constexpr int TH = kWave / TW;
+    tx0 = c0 / TW;
+    tx1 = c1 / TW;
+    ty0 = r0 / TH;
+    ty1 = r1 / TH;
 }
 
 // Binning.  A block takes 256 consecutive faces of one chunk; meshes list
@@ -298,7 +300,7 @@ struct FaceTiles {
     int ux0, ux1, uy0, uy1;                 // union of the background rects over the chunk
 };
 
-template <int T>
+template <int T, int TW>
 __device__ __forceinline__ bool face_chunk_tiles(const Inst &a, int f, const Chunk &ch, int ftx0[T], int ftx1[T],
                                                  int fty0[T], int fty1[T], int btx0[T], int btx1[T], int bty0[T],
                                                  int bty1[T], FaceTiles &u)
@@ -331,8 +333,8 @@ __device__ __forceinline__ bool face_chunk_tiles(const Inst &a, int f, const Chu
                 x[q] = fmaf(tau, bx[q], ax[q]);
                 y[q] = fmaf(tau, by[q], ay[q]);
             }
-            face_tiles(x, y, a, 0.0f, ftx0[j], ftx1[j], fty0[j], fty1[j]);
-            face_tiles(x, y, a, a.halo, btx0[j], btx1[j], bty0[j], bty1[j]);
+            face_tiles<TW>(x, y, a, 0.0f, ftx0[j], ftx1[j], fty0[j], fty1[j]);
+            face_tiles<TW>(x, y, a, a.halo, btx0[j], btx1[j], bty0[j], bty1[j]);
             if (btx0[j] <= btx1[j]) {
                 u.ux0 = min(u.ux0, btx0[j]);
                 u.ux1 = max(u.ux1, btx1[j]);
@@ -344,7 +346,8 @@ __device__ __forceinline__ bool face_chunk_tiles(const Inst &a, int f, const Chu
     return u.ux0 <= u.ux1;
 }
 
-template <int T>
+// TW: tile width (the tile shape is a batch-wide option)
+template <int T, int TW>
 __global__ __launch_bounds__(kBinThreads) void k_bin(const Inst *__restrict__ tab, int n, int pass)
 {
     __shared__ int lcnt[kBinWin];
@@ -359,7 +362,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const Inst *__restrict__ ta
     if (ch.n <= 0) return;   // block-uniform
     int ftx0[T], ftx1[T], fty0[T], fty1[T], btx0[T], btx1[T], bty0[T], bty1[T];
     FaceTiles u;
-    const bool has = f < a.F && face_chunk_tiles<T>(a, f, ch, ftx0, ftx1, fty0, fty1, btx0, btx1, bty0, bty1, u);
+    const bool has = f < a.F && face_chunk_tiles<T, TW>(a, f, ch, ftx0, ftx1, fty0, fty1, btx0, btx1, bty0, bty1, u);
     if (threadIdx.x == 0) {
         win[0] = INT_MAX;
         win[1] = INT_MIN;
@@ -976,10 +979,28 @@ __device__ __forceinline__ float log2_one_minus(float A, float om)
     return __log2f(om);
 }
 
-// pixel p of a tile (bit 8 * row + column) relative to the tile anchor, which
+// pixel p of a tile (bit tw * row + column) relative to the tile anchor, which
 // lies between the 4 centre pixels; exact for W, H powers of 2
-__device__ __forceinline__ float pix_du(int p, float inv_w) { return (float)(2 * (p & 7) - 7) * inv_w; }
-__device__ __forceinline__ float pix_dv(int p, float inv_h) { return (float)(7 - 2 * (p >> 3)) * inv_h; }
+// (TWS: the tile width when known at compile time, 0 when read from a)
+template <int TWS = 0>
+__device__ __forceinline__ float pix_du(const Inst &a, int p)
+{
+    const int tw = TWS ? TWS : a.tw;
+    return (float)(2 * (p & (tw - 1)) - (tw - 1)) * a.inv_w;
+}
+template <int TWS = 0>
+__device__ __forceinline__ float pix_dv(const Inst &a, int p)
+{
+    const int th = TWS ? kWave / TWS : a.th, lw = TWS ? __builtin_ctz(TWS) : a.lw;
+    return (float)((th - 1) - 2 * (p >> lw)) * a.inv_h;
+}
+
+// image pixel of lane `lane` in tile (tx, ty)
+__device__ __forceinline__ void tile_pixel(const Inst &a, int tx, int ty, int lane, int &px, int &py)
+{
+    px = (tx << a.lw) + (lane & (a.tw - 1));
+    py = (ty << a.lh) + (lane >> a.lw);
+}
 
 struct TileCtx {
     int c, tile, px, py;
@@ -995,13 +1016,12 @@ __device__ __forceinline__ void tile_ctx(const Inst &a, int ct, TileCtx &g)
     g.c = ct / a.ntiles;
     g.tile = ct - g.c * a.ntiles;
     const int tx = g.tile % a.tiles_x, ty = g.tile / a.tiles_x;
-    g.px = tx * kTile + (lane & 7);
-    g.py = ty * kTile + (lane >> 3);
+    tile_pixel(a, tx, ty, lane, g.px, g.py);
     g.inimg = g.px < a.W && g.py < a.H;
-    g.ua = (double)(16 * tx + 8 - a.W) / (double)a.W;
-    g.va = (double)(a.H - 16 * ty - 8) / (double)a.H;
-    g.du = pix_du(lane, a.inv_w);
-    g.dv = pix_dv(lane, a.inv_h);
+    g.ua = (double)(2 * a.tw * tx + a.tw - a.W) / (double)a.W;
+    g.va = (double)(a.H - 2 * a.th * ty - a.th) / (double)a.H;
+    g.du = pix_du(a, lane);
+    g.dv = pix_dv(a, lane);
     g.ck = chunk_info(g.c, a.K, a.S, a.CPS);
 }
 
@@ -1050,43 +1070,94 @@ __device__ __forceinline__ size_t pix_index(const Inst &a, int tile, int k, int 
 // ------------------------------------------------------------ item machinery
 
 // mask of the tile pixels whose centres lie in [x0 - g, x1 + g] x [y0 - g, y1 + g]
-// (anchor-local; bit = 8 * row + column), with a margin of 0.05 pixel so that
+// (anchor-local; bit = TW * row + column), with a margin of 0.05 pixel so that
 // the box never cuts off a pixel the exact test would accept
-__device__ __forceinline__ uint64_t rect_mask(float x0, float x1, float y0, float y1, float g, float W, float H)
+template <int TW>
+__device__ __forceinline__ uint64_t rect_mask_t(float x0, float x1, float y0, float y1, float g, float W, float H)
 {
-    // column c has centre du = (2c - 7)/W, row r has dv = (7 - 2r)/H
-    const float ca = fmaf(x0 - g, W, 7.0f) * 0.5f - 0.05f, cb = fmaf(x1 + g, W, 7.0f) * 0.5f + 0.05f;
-    const float ra = (7.0f - (y1 + g) * H) * 0.5f - 0.05f, rb = (7.0f - (y0 - g) * H) * 0.5f + 0.05f;
-    const int c0 = max((int)ceilf(fmaxf(ca, -1.0f)), 0), c1 = min((int)floorf(fminf(cb, 8.0f)), 7);
-    const int r0 = max((int)ceilf(fmaxf(ra, -1.0f)), 0), r1 = min((int)floorf(fminf(rb, 8.0f)), 7);
+    constexpr int TH = kWave / TW;
+    constexpr uint64_t REP = ~0ull / ((1ull << TW) - 1ull);   // bit 0 of every row
+    // column c has centre du = (2c - (TW-1))/W, row r has dv = ((TH-1) - 2r)/H
+    const float ca = fmaf(x0 - g, W, (float)(TW - 1)) * 0.5f - 0.05f, cb = fmaf(x1 + g, W, (float)(TW - 1)) * 0.5f + 0.05f;
+    const float ra = ((float)(TH - 1) - (y1 + g) * H) * 0.5f - 0.05f, rb = ((float)(TH - 1) - (y0 - g) * H) * 0.5f + 0.05f;
+    const int c0 = max((int)ceilf(fmaxf(ca, -1.0f)), 0), c1 = min((int)floorf(fminf(cb, (float)TW)), TW - 1);
+    const int r0 = max((int)ceilf(fmaxf(ra, -1.0f)), 0), r1 = min((int)floorf(fminf(rb, (float)TH)), TH - 1);
     if (c0 > c1 || r0 > r1) return 0ull;
-    const uint64_t row = (uint64_t)((0xffu >> (7 - c1 + c0)) << c0);
-    const uint64_t hi = r1 == 7 ? ~0ull : ((1ull << (8 * (r1 + 1))) - 1ull);
-    const uint64_t lo = (1ull << (8 * r0)) - 1ull;
-    return (row * 0x0101010101010101ull) & hi & ~lo;
+    const uint64_t row = (uint64_t)(((2u << (c1 - c0)) - 1u) << c0);
+    const uint64_t hi = r1 == TH - 1 ? ~0ull : ((1ull << (TW * (r1 + 1))) - 1ull);
+    const uint64_t lo = (1ull << (TW * r0)) - 1ull;
+    return (row * REP) & hi & ~lo;
 }
 
 // mask of the tile pixels whose centres lie within distance g of the box
 // [x0, x1] x [y0, y1] (anchor-local), with a margin of 0.05 pixel: a superset
 // of the pixels within distance g of a triangle inside the box, i.e. of the
 // pixels the background term can reach (the box grown by g, corners rounded)
-__device__ __forceinline__ uint64_t disc_mask(float x0, float x1, float y0, float y1, float g, float W, float H)
+template <int TW>
+__device__ __forceinline__ uint64_t disc_mask_t(float x0, float x1, float y0, float y1, float g, float W, float H)
 {
+    constexpr int TH = kWave / TW;
     const float ih = rcp(H), my = 0.1f * ih, g2 = g * g;
     uint64_t m = 0;
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        // row r has centre dv = (7 - 2r)/H
-        const float v = (float)(7 - 2 * r) * ih;
+    for (int r = 0; r < TH; ++r) {
+        // row r has centre dv = ((TH-1) - 2r)/H
+        const float v = (float)(TH - 1 - 2 * r) * ih;
         const float dy = fmaxf(fmaxf(y0 - v, v - y1) - my, 0.0f);
         const float h2 = fmaf(-dy, dy, g2);
         const float hx = sqrtf(fmaxf(h2, 0.0f));
-        const float ca = fmaf(x0 - hx, W, 7.0f) * 0.5f - 0.05f, cb = fmaf(x1 + hx, W, 7.0f) * 0.5f + 0.05f;
-        const int c0 = max((int)ceilf(fmaxf(ca, -1.0f)), 0), c1 = min((int)floorf(fminf(cb, 8.0f)), 7);
-        const uint32_t row = (h2 >= 0.0f && c0 <= c1) ? ((0xffu >> (7 - c1 + c0)) << c0) : 0u;
-        m |= (uint64_t)row << (8 * r);
+        const float ca = fmaf(x0 - hx, W, (float)(TW - 1)) * 0.5f - 0.05f, cb = fmaf(x1 + hx, W, (float)(TW - 1)) * 0.5f + 0.05f;
+        const int c0 = max((int)ceilf(fmaxf(ca, -1.0f)), 0), c1 = min((int)floorf(fminf(cb, (float)TW)), TW - 1);
+        const uint32_t row = (h2 >= 0.0f && c0 <= c1) ? (((2u << (c1 - c0)) - 1u) << c0) : 0u;
+        m |= (uint64_t)row << (TW * r);
     }
     return m;
+}
+
+// the same for 16 x 4 and 4 x 16 tiles (shape in run-time values): the
+// rectangle in closed form, the rounded box row by row
+__device__ __forceinline__ uint64_t rect_mask_any(const Inst &a, float x0, float x1, float y0, float y1, float g)
+{
+    const int tw = a.tw, th = a.th;
+    const float W = (float)a.W, H = (float)a.H, cw = (float)(tw - 1), ch = (float)(th - 1);
+    const float ca = fmaf(x0 - g, W, cw) * 0.5f - 0.05f, cb = fmaf(x1 + g, W, cw) * 0.5f + 0.05f;
+    const float ra = (ch - (y1 + g) * H) * 0.5f - 0.05f, rb = (ch - (y0 - g) * H) * 0.5f + 0.05f;
+    const int c0 = max((int)ceilf(fmaxf(ca, -1.0f)), 0), c1 = min((int)floorf(fminf(cb, (float)tw)), tw - 1);
+    const int r0 = max((int)ceilf(fmaxf(ra, -1.0f)), 0), r1 = min((int)floorf(fminf(rb, (float)th)), th - 1);
+    if (c0 > c1 || r0 > r1) return 0ull;
+    const uint64_t row = (uint64_t)(((2u << (c1 - c0)) - 1u) << c0);
+    const uint64_t hi = r1 == th - 1 ? ~0ull : ((1ull << (tw * (r1 + 1))) - 1ull);
+    const uint64_t lo = (1ull << (tw * r0)) - 1ull;
+    return (row * a.rep) & hi & ~lo;
+}
+
+__device__ __forceinline__ uint64_t disc_mask_any(const Inst &a, float x0, float x1, float y0, float y1, float g)
+{
+    const int tw = a.tw, th = a.th;
+    const float W = (float)a.W, cw = (float)(tw - 1), ih = rcp((float)a.H), my = 0.1f * ih, g2 = g * g;
+    uint64_t m = 0;
+    for (int r = 0; r < th; ++r) {
+        const float v = (float)(th - 1 - 2 * r) * ih;   // row r's centre
+        const float dy = fmaxf(fmaxf(y0 - v, v - y1) - my, 0.0f);
+        const float h2 = fmaf(-dy, dy, g2);
+        if (h2 < 0.0f) continue;
+        const float hx = sqrtf(h2);
+        const float ca = fmaf(x0 - hx, W, cw) * 0.5f - 0.05f, cb = fmaf(x1 + hx, W, cw) * 0.5f + 0.05f;
+        const int c0 = max((int)ceilf(fmaxf(ca, -1.0f)), 0), c1 = min((int)floorf(fminf(cb, (float)tw)), tw - 1);
+        if (c0 <= c1) m |= (uint64_t)(((2u << (c1 - c0)) - 1u) << c0) << (tw * r);
+    }
+    return m;
+}
+
+// the masks for the instance's tile shape (a wave-uniform choice; TWS == 8:
+// the kernel is built for 8 x 8 tiles)
+template <int TWS = 0>
+__device__ __forceinline__ uint64_t tile_mask(const Inst &a, bool disc, float x0, float x1, float y0, float y1, float g)
+{
+    const float W = (float)a.W, H = (float)a.H;
+    const bool t8 = TWS == 8 || a.tw == 8;
+    if (disc) return t8 ? disc_mask_t<8>(x0, x1, y0, y1, g, W, H) : disc_mask_any(a, x0, x1, y0, y1, g);
+    return t8 ? rect_mask_t<8>(x0, x1, y0, y1, g, W, H) : rect_mask_any(a, x0, x1, y0, y1, g);
 }
 
 // position of the r-th set bit (r < popcount(m))
@@ -1193,7 +1264,7 @@ __device__ __forceinline__ Pref prefetch(const Inst &a, int64_t first, int nb)
 // sub-frames outside the chunk).  Returns the number of items; cnt / pre are
 // the lane's entry's item count and first item.  Optionally also stages the
 // vertex attributes (at) and vertex indices (vids).
-template <int T>
+template <int T, int TWS = 0>
 __device__ __forceinline__ int stage_items(const Inst &a, ItemShared<T> &sh, const Pref &pf, int nb, int s,
                                            const TileCtx &g, float tc, const float tau[T], int kind, float grow,
                                            const uint64_t allow[T], float (*at)[NB], int (*vids)[3], int &cnt,
@@ -1223,8 +1294,7 @@ __device__ __forceinline__ int stage_items(const Inst &a, ItemShared<T> &sh, con
                     y0 = fminf(y0, yt);
                     y1 = fmaxf(y1, yt);
                 }
-                mj = (kind == kRecBg ? disc_mask(x0, x1, y0, y1, grow, (float)a.W, (float)a.H)
-                                     : rect_mask(x0, x1, y0, y1, grow, (float)a.W, (float)a.H)) &
+                mj = tile_mask<TWS>(a, kind == kRecBg, x0, x1, y0, y1, grow) &
                      allow[j];
             }
             sh.m[j][lane] = mj;
@@ -1346,12 +1416,12 @@ struct FgShared {
 };
 
 // foreground item: coverage (eqs 1-3 / 8) and depth test (eq 9) per sub-frame
-template <int T, int SOLVER>
+template <int T, int SOLVER, int TWS>
 __device__ __forceinline__ void fg_item(const Inst &a, FgShared<T> &sh, int e, int p, const float tau[T],
                                         float tc)
 {
     const LdsRec r = lds_rec(sh.it, e);
-    const float du = pix_du(p, a.inv_w), dv = pix_dv(p, a.inv_h);
+    const float du = pix_du<TWS>(a, p), dv = pix_dv<TWS>(a, p);
     Bary<SOLVER> bc;
     bc.setup(r, tc, du, dv);
     const unsigned long long f = (uint32_t)__float_as_int(r.at(R_F));
@@ -1402,7 +1472,9 @@ __device__ __forceinline__ void shade_gather(const Inst &a, int f, int s, const 
                   tc, tau, g, rgb);
 }
 
-template <int T, int SOLVER>
+// TWS: 8 for a batch of 8 x 8 tiles (constant pixel offsets and masks), 0
+// for the other tile shapes
+template <int T, int SOLVER, int TWS>
 __global__ __launch_bounds__(64) void k_fg(const Inst *__restrict__ tab, int n)
 {
     __shared__ FgShared<T> sh;
@@ -1437,9 +1509,9 @@ __global__ __launch_bounds__(64) void k_fg(const Inst *__restrict__ tab, int n)
     for (int base = 0; base < n_e; base += NB) {
         const int nb = min(NB, n_e - base);
         int cnt, pre;
-        const int total = stage_items<T>(a, sh.it, prefetch(a, beg + base, nb), nb, ck.s, g, tc, tau, kRecFg, 0.0f,
+        const int total = stage_items<T, TWS>(a, sh.it, prefetch(a, beg + base, nb), nb, ck.s, g, tc, tau, kRecFg, 0.0f,
                                          allow, nullptr, nullptr, cnt, pre);
-        for_items<T>(sh.it, total, cnt, pre, [&](int e, int p) { fg_item<T, SOLVER>(a, sh, e, p, tau, tc); });
+        for_items<T>(sh.it, total, cnt, pre, [&](int e, int p) { fg_item<T, SOLVER, TWS>(a, sh, e, p, tau, tc); });
     }
     lds_sync();
     bool anyunc = false, anycov = false;
@@ -1538,7 +1610,7 @@ __device__ __forceinline__ void bg_item_fwd(const Inst &a, BgShared<T> &sh, int 
                                             float (&om_lo)[T])
 {
     const LdsRec r = lds_rec(sh.it, e);
-    const float du = pix_du(p, a.inv_w), dv = pix_dv(p, a.inv_h);
+    const float du = pix_du(a, p), dv = pix_dv(a, p);
     Bary<SOLVER> bc;
     bc.setup(r, tc, du, dv);
     KEdges ke;
@@ -1702,7 +1774,8 @@ __global__ __launch_bounds__(64 * kResWaves) void k_resolve(const Inst *__restri
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int tile = blockIdx.x - a.b_res;
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
-    const int px = tx * kTile + (lane & 7), py = ty * kTile + (lane >> 3);
+    int px, py;
+    tile_pixel(a, tx, ty, lane, px, py);
     const bool in = px < a.W && py < a.H;
     // wave w sums sub-frames w, w + kResWaves, ... in double
     double acc[NCH + 1];
@@ -1886,7 +1959,7 @@ __device__ __forceinline__ void fg_item_bwd(const Inst &a, FgBwdShared<T> &sh, i
                                             float tc, float (&acc)[12 + 3 * NCH])
 {
     const LdsRec r = lds_rec(sh.it, e);
-    const float du = pix_du(p, a.inv_w), dv = pix_dv(p, a.inv_h);
+    const float du = pix_du(a, p), dv = pix_dv(a, p);
     float gI[NCH], gw[3], ws[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) gI[ch] = sh.gI[ch][p];
@@ -1958,7 +2031,8 @@ __global__ __launch_bounds__(64) void k_fg_bwd(const Inst *__restrict__ tab, int
     bool gcol = false, gstored = false;
     {
         const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
-        const int px = tx * kTile + (lane & 7), py = ty * kTile + (lane >> 3);
+        int px, py;
+        tile_pixel(a, tx, ty, lane, px, py);
         const bool inimg = px < a.W && py < a.H;
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch)
@@ -2118,7 +2192,7 @@ __device__ __forceinline__ void bg_item_bwd(const Inst &a, BgBwdShared<T> &sh, i
                                             const float tau[T], uint32_t xbits, float tc, float (&gK)[12])
 {
     const LdsRec r = lds_rec(sh.it, e);
-    const float du = pix_du(p, a.inv_w), dv = pix_dv(p, a.inv_h);
+    const float du = pix_du(a, p), dv = pix_dv(a, p);
     const float galpha = sh.gal[p];
     Bary<SOLVER> bc;
     bc.setup(r, tc, du, dv);
@@ -2419,6 +2493,11 @@ static Inst make_inst(const Plan &p, const Io &io, char *base, const Grids &star
     a.W = p.W;
     a.H = p.H;
     a.tiles_x = p.tiles_x;
+    a.tw = p.tw;
+    a.th = p.th;
+    a.lw = __builtin_ctz((unsigned)p.tw);
+    a.lh = __builtin_ctz((unsigned)p.th);
+    a.rep = ~0ull / ((1ull << p.tw) - 1ull);
     a.tiles_y = p.tiles_y;
     a.ntiles = p.ntiles;
     a.CPS = p.CPS;
@@ -2504,14 +2583,18 @@ static void forward_T(const Batch &bt, const Inst *tab, void *ws, hipStream_t st
     const int n = bt.n;
     const Grids &g = bt.g;
     int64_t *tprefix = (int64_t *)((char *)ws + bt.o_tprefix);
-    hipLaunchKernelGGL(k_bin<T>, dim3((unsigned)g.bin), dim3(kBinThreads), 0, st, tab, n, 0);
+    const auto kbin = bt.tw == 16 ? k_bin<T, 16> : (bt.tw == 4 ? k_bin<T, 4> : k_bin<T, 8>);
+    hipLaunchKernelGGL(kbin, dim3((unsigned)g.bin), dim3(kBinThreads), 0, st, tab, n, 0);
     hipLaunchKernelGGL(k_scan1, dim3((unsigned)g.scan1), dim3(kScanThreads), 0, st, tab, n, 0);
     hipLaunchKernelGGL(k_scan2, dim3((unsigned)n), dim3(kScanThreads), 0, st, tab, 0);
     hipLaunchKernelGGL(k_scan3, dim3((unsigned)g.scan3), dim3(256), 0, st, tab, n, 0);
-    hipLaunchKernelGGL(k_bin<T>, dim3((unsigned)g.bin), dim3(kBinThreads), 0, st, tab, n, 1);
+    hipLaunchKernelGGL(kbin, dim3((unsigned)g.bin), dim3(kBinThreads), 0, st, tab, n, 1);
     if (bt.det) hipLaunchKernelGGL(k_sort_lists, dim3((unsigned)g.sort), dim3(kSortThreads), 0, st, tab, n);
     mark(pe, 2, st);
-    hipLaunchKernelGGL((k_fg<T, SOLVER>), dim3((unsigned)g.fg), dim3(kWave), 0, st, tab, n);
+    if (bt.tw == 8)
+        hipLaunchKernelGGL((k_fg<T, SOLVER, 8>), dim3((unsigned)g.fg), dim3(kWave), 0, st, tab, n);
+    else
+        hipLaunchKernelGGL((k_fg<T, SOLVER, 0>), dim3((unsigned)g.fg), dim3(kWave), 0, st, tab, n);
     hipLaunchKernelGGL(k_scan1, dim3((unsigned)g.tscan1), dim3(kScanThreads), 0, st, tab, n, 1);
     hipLaunchKernelGGL(k_scan2, dim3((unsigned)n), dim3(kScanThreads), 0, st, tab, 1);
     hipLaunchKernelGGL(k_scan3, dim3((unsigned)g.tscan3), dim3(256), 0, st, tab, n, 1);

@@ -27,6 +27,7 @@ class RenderOptions:
     slice_len: int = 0           # background-list entries per task (0: automatic)
     check: bool = True           # read the device header after each forward (one sync)
     deterministic: bool = False  # bitwise-reproducible results (RB_FLAG_DETERMINISTIC; slower)
+    tile_w: int = 0              # tile width in pixels: 4, 8 or 16 (height 64 / tile_w); 0 = 8
 
     def c_struct(self, capacity: int) -> B.rb_options:
         o = B.rb_options()
@@ -38,6 +39,7 @@ class RenderOptions:
         o.chunk_len = int(self.chunk_len)
         o.slice_len = int(self.slice_len)
         o.list_capacity = int(capacity)
+        o.tile_w = int(self.tile_w)
         return o
 
 

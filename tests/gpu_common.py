@@ -31,11 +31,11 @@ def say(*a):
     sys.stdout.flush()
 
 
-def gpu_forward(sc, solver="fast", chunk_len=4, slice_len=0, delta=1e-4, eps=1e-8, deterministic=False):
+def gpu_forward(sc, solver="fast", chunk_len=4, slice_len=0, delta=1e-4, eps=1e-8, deterministic=False, tile_w=0):
     import torch
     st = R.scene_tensors(sc, "cuda")
     opts = R.RenderOptions(sc.num_subframes, delta=delta, eps_cutoff=eps, solver=solver,
-                           chunk_len=chunk_len, slice_len=slice_len, deterministic=deterministic)
+                           chunk_len=chunk_len, slice_len=slice_len, deterministic=deterministic, tile_w=tile_w)
     img, state = R.render_forward(st.verts, st.faces, st.attrs, st.model, st.camera, opts)
     torch.cuda.synchronize()
     return img.double().cpu().numpy(), state, st

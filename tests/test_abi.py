@@ -48,7 +48,7 @@ def test_library_exports_every_declared_symbol(L):
 
 def test_struct_layouts_match_the_header(tmp_path):
     fields = [("rb_camera", None), ("rb_motion", None), ("rb_options", None), ("rb_header", None),
-              ("rb_profile_stats", None), ("rb_instance", None), ("rb_options", "list_capacity"),
+              ("rb_profile_stats", None), ("rb_instance", None), ("rb_options", "list_capacity"), ("rb_options", "tile_w"),
               ("rb_motion", "keyframe_model"), ("rb_instance", "motion"), ("rb_instance", "camera"),
               ("rb_instance", "list_capacity"), ("rb_instance", "grad_attrs"),
               ("rb_profile_stats", "fwd_calls")]
@@ -120,6 +120,10 @@ def test_deterministic_flag_adds_the_fixed_point_sums(L):
     (lambda a: setattr(a["op"], "chunk_len", 16), B.RB_EUNSUPPORTED),
     (lambda a: setattr(a["op"], "list_capacity", -5), B.RB_EINVAL),
     (lambda a: setattr(a["op"], "flags", 2), B.RB_EINVAL),
+    (lambda a: setattr(a["op"], "tile_w", 3), B.RB_EUNSUPPORTED),
+    (lambda a: setattr(a["op"], "tile_w", 32), B.RB_EUNSUPPORTED),
+    (lambda a: setattr(a["op"], "tile_w", -8), B.RB_EINVAL),
+    (lambda a: setattr(a["op"], "reserved", 1), B.RB_EINVAL),
     (lambda a: setattr(a["op"], "flags", -1), B.RB_EINVAL),
     (lambda a: setattr(a["cam"], "width", 0), B.RB_EINVAL),
     (lambda a: setattr(a["cam"], "tan_half_fov", -1.0), B.RB_EINVAL),

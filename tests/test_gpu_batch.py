@@ -101,12 +101,20 @@ def test_autotuner_picks_a_valid_configuration(case):
     import os
     import tempfile
     cache = os.path.join(tempfile.mkdtemp(), "autotune.json")
-    T, SL = BT.autotune(sts, targets, chunk_lens=(2, 4), slice_lens=(32, 64), reps=2, log=say, cache_path=cache)
-    assert T in (2, 4) and SL in (32, 64)
-    assert BT.autotune(sts, targets, chunk_lens=(2, 4), slice_lens=(32, 64)) == (T, SL)
+    timed = []
+
+    def log(m):
+        timed.append(m)
+        say(m)
+
+    T, SL, TW = BT.autotune(sts, targets, chunk_lens=(2, 4), slice_lens=(32, 64), reps=2, log=log, cache_path=cache)
+    assert T in (2, 4) and SL in (32, 64) and TW in (8, 16, 4)
+    # 2 x 2 (chunk, slice) pairs on 8 x 8 tiles, then the two other tile shapes
+    assert len(timed) == 6
+    assert BT.autotune(sts, targets, chunk_lens=(2, 4), slice_lens=(32, 64)) == (T, SL, TW)
     # a fresh process state reads the batch class from the file without timing
     BT._tuned.clear()
-    timed = []
-    assert BT.autotune(sts, targets, chunk_lens=(2, 4), slice_lens=(32, 64), log=timed.append,
-                       cache_path=cache) == (T, SL)
+    timed.clear()
+    assert BT.autotune(sts, targets, chunk_lens=(2, 4), slice_lens=(32, 64), log=log,
+                       cache_path=cache) == (T, SL, TW)
     assert not timed

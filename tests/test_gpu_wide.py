@@ -56,3 +56,34 @@ def test_wide_halo_batch_of_two_matches_oracle():
                            label=f"wide batch {i} verts")
         assert_grad_parity(r.grad_attrs[i].double().cpu().numpy(), ogs[i].grad_attrs, ogs[i].slack_attrs,
                            label=f"wide batch {i} attrs")
+
+
+def test_mixed_wide_and_narrow_batch_matches_oracle():
+    # one wide-halo and two narrow-halo instances: the batch runs the narrow
+    # kernel builds, with the wide instance keeping its own run lengths and
+    # chunk grouping (per-instance plan values)
+    import torch
+    from paper_2602_07860_amd import batch as BT
+    from paper_2602_07860_amd import render as R
+    scs = [wl.make_workload(wl.SMALL, motion=wl.Motion("rotate", axis=(0.3, 1.0, -0.2), revs=0.5, trans=(0.4, 0.1, 0.0)),
+                            num_segments=6, num_subframes=13, width=640, height=640),
+           wl.make_workload(wl.SMALL),
+           wl.make_workload(wl.SMALL, motion=wl.Motion("rotate", axis=(0.1, 0.8, 0.5), revs=0.6, trans=(0.5, 0.2, 0.0)),
+                            num_segments=5, num_subframes=23, width=61, height=37)]
+    say("case: batch mixing a wide-halo and two narrow-halo instances")
+    Gs = [np.random.default_rng(40 + i).normal(size=(sc.attrs.shape[1] + 1, sc.height, sc.width))
+          for i, sc in enumerate(scs)]
+    ogs = [reference(sc, G) for sc, G in zip(scs, Gs)]
+    r = BT.BatchRenderer([R.scene_tensors(sc, "cuda") for sc in scs], R.RenderOptions(0))
+    r.fit()
+    imgs = [im.double().cpu().numpy() for im in r.forward()]
+    for g, G in zip(r.grad_images, Gs):
+        g.copy_(torch.as_tensor(G, dtype=torch.float32))
+    r.backward()
+    torch.cuda.synchronize()
+    for i in range(len(scs)):
+        assert_image_parity(imgs[i], ogs[i], label=f"mixed batch {i}")
+        assert_grad_parity(r.grad_verts[i].double().cpu().numpy(), ogs[i].grad_verts, ogs[i].slack_verts,
+                           label=f"mixed batch {i} verts")
+        assert_grad_parity(r.grad_attrs[i].double().cpu().numpy(), ogs[i].grad_attrs, ogs[i].slack_attrs,
+                           label=f"mixed batch {i} attrs")
