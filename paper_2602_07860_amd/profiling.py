@@ -10,6 +10,15 @@
       per-kernel mean of every counter of a `rocprofv3 --pmc ... --output-format
       csv` run (CSV = its counter_collection.csv), with the kernels' register,
       scratch and LDS sizes;
+  python -m paper_2602_07860_amd.profiling derived --a CSV --b CSV --fetch DIR --write DIR \\
+          --copy-fetch DIR --copy-write DIR [--title T]
+      per kernel, from the two counter runs (A: SQ_INSTS_VALU,
+      SQ_THREAD_CYCLES_VALU, SQ_INSTS_LDS, SQ_LDS_BANK_CONFLICT; B: SQ_INSTS_SALU,
+      SQ_INSTS_VMEM_RD, SQ_INSTS_VMEM_WR, SQ_WAIT_ANY, SQ_ACTIVE_INST_ANY) and the
+      traffic runs: the share of active lanes in VALU instructions, LDS bank
+      conflict cycles per LDS instruction, the VALU share of issued
+      instructions, the share of wave cycles spent waiting, and HBM GB read
+      and written per launch;
   python -m paper_2602_07860_amd.profiling traffic --kernel K --workload W \\
           [--match NAME] --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR --out FILE
       combine `rocprofv3 --pmc FETCH_SIZE` and `--pmc WRITE_SIZE` runs of the
@@ -128,6 +137,50 @@ def _counters(a) -> None:
     print("\n".join(out))
 
 
+def _means(path: str) -> dict:
+    """{kernel: {counter: mean per dispatch}} of one counter_collection.csv
+    (or of every such file under a directory)."""
+    files = [path] if os.path.isfile(path) else glob.glob(os.path.join(path, "**", "*counter_collection.csv"),
+                                                          recursive=True)
+    agg: dict = {}
+    for f in files:
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                agg.setdefault(r["Kernel_Name"], {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    return {k: {c: sum(v) / len(v) for c, v in d.items()} for k, d in agg.items()}
+
+
+def _derived(a) -> None:
+    A, Bc = _means(a.a), _means(a.b)
+    fe, wr = _means(a.fetch), _means(a.write)
+    cf = COPY_BYTES / (_counter_mean(a.copy_fetch, "FETCH_SIZE", a.copy_kernel) * 1024)
+    cw = COPY_BYTES / (_counter_mean(a.copy_write, "WRITE_SIZE", a.copy_kernel) * 1024)
+    out = ["# derived per-dispatch figures" + (f": {a.title}" if a.title else ""),
+           "# active lanes = SQ_THREAD_CYCLES_VALU / (64 SQ_INSTS_VALU); LDS conflict cycles per LDS instruction;",
+           "# VALU share = SQ_INSTS_VALU / (VALU + SALU + LDS + VMEM instructions); waiting = SQ_WAIT_ANY /",
+           "# (SQ_WAIT_ANY + SQ_ACTIVE_INST_ANY); HBM GB per launch from FETCH_SIZE and WRITE_SIZE (KiB per",
+           f"# dispatch) scaled by a 1 GiB device copy (x{cf:.3f} and x{cw:.3f})",
+           "",
+           f"{'kernel':<34}{'active lanes':>13}{'LDS confl/ins':>14}{'VALU share':>11}{'waiting':>9}{'fetch GB':>10}{'write GB':>10}"]
+    rows = []
+    for k, d in A.items():
+        if "rb::" not in k or "SQ_INSTS_VALU" not in d or k not in Bc:
+            continue
+        b = Bc[k]
+        valu = d["SQ_INSTS_VALU"]
+        lanes = d["SQ_THREAD_CYCLES_VALU"] / (64.0 * valu) if valu else float("nan")
+        lds = d.get("SQ_INSTS_LDS", 0.0)
+        confl = d.get("SQ_LDS_BANK_CONFLICT", 0.0) / lds if lds else 0.0
+        tot = valu + b.get("SQ_INSTS_SALU", 0.0) + lds + b.get("SQ_INSTS_VMEM_RD", 0.0) + b.get("SQ_INSTS_VMEM_WR", 0.0)
+        wait = b.get("SQ_WAIT_ANY", 0.0) / max(b.get("SQ_WAIT_ANY", 0.0) + b.get("SQ_ACTIVE_INST_ANY", 0.0), 1.0)
+        f = fe.get(k, {}).get("FETCH_SIZE", float("nan")) * 1024 * cf / 1e9
+        w = wr.get(k, {}).get("WRITE_SIZE", float("nan")) * 1024 * cw / 1e9
+        name = k.split("(")[0].replace("void ", "")
+        rows.append((valu, f"{name:<34}{lanes:>13.3f}{confl:>14.3f}{valu / tot:>11.3f}{wait:>9.3f}{f:>10.2f}{w:>10.2f}"))
+    out += [r for _, r in sorted(rows, key=lambda x: -x[0])]
+    print("\n".join(out))
+
+
 def _copy() -> None:
     import torch
     x = torch.ones(COPY_BYTES // 4, device="cuda")
@@ -174,6 +227,11 @@ def main() -> None:
     cn.add_argument("--title", default="")
     cn.add_argument("--command", default="")
     cn.add_argument("--top", type=int, default=16)
+    dv = sub.add_parser("derived")
+    for k in ("a", "b", "fetch", "write", "copy_fetch", "copy_write"):
+        dv.add_argument("--" + k.replace("_", "-"), required=True)
+    dv.add_argument("--copy-kernel", default="copyBuffer")
+    dv.add_argument("--title", default="")
     t = sub.add_parser("traffic")
     t.add_argument("--kernel", required=True)
     t.add_argument("--match", default="", help="substring of the profiled kernel names (default: --kernel)")
@@ -191,6 +249,8 @@ def main() -> None:
         _summary(a)
     elif a.cmd == "counters":
         _counters(a)
+    elif a.cmd == "derived":
+        _derived(a)
     else:
         _traffic(a)
 
