@@ -580,7 +580,8 @@ __global__ void k_scan3(const Inst *__restrict__ tab, int n, int which)
 // +infinity and never take part (a compare-exchange keeps the minimum at the
 // lower index, so such a pair is a no-op).  Stages whose pairs lie within one
 // block of kSortB entries run in LDS; longer lists do the wider stages in
-// global memory.
+// global memory.  Lists of at most 64 entries are sorted by the block's first
+// wave in registers, one entry per lane.
 
 constexpr int kSortThreads = 256, kSortB = 4096;
 
@@ -644,6 +645,25 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_lists(const Inst *__restr
     const int64_t len = a.cnt[g], beg = a.off[g];
     if (len <= 1 || beg + len > a.cap) return;   // (an overflowed forward is reported, not used)
     uint32_t RB_G *L = a.list + beg;
+    if (len <= kWave) {
+        // the same network over the 64 lanes; lanes past the end hold the
+        // largest value and keep it
+        if (threadIdx.x >= kWave) return;
+        const int lane = threadIdx.x;
+        uint32_t x = lane < len ? L[lane] : 0xffffffffu;
+        auto cx = [&](int partner) {
+            const uint32_t y = (uint32_t)__shfl((int)x, partner, kWave);
+            x = lane < partner ? min(x, y) : max(x, y);
+        };
+#pragma unroll
+        for (int k = 2; k <= kWave; k <<= 1) {
+            cx(lane ^ (k - 1));
+#pragma unroll
+            for (int j = k >> 2; j >= 1; j >>= 1) cx(lane ^ j);
+        }
+        if (lane < len) L[lane] = x;
+        return;
+    }
     // network size: the smallest power of two >= len
     int64_t P = 2;
     while (P < len) P <<= 1;
