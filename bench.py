@@ -18,8 +18,8 @@ Workloads (synthetic, seeded; see paper_2602_07860_amd/workloads.py):
     render of a second seeded displacement (static geometry).
   batch: 32 instances of mixed sizes, resolutions {128, 256, 512}^2,
     K in [32, 256], half translation / half rotation, all in one launch
-    sequence captured in a graph and replayed; chunk and slice lengths from
-    the autotuner.
+    sequence captured in a graph and replayed; chunk length, slice length and
+    tile shape from the autotuner.
   sweep: the speed comparison of Sec. 4.2 on stand-in models (50 nu=17
     spheres, 5780 faces, 128x128, translation) for K in 10..200: the fast
     solver against the static-frames baseline (K still renders averaged);
@@ -30,7 +30,8 @@ Workloads (synthetic, seeded; see paper_2602_07860_amd/workloads.py):
 One step = forward render + dL/dI + adjoint into vertex positions and colours.
 Inputs are resident in GPU memory before the timed region.  The step is timed
 for the fast solver (eq 8) and for the per-sub-frame recompute (eqs 1-3) on
-the same GPU.
+the same GPU: "ms_per_step" is the mean over the timed steps (events around
+all of them), "ms_per_step_median" the median of the per-step durations.
 
 Prints ONE JSON line.  Extra objects: "roofline" for the dominant kernel
 (algorithmic FLOPs from the FP64 reference's exact pair counters on the
@@ -91,21 +92,24 @@ def kernel_ms(prof):
             "vertex_grad": prof.vertex_grad_ms / b}
 
 
-def timed(fn, steps, B, torch, phases=True, phase_steps=None, phases_in_loop=False):
+def timed(fn, steps, B, torch, phases=True, phase_steps=None, phases_in_loop=False, per_step=None):
     """Average ms of fn() over `steps` calls (device events) and, optionally,
     the per-kernel phases: recorded during those same calls (phases_in_loop;
     the library's phase events cost microseconds per call) or over a second
-    pass of `phase_steps` (default `steps`) calls."""
+    pass of `phase_steps` (default `steps`) calls.  With a list per_step, the
+    duration of every call (an event after each) is appended to it."""
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     if phases and phases_in_loop:
         B.rb_profile_enable(True)
-    e0.record()
-    for _ in range(steps):
+    ev[0].record()
+    for i in range(steps):
         fn()
-    e1.record()
+        ev[i + 1].record()
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
+    ms = ev[0].elapsed_time(ev[-1]) / steps
+    if per_step is not None:
+        per_step.extend(ev[i].elapsed_time(ev[i + 1]) for i in range(steps))
     if not phases:
         return ms, None
     if not phases_in_loop:
@@ -163,7 +167,8 @@ def run_single(start, tg, args, torch, B, R, adam=False):
                 box["o"] = opts(solver, check=False)
         if "geom" not in box:
             box["geom"] = (verts.detach().clone(), attrs.detach().clone())
-        ms, km = timed(step, args.steps, B, torch, phases_in_loop=adam)
+        each = []
+        ms, km = timed(step, args.steps, B, torch, phases_in_loop=adam, per_step=each)
         img, gv, ga, state = box["out"]
         h = B.rb_read_header(state.workspace.data_ptr(), torch.cuda.current_stream().cuda_stream)
         if h.error_bits:
@@ -172,7 +177,7 @@ def run_single(start, tg, args, torch, B, R, adam=False):
             raise RuntimeError("non-finite output")
         loss = float(((img - target) ** 2).sum())
         gv_, ga_ = box["geom"]
-        res[solver] = dict(ms=ms, km=km, loss=loss,
+        res[solver] = dict(ms=ms, km=km, loss=loss, median_ms=float(np.median(each)),
                            geom=(gv_.cpu().numpy().astype(np.float32), ga_.cpu().numpy().astype(np.float32)))
         del box, opt, verts, attrs
     return res
@@ -196,14 +201,15 @@ def run_batch(scenes, targets_sc, args, torch, B, R):
         step.capture()
         for _ in range(max(1, args.warmup)):
             step.replay()
-        ms, _ = timed(step.replay, args.steps, B, torch, phases=False)
+        each = []
+        ms, _ = timed(step.replay, args.steps, B, torch, phases=False, per_step=each)
         _, km = timed(step.eager, max(2, args.steps // 4), B, torch)   # phase events need eager calls
         hs = r.headers()
         if any(h.error_bits for h in hs):
             raise RuntimeError("device header reports errors")
         if not all(bool(torch.isfinite(x).all()) for x in r.images + r.grad_verts + r.grad_attrs):
             raise RuntimeError("non-finite output")
-        res[solver] = dict(ms=ms, km=km, chunk_len=T, slice_len=SL, tile_w=TW)
+        res[solver] = dict(ms=ms, km=km, chunk_len=T, slice_len=SL, tile_w=TW, median_ms=float(np.median(each)))
         del step, r
     return res
 
@@ -481,6 +487,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(fast["ms"], 4),
+        "ms_per_step_median": round(fast["median_ms"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
