@@ -92,3 +92,19 @@ def test_batch_two_runs_bitwise_equal():
         dv, da = rel_l2(a[1][i].astype(np.float64), gv), rel_l2(a[2][i].astype(np.float64), ga)
         say(f"  instance {i} vs single: image {di:.2e}, verts {dv:.2e}, attrs {da:.2e}")
         assert di <= 1e-6 and dv <= 1e-5 and da <= 1e-5
+
+
+@pytest.mark.parametrize("solver,tile_w", [("recompute", 0), ("fast", 16), ("recompute", 4)])
+def test_deterministic_with_other_solver_and_tiles(solver, tile_w):
+    sc = wl.make_workload(wl.SMALL, motion=wl.Motion("rotate", axis=(0.3, 1.0, -0.2), revs=0.8, trans=(0.3, 0.0, 0.0)),
+                          num_segments=10, num_subframes=41, width=48, height=40)
+    say(f"case: deterministic small rotation solver={solver} tile_w={tile_w}")
+    G = np.random.default_rng(23).normal(size=(sc.attrs.shape[1] + 1, sc.height, sc.width))
+    a = _run(sc, G, deterministic=True, solver=solver, tile_w=tile_w)
+    b = _run(sc, G, deterministic=True, solver=solver, tile_w=tile_w)
+    for x, y, name in zip(a, b, ("image", "grad_verts", "grad_attrs")):
+        assert np.array_equal(x.view(np.uint64), y.view(np.uint64)), name
+    og = reference(sc, G)
+    assert_image_parity(a[0], og, label=f"det {solver} tile{tile_w}")
+    assert_grad_parity(a[1], og.grad_verts, og.slack_verts, label=f"det {solver} tile{tile_w} verts")
+    assert_grad_parity(a[2], og.grad_attrs, og.slack_attrs, label=f"det {solver} tile{tile_w} attrs")
