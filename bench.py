@@ -183,6 +183,42 @@ def run_single(start, tg, args, torch, B, R, adam=False):
     return res
 
 
+def run_loop(args, torch, B, R):
+    """The large workload's shape-recovery loop run end to end: --loop-steps
+    Adam steps from the plain sphere (fast solver), every step a forward,
+    dL/dI of the L2 loss, the adjoint and the Adam update, timed as a whole
+    with device events; the loss at the start and at the end."""
+    from paper_2602_07860_amd import workloads as wl
+    dev = "cuda:0"
+    tg = wl.make_workload(wl.LARGE)
+    start = wl.plain_start(tg)
+    st, tt = R.scene_tensors(start, dev), R.scene_tensors(tg, dev)
+    o = R.RenderOptions(start.num_subframes, chunk_len=args.chunk_len, slice_len=args.slice_len, tile_w=args.tile_w)
+    target, _ = R.render_forward(tt.verts, tt.faces, tt.attrs, tt.model, tt.camera, o)
+    verts, attrs = st.verts.clone(), st.attrs.clone()
+    opt = torch.optim.Adam([verts, attrs], lr=0.01, betas=(0.5, 0.99))
+    losses = []
+
+    def step():
+        img, state = R.render_forward(verts, st.faces, attrs, st.model, st.camera, o)
+        d = img - target
+        losses.append(torch.sum(d * d))
+        gv, ga = R.render_backward(verts, st.faces, attrs, st.model, state, 2.0 * d)
+        verts.grad, attrs.grad = gv, ga
+        opt.step()
+
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.loop_steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    total = e0.elapsed_time(e1)
+    return {"steps": args.loop_steps, "total_s": round(total * 1e-3, 3), "ms_per_step": round(total / args.loop_steps, 4),
+            "loss_first_step": round(float(losses[0]), 3), "loss_last_step": round(float(losses[-1]), 3)}
+
+
 def run_batch(scenes, targets_sc, args, torch, B, R):
     from paper_2602_07860_amd import batch as BT
     dev = "cuda:0"
@@ -355,6 +391,9 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--tile-w", type=int, default=0, choices=(0, 4, 8, 16),
                     help="tile width in pixels for the large and medium workloads (0: 8)")
+    ap.add_argument("--loop-steps", type=int, default=0,
+                    help="large workload: also run the whole Adam loop of this many steps end to end "
+                         "(the shape-recovery schedule has 200)")
     ap.add_argument("--deterministic", action="store_true",
                     help="render with RB_FLAG_DETERMINISTIC (large and medium workloads)")
     args = ap.parse_args()
@@ -438,6 +477,9 @@ def main():
             config["deterministic"] = True
         if adam:
             config["loss_after_loop"] = round(res["fast"]["loss"], 4)
+        if adam and args.loop_steps > 0:
+            loop = run_loop(args, torch, B, R)
+            log(f"loop end to end: {loop}")
     units = sum(s.height * s.width * s.num_subframes for s in scenes)
     for solver, r in res.items():
         log(f"{solver}: {r['ms']:.3f} ms/step  {units / (r['ms'] * 1e-3):.3e} px-sub/s  "
@@ -501,6 +543,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if args.workload == "large" and args.loop_steps > 0:
+        out["loop_end_to_end"] = loop
     print(json.dumps(out), flush=True)
 
 
