@@ -120,4 +120,4 @@ def test_autograd_function_matches_adjoint():
     torch.cuda.synchronize()
     assert torch.allclose(verts.grad, gv, rtol=1e-4, atol=1e-6)
     assert torch.allclose(attrs.grad, ga, rtol=1e-4, atol=1e-6)
-    assert float(loss) > 0
+    assert float(loss.detach()) > 0
