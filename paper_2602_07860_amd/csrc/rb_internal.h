@@ -17,6 +17,7 @@ namespace rb {
 constexpr int kWave = 64;
 constexpr int kTileWDefault = 8;
 constexpr float kTauDet = 1e-10f;         // |det F(tau)| at or below this: face skipped
+constexpr double kTauDetBin = 1e-10;      // the same rule in double, applied when the lists are built
 // background adjoint: a term whose weight prod_{m != j}(1 - A_m) A_j is below
 // this is left out, and so is a whole (pixel, sub-frame) where the bound
 // prod_m (1 - A_m) / min(min_m (1 - A_m), 1/2) on its weights is (the FP64

@@ -306,11 +306,14 @@ __device__ __forceinline__ bool face_chunk_tiles(const Inst &a, int f, const Chu
                                                  int bty1[T], FaceTiles &u)
 {
     float ax[3], ay[3], bx[3], by[3];
+    double2 kp[3], kr[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
         int v = clampi(a.faces[3 * f + q], 0, a.V - 1);
-        double2 p = a.kf[(size_t)ch.s * a.V + v];
-        double2 r = a.kf[(size_t)(ch.s + 1) * a.V + v];
+        const double2 p = a.kf[(size_t)ch.s * a.V + v];
+        const double2 r = a.kf[(size_t)(ch.s + 1) * a.V + v];
+        kp[q] = p;
+        kr[q] = r;
         ax[q] = (float)p.x;
         ay[q] = (float)p.y;
         bx[q] = (float)(r.x - p.x);
@@ -326,6 +329,22 @@ __device__ __forceinline__ bool face_chunk_tiles(const Inst &a, int f, const Chu
         ftx1[j] = fty1[j] = btx1[j] = bty1[j] = 0;
         if (j < ch.n) {
             int rem = (ch.k0 + j) * a.S - ch.s * (a.K - 1);
+            // the skip rule |det F(tau)| <= kTauDet is decided here, in
+            // double from the double keyframes: a face that is degenerate at
+            // this sub-frame (a repeated vertex, coincident or collinear
+            // vertices) gets no entry bit, whatever its float32 determinant
+            // in the raster kernels would round to
+            {
+                const double td = a.K > 1 ? (double)rem / (double)(a.K - 1) : 0.0;
+                double xd[3], yd[3];
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    xd[q] = (1.0 - td) * kp[q].x + td * kr[q].x;
+                    yd[q] = (1.0 - td) * kp[q].y + td * kr[q].y;
+                }
+                const double D = (xd[1] - xd[0]) * (yd[2] - yd[0]) - (xd[2] - xd[0]) * (yd[1] - yd[0]);
+                if (!(fabs(D) > (double)kTauDetBin)) continue;
+            }
             float tau = a.K > 1 ? (float)rem / (float)(a.K - 1) : 0.0f;
             float x[3], y[3];
 #pragma unroll
