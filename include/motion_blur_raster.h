@@ -181,9 +181,9 @@ rb_status rb_read_header(const void *workspace, rb_header *out, void *stream);
  * in one sequence of launches, every kernel covering all instances (the
  * background passes are persistent kernels over the tasks of all instances).
  * The rb_instance array is HOST memory holding DEVICE pointers.  options
- * supplies delta, eps_cutoff, solver, chunk_len and slice_len for the whole
- * batch; num_subframes and list_capacity of options are ignored in favour of
- * each instance's own.  mode RB_BATCH_FORWARD writes every instance's image;
+ * supplies delta, eps_cutoff, solver, flags, chunk_len, slice_len and tile_w
+ * for the whole batch; num_subframes and list_capacity of options are ignored
+ * in favour of each instance's own.  mode RB_BATCH_FORWARD writes every instance's image;
  * RB_BATCH_BACKWARD reads grad_image and overwrites grad_verts / grad_attrs,
  * reusing the state the forward left in the same workspace. */
 typedef struct {
