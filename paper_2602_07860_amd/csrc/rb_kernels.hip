@@ -782,9 +782,11 @@ struct FaceRec {
 };
 
 // An entry staged in LDS, field-major: field k of entry e at rec[k][e].
-struct LdsRec {
+// a staged record in LDS, field-major with a stride of NBX entries
+template <int NBX>
+struct LdsRecN {
     const float *p;
-    __device__ float at(int k) const { return p[k * NB]; }
+    __device__ float at(int k) const { return p[k * NBX]; }
 };
 
 __device__ __forceinline__ void lds_sync()
@@ -1253,25 +1255,26 @@ __device__ __forceinline__ int lane_rank(uint64_t bal)
     return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
 }
 
-// Item bookkeeping shared by the forward and backward walks.
-template <int T>
+// Item bookkeeping shared by the forward and backward walks (NBX entries
+// staged per batch).
+template <int T, int NBX = NB>
 struct ItemShared {
-    float rec[R_N][NB];  // staged entries, field-major
-    uint64_t m[T][NB];   // per sub-frame and entry: pixels to evaluate
-    uint64_t U[NB];      // union over the sub-frames
-    int pre[NB + 1];     // number of the entry's first item (entry nb: the batch's item count)
-    int ne[NB];          // entries with at least one item, in order
+    float rec[R_N][NBX];  // staged entries, field-major
+    uint64_t m[T][NBX];   // per sub-frame and entry: pixels to evaluate
+    uint64_t U[NBX];      // union over the sub-frames
+    int pre[NBX + 1];     // number of the entry's first item (entry nb: the batch's item count)
+    int ne[NBX];          // entries with at least one item, in order
     uint8_t flag[kWave];
 };
 
-template <int T>
-__device__ __forceinline__ LdsRec lds_rec(ItemShared<T> &sh, int e)
+template <int T, int NBX>
+__device__ __forceinline__ LdsRecN<NBX> lds_rec(ItemShared<T, NBX> &sh, int e)
 {
-    return LdsRec{&sh.rec[0][e]};
+    return LdsRecN<NBX>{&sh.rec[0][e]};
 }
 
-template <int T>
-__device__ __forceinline__ void store_rec(ItemShared<T> &sh, int e, const FaceRec &r)
+template <int T, int NBX>
+__device__ __forceinline__ void store_rec(ItemShared<T, NBX> &sh, int e, const FaceRec &r)
 {
 #pragma unroll
     for (int k = 0; k < R_N - 1; ++k) sh.rec[k][e] = r.v[k];
@@ -1459,7 +1462,7 @@ template <int T, int SOLVER, int TWS>
 __device__ __forceinline__ void fg_item(const Inst &a, FgShared<T> &sh, int e, int p, const float tau[T],
                                         float tc)
 {
-    const LdsRec r = lds_rec(sh.it, e);
+    const auto r = lds_rec(sh.it, e);
     const float du = pix_du<TWS>(a, p), dv = pix_dv<TWS>(a, p);
     Bary<SOLVER> bc;
     bc.setup(r, tc, du, dv);
@@ -1648,7 +1651,7 @@ __device__ __forceinline__ void bg_item_fwd(const Inst &a, BgShared<T> &sh, int 
                                             uint32_t xbits, int xk, float tc, double (&ls)[T], int (&nz)[T],
                                             float (&om_lo)[T])
 {
-    const LdsRec r = lds_rec(sh.it, e);
+    const auto r = lds_rec(sh.it, e);
     const float du = pix_du(a, p), dv = pix_dv(a, p);
     Bary<SOLVER> bc;
     bc.setup(r, tc, du, dv);
@@ -1979,12 +1982,17 @@ __device__ __forceinline__ void vt_flush(VTab<NV, NS, V> &vt, int s, const Inst 
 
 // ------------------------------------------------------- backward: k_fg_bwd
 
+// winning faces staged per batch in the foreground adjoint: half the list
+// walk's batch, which keeps the wave's LDS near 9 KB (16 waves per compute
+// unit) with a 64-slot vertex table that one batch cannot overfill
+constexpr int NBF = 16;
+
 template <int T>
 struct FgBwdShared {
-    ItemShared<T> it;         // staged winning faces, their (pixel, sub-frame) masks and items
-    float at[3 * NCH][NB];    // their vertex attributes
-    int vslot[NB][3];         // their vertices: index, then vertex-table slot
-    VTab<4 + NCH, 128, double> vt;   // one batch of at most NB faces between flushes
+    ItemShared<T, NBF> it;    // staged winning faces, their (pixel, sub-frame) masks and items
+    float at[3 * NCH][NBF];   // their vertex attributes
+    int vslot[NBF][3];        // their vertices: index, then vertex-table slot
+    VTab<4 + NCH, 64, double> vt;    // at most 3 NBF new vertices per batch
     float gI[NCH][kWave];     // dL/dcolour of each pixel, already divided by K
 };
 
@@ -1997,7 +2005,7 @@ template <int T, int SOLVER>
 __device__ __forceinline__ void fg_item_bwd(const Inst &a, FgBwdShared<T> &sh, int e, int p, const float tau[T],
                                             float tc, float (&acc)[12 + 3 * NCH])
 {
-    const LdsRec r = lds_rec(sh.it, e);
+    const auto r = lds_rec(sh.it, e);
     const float du = pix_du(a, p), dv = pix_dv(a, p);
     float gI[NCH], gw[3], ws[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
@@ -2113,7 +2121,7 @@ __global__ __launch_bounds__(64) void k_fg_bwd(const Inst *__restrict__ tab, int
 
         // Only the winning faces are staged (the list is not walked): the first
         // pending pair's face becomes the next entry and takes every pending pair
-        // of that face, as its per-sub-frame pixel masks; a batch of NB entries
+        // of that face, as its per-sub-frame pixel masks; a batch of NBF entries
         // (or the last one) is staged and its items (entry, pixel) are run.
         uint64_t mown[T];         // masks of entry `lane` of the batch being gathered
 #pragma unroll
@@ -2143,7 +2151,7 @@ __global__ __launch_bounds__(64) void k_fg_bwd(const Inst *__restrict__ tab, int
                 if (lane == ne) sel = f;
                 ++ne;
             }
-            if (ne == NB || (j0 < 0 && ne > 0)) {
+            if (ne == NBF || (j0 < 0 && ne > 0)) {
                 if (used + 3 * ne > sh.vt.kLoad) {
                     vt_flush(sh.vt, ck.s, a);
                     used = 0;
@@ -2230,7 +2238,7 @@ template <int T, int SOLVER>
 __device__ __forceinline__ void bg_item_bwd(const Inst &a, BgBwdShared<T> &sh, int e, int p,
                                             const float tau[T], uint32_t xbits, float tc, float (&gK)[12])
 {
-    const LdsRec r = lds_rec(sh.it, e);
+    const auto r = lds_rec(sh.it, e);
     const float du = pix_du(a, p), dv = pix_dv(a, p);
     const float galpha = sh.gal[p];
     Bary<SOLVER> bc;
