@@ -13,11 +13,14 @@
 //   k_bin (x2), k_scan1..3
 //                      one thread per (face, chunk of at most T sub-frames of
 //                      one segment) takes the face's exact box at each of the
-//                      chunk's sub-frames and, for every 8x8 tile the union
-//                      touches, emits face << 8 | sub-frame mask into the
-//                      foreground list (exact box) and the background list
-//                      (box grown by the influence radius); counts and fill
-//                      ranks go through LDS window counters.
+//                      chunk's sub-frames and, for every tile (64 pixels:
+//                      8x8, 16x4 or 4x16) the union touches, emits
+//                      face << 8 | sub-frame mask into the foreground list
+//                      (exact box) and the background list (box grown by the
+//                      influence radius), leaving out the sub-frames where
+//                      the face is degenerate (|det F| <= 1e-10 in double);
+//                      counts and fill ranks go through LDS window counters.
+//   k_sort_lists       (deterministic mode) sorts every list into face order.
 //   k_fg               one 64-lane wave per (chunk, tile), lane = pixel: list
 //                      entries are staged in LDS 32 at a time (anchor-local
 //                      float32 records) and dealt out as (entry, pixel)
@@ -36,16 +39,19 @@
 //                      in the records.
 //   k_resolve          mean over the K sub-frames (double).
 // Backward (launch_backward):
-//   k_bwd_init         clears the keyframe and attribute gradients.
+//   k_bwd_init         clears the keyframe and attribute gradients
+//                      (k_det_prep: the fixed-point sums of the
+//                      deterministic mode and their scale).
 //   k_fg_bwd           one wave per (group of chunks of a segment, tile):
 //                      gathers the distinct winners from the visibility,
-//                      stages them and runs the shading / barycentric
-//                      adjoint into an LDS table keyed by vertex.
+//                      stages them 16 at a time and runs the shading /
+//                      barycentric adjoint into an LDS table keyed by vertex.
 //   k_bg_bwd           persistent waves over the background tasks, with a
 //                      task counter: re-walks the list slices for the
 //                      (pixel, sub-frame)s with gradient (leaving out terms
 //                      of negligible weight) and runs the closest-point /
 //                      barycentric adjoint into the vertex table.
+//   k_det_finish       (deterministic mode) fixed-point sums to float.
 //   k_kf_to_vertex     maps keyframe gradients through the projection and
 //                      the keyframe transforms to the rest vertices.
 // The adjoints deal items to lanes in runs (for_runs) so that a lane adds a
@@ -703,7 +709,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_lists(const Inst *__restr
 // ----------------------------------------------------------------- raster
 //
 // Forward, three kernels:
-//  * k_fg, one 64-lane wave per (chunk, 8x8 tile), lane = pixel: z-buffer
+//  * k_fg, one 64-lane wave per (chunk, tile), lane = pixel: z-buffer
 //    over the tile's foreground list (eq 9), shading of the winners, and the
 //    per-(pixel, sub-frame) records the rest reads: winner (or uncovered),
 //    colour, zeroed background accumulators.  It also counts the background

@@ -44,13 +44,41 @@ SOURCES = [os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", f)
            for f in ("rb_kernels.hip", "rb_api.cpp", "rb_internal.h")]
 
 
-def source_hash() -> str:
-    """Hash of the kernel sources and of the host plan that sets their launch
-    parameters."""
+def code_text(src: str) -> str:
+    """C++ source without its comments and with whitespace collapsed, so that
+    an edit of the comments alone does not count as a change of the code."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        if src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        elif src[i] == '"':
+            j = i + 1
+            while j < n and src[j] != '"':
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        else:
+            out.append(src[i])
+            i += 1
+    return " ".join("".join(out).split())
+
+
+def source_hash(texts=None) -> str:
+    """Hash of the code (comments left out) of the kernel sources and of the
+    host plan that sets their launch parameters."""
     h = hashlib.sha256()
-    for p in SOURCES:
-        with open(p, "rb") as f:
-            h.update(f.read())
+    if texts is None:
+        texts = []
+        for p in SOURCES:
+            with open(p) as f:
+                texts.append(f.read())
+    for t in texts:
+        h.update(code_text(t).encode())
     return h.hexdigest()
 
 

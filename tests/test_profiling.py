@@ -27,3 +27,15 @@ def test_batch_class_is_coarse_and_stable():
     assert c1 == BT.batch_class(list(reversed(sts)), "fast")
     assert c1 != BT.batch_class(sts, "recompute")
     assert c1.startswith("fast|n4|")
+
+
+def test_source_hash_ignores_comments_only():
+    from paper_2602_07860_amd import profiling as P
+    a = 'int f(int x) { return x + 1; } // one\n/* two */\nconst char *s = "// not a comment";\n'
+    b = 'int f(int x)  {\n  return x + 1;  // changed comment\n}\nconst char *s = "// not a comment";\n'
+    c = 'int f(int x) { return x + 2; }\nconst char *s = "// not a comment";\n'
+    d = 'int f(int x) { return x + 1; }\nconst char *s = "// other";\n'
+    assert P.code_text(a) == P.code_text(b)
+    assert P.source_hash([a]) == P.source_hash([b])
+    assert P.source_hash([a]) != P.source_hash([c])
+    assert P.source_hash([a]) != P.source_hash([d])
