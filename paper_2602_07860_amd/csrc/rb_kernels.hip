@@ -633,28 +633,63 @@ __device__ __forceinline__ void cx_pair(P buf, int64_t q, int64_t k, int64_t j, 
     }
 }
 
-// LDS pass over block [b0, b0 + blk) of the list (blk a power of two, at
-// most kSortB): the mirror steps of block sizes 2 .. blk, each followed by
-// its halving steps, or (full == false) only the halving steps from distance
-// blk / 2 down to 1
+// The stages whose compare distance is below 64 stay inside one 64-entry
+// chunk of the block: a wave runs them on its chunks in registers (one entry
+// per lane, partners through shuffles), with no barrier between stages.
+// full: the whole network of block sizes 2 .. 64; else the halving steps
+// from distance 32 down to 1.
+__device__ __forceinline__ void chunk_pass(uint32_t *sh, int blk, bool full)
+{
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    for (int c = w; c < blk / kWave; c += kSortThreads / kWave) {
+        uint32_t x = sh[c * kWave + lane];
+        auto step = [&](int m) {
+            const uint32_t y = (uint32_t)__shfl_xor((int)x, m, kWave);
+            x = lane < (lane ^ m) ? min(x, y) : max(x, y);
+        };
+        if (full) {
+#pragma unroll
+            for (int k = 2; k <= kWave; k <<= 1) {
+                step(k - 1);
+#pragma unroll
+                for (int m = k >> 2; m >= 1; m >>= 1) step(m);
+            }
+        } else {
+#pragma unroll
+            for (int m = kWave / 2; m >= 1; m >>= 1) step(m);
+        }
+        sh[c * kWave + lane] = x;
+    }
+}
+
+// LDS pass over block [b0, b0 + blk) of the list (blk a power of two,
+// 128 <= blk <= kSortB): the mirror steps of block sizes 2 .. blk, each
+// followed by its halving steps, or (full == false) only the halving steps
+// from distance blk / 2 down to 1
 __device__ __forceinline__ void lds_pass(uint32_t RB_G *L, int64_t len, int64_t b0, int blk, bool full, uint32_t *sh)
 {
     const int m = (int)min<int64_t>(blk, len - b0);
     for (int t = threadIdx.x; t < blk; t += kSortThreads) sh[t] = t < m ? L[b0 + t] : 0xffffffffu;
     __syncthreads();
-    auto halve = [&](int j) {
-        for (; j >= 1; j >>= 1) {
+    auto halve_lds = [&](int j) {   // halving steps of distance j .. 64
+        for (; j >= kWave; j >>= 1) {
             for (int q = threadIdx.x; q < blk / 2; q += kSortThreads) cx_pair(sh, q, 0, j, blk);
             __syncthreads();
         }
     };
     if (!full) {
-        halve(blk >> 1);
+        halve_lds(blk >> 1);
+        chunk_pass(sh, blk, false);
+        __syncthreads();
     } else {
-        for (int k = 2; k <= blk; k <<= 1) {
+        chunk_pass(sh, blk, true);
+        __syncthreads();
+        for (int k = 2 * kWave; k <= blk; k <<= 1) {
             for (int q = threadIdx.x; q < blk / 2; q += kSortThreads) cx_pair(sh, q, k, 0, blk);
             __syncthreads();
-            halve(k >> 2);
+            halve_lds(k >> 2);
+            chunk_pass(sh, blk, false);
+            __syncthreads();
         }
     }
     for (int t = threadIdx.x; t < m; t += kSortThreads) L[b0 + t] = sh[t];
