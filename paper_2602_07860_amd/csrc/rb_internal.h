@@ -16,6 +16,7 @@ namespace rb {
 // 8 x 8 by default, 16 x 4 or 4 x 16 on request
 constexpr int kWave = 64;
 constexpr int kTileWDefault = 8;
+constexpr int kMaxTileH = 16;          // rows of the tallest tile shape (4 x 16)
 constexpr float kTauDet = 1e-10f;         // |det F(tau)| at or below this: face skipped
 constexpr double kTauDetBin = 1e-10;      // the same rule in double, applied when the lists are built
 // background adjoint: a term whose weight prod_{m != j}(1 - A_m) A_j is below

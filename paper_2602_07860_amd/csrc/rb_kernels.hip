@@ -1175,18 +1175,20 @@ __device__ __forceinline__ uint64_t rect_mask_t(float x0, float x1, float y0, fl
 // [x0, x1] x [y0, y1] (anchor-local), with a margin of 0.05 pixel: a superset
 // of the pixels within distance g of a triangle inside the box, i.e. of the
 // pixels the background term can reach (the box grown by g, corners rounded)
+// (g2r: the squared distance per tile row instead of g * g, when given)
 template <int TW>
-__device__ __forceinline__ uint64_t disc_mask_t(float x0, float x1, float y0, float y1, float g, float W, float H)
+__device__ __forceinline__ uint64_t disc_mask_t(float x0, float x1, float y0, float y1, float g, float W, float H,
+                                                const float *g2r = nullptr)
 {
     constexpr int TH = kWave / TW;
-    const float ih = rcp(H), my = 0.1f * ih, g2 = g * g;
+    const float ih = rcp(H), my = 0.1f * ih, gg = g * g;
     uint64_t m = 0;
 #pragma unroll
     for (int r = 0; r < TH; ++r) {
         // row r has centre dv = ((TH-1) - 2r)/H
         const float v = (float)(TH - 1 - 2 * r) * ih;
         const float dy = fmaxf(fmaxf(y0 - v, v - y1) - my, 0.0f);
-        const float h2 = fmaf(-dy, dy, g2);
+        const float h2 = fmaf(-dy, dy, g2r ? g2r[r] : gg);
         const float hx = sqrtf(fmaxf(h2, 0.0f));
         const float ca = fmaf(x0 - hx, W, (float)(TW - 1)) * 0.5f - 0.05f, cb = fmaf(x1 + hx, W, (float)(TW - 1)) * 0.5f + 0.05f;
         const int c0 = max((int)ceilf(fmaxf(ca, -1.0f)), 0), c1 = min((int)floorf(fminf(cb, (float)TW)), TW - 1);
@@ -1213,15 +1215,16 @@ __device__ __forceinline__ uint64_t rect_mask_any(const Inst &a, float x0, float
     return (row * a.rep) & hi & ~lo;
 }
 
-__device__ __forceinline__ uint64_t disc_mask_any(const Inst &a, float x0, float x1, float y0, float y1, float g)
+__device__ __forceinline__ uint64_t disc_mask_any(const Inst &a, float x0, float x1, float y0, float y1, float g,
+                                                  const float *g2r = nullptr)
 {
     const int tw = a.tw, th = a.th;
-    const float W = (float)a.W, cw = (float)(tw - 1), ih = rcp((float)a.H), my = 0.1f * ih, g2 = g * g;
+    const float W = (float)a.W, cw = (float)(tw - 1), ih = rcp((float)a.H), my = 0.1f * ih, gg = g * g;
     uint64_t m = 0;
     for (int r = 0; r < th; ++r) {
         const float v = (float)(th - 1 - 2 * r) * ih;   // row r's centre
         const float dy = fmaxf(fmaxf(y0 - v, v - y1) - my, 0.0f);
-        const float h2 = fmaf(-dy, dy, g2);
+        const float h2 = fmaf(-dy, dy, g2r ? g2r[r] : gg);
         if (h2 < 0.0f) continue;
         const float hx = sqrtf(h2);
         const float ca = fmaf(x0 - hx, W, cw) * 0.5f - 0.05f, cb = fmaf(x1 + hx, W, cw) * 0.5f + 0.05f;
@@ -1234,11 +1237,12 @@ __device__ __forceinline__ uint64_t disc_mask_any(const Inst &a, float x0, float
 // the masks for the instance's tile shape (a wave-uniform choice; TWS == 8:
 // the kernel is built for 8 x 8 tiles)
 template <int TWS = 0>
-__device__ __forceinline__ uint64_t tile_mask(const Inst &a, bool disc, float x0, float x1, float y0, float y1, float g)
+__device__ __forceinline__ uint64_t tile_mask(const Inst &a, bool disc, float x0, float x1, float y0, float y1, float g,
+                                              const float *g2r = nullptr)
 {
     const float W = (float)a.W, H = (float)a.H;
     const bool t8 = TWS == 8 || a.tw == 8;
-    if (disc) return t8 ? disc_mask_t<8>(x0, x1, y0, y1, g, W, H) : disc_mask_any(a, x0, x1, y0, y1, g);
+    if (disc) return t8 ? disc_mask_t<8>(x0, x1, y0, y1, g, W, H, g2r) : disc_mask_any(a, x0, x1, y0, y1, g, g2r);
     return t8 ? rect_mask_t<8>(x0, x1, y0, y1, g, W, H) : rect_mask_any(a, x0, x1, y0, y1, g);
 }
 
@@ -1346,12 +1350,13 @@ __device__ __forceinline__ Pref prefetch(const Inst &a, int64_t first, int nb)
 // pixel masks; allow[j] is the set of pixels in question at sub-frame j (0 for
 // sub-frames outside the chunk).  Returns the number of items; cnt / pre are
 // the lane's entry's item count and first item.  Optionally also stages the
-// vertex attributes (at) and vertex indices (vids).
+// vertex attributes (at) and vertex indices (vids).  With reach, background
+// boxes are grown row by row by reach[j][row] (squared) instead of by grow.
 template <int T, int TWS = 0>
 __device__ __forceinline__ int stage_items(const Inst &a, ItemShared<T> &sh, const Pref &pf, int nb, int s,
                                            const TileCtx &g, float tc, const float tau[T], int kind, float grow,
                                            const uint64_t allow[T], float (*at)[NB], int (*vids)[3], int &cnt,
-                                           int &pre)
+                                           int &pre, const float (*reach)[kMaxTileH] = nullptr)
 {
     const int lane = threadIdx.x & 63;
     lds_sync();
@@ -1377,7 +1382,7 @@ __device__ __forceinline__ int stage_items(const Inst &a, ItemShared<T> &sh, con
                     y0 = fminf(y0, yt);
                     y1 = fmaxf(y1, yt);
                 }
-                mj = tile_mask<TWS>(a, kind == kRecBg, x0, x1, y0, y1, grow) &
+                mj = tile_mask<TWS>(a, kind == kRecBg, x0, x1, y0, y1, grow, reach ? reach[j] : nullptr) &
                      allow[j];
             }
             sh.m[j][lane] = mj;
@@ -2268,6 +2273,7 @@ struct BgBwdShared {
     float P[T][kWave];        // forward product over the non-zero factors if there is none
                               // of A == 1; minus the product if there is one; -0 if more
     float gal[kWave];         // dL/dalpha of each pixel, already divided by K
+    float reach[T][kMaxTileH];  // per tile row: squared reach of its pixels' terms (-1: none)
 };
 
 // Background adjoint of one item: dalpha/dA_j = prod_{m != j}(1 - A_m),
@@ -2394,6 +2400,7 @@ __global__ __launch_bounds__(64, WPS) void k_bg_bwd(const Inst *__restrict__ tab
         const int64_t ntasks = min(a.hdr->ntasks, a.maxtasks);
         const int MB = a.bwd_merge;
         const int64_t nunits = (ntasks + MB - 1) / MB;
+        const float halo2 = a.halo * a.halo, reach_pad = 1e-3f / a.inv_delta + 1e-8f;
     for (;;) {
         const int64_t u = next_task(&a.hdr->bwd_task_ctr);
         if (u >= nunits) break;
@@ -2437,8 +2444,22 @@ __global__ __launch_bounds__(64, WPS) void k_bg_bwd(const Inst *__restrict__ tab
             // P / min(min(1 - A), 1/2): below kAdjWMin the pixel-sub-frame is
             // skipped; with two zero factors every weight is 0
             const bool live = nz == 1 || (nz == 0 && !(P < kAdjWMin * om_lo));
-            bgm[j] = __ballot(vid == -1 && gal != 0.0f && live);
+            const bool act = vid == -1 && gal != 0.0f && live;
+            bgm[j] = __ballot(act);
             anybg = anybg || bgm[j] != 0ull;
+            // squared reach of the pixel's terms: with no zero factor a term's
+            // weight is P A / (1 - A) = P / (exp(d / delta) - 1), at least
+            // kAdjWMin only for d <= delta ln(1 + P / kAdjWMin); with one zero
+            // factor only that factor's own term (d = 0) has weight.  The
+            // margin (1%, 1e-3 delta, 1e-8) is far above float rounding, so no
+            // term the weight test keeps is cut off; the maximum over the tile
+            // row grows the faces' boxes in staging
+            float rr = -1.0f;
+            if (act)
+                rr = nz == 0 ? fminf(halo2, fmaf(log1pf(P * (1.0f / kAdjWMin)) / a.inv_delta, 1.01f, reach_pad))
+                             : reach_pad;
+            for (int o = 1; o < a.tw; o <<= 1) rr = fmaxf(rr, __shfl_xor(rr, o, 64));
+            if ((lane & (a.tw - 1)) == 0) sh.reach[j][lane / a.tw] = rr;
         }
         if (!anybg) continue;
         const int64_t idx = (int64_t)a.NC * a.ntiles + ct;
@@ -2457,7 +2478,7 @@ __global__ __launch_bounds__(64, WPS) void k_bg_bwd(const Inst *__restrict__ tab
             }
             int cnt, pre;
             const int total = stage_items<T>(a, sh.it, cur, nb, ck.s, g, tc, tau, kRecBg, a.halo, bgm, nullptr,
-                                             sh.vslot, cnt, pre);
+                                             sh.vslot, cnt, pre, sh.reach);
             used += vt_bind(sh.vt, sh.vslot, nb);
             float gK[12];
 #pragma unroll
