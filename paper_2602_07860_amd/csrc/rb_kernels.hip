@@ -49,8 +49,11 @@
 //   k_bg_bwd           persistent waves over the background tasks, with a
 //                      task counter: re-walks the list slices for the
 //                      (pixel, sub-frame)s with gradient (leaving out terms
-//                      of negligible weight) and runs the closest-point /
-//                      barycentric adjoint into the vertex table.
+//                      of negligible weight; faces' boxes are grown per tile
+//                      row by how far the row's terms can reach under that
+//                      rule, not by the full halo) and runs the
+//                      closest-point / barycentric adjoint into the vertex
+//                      table.
 //   k_det_finish       (deterministic mode) fixed-point sums to float.
 //   k_kf_to_vertex     maps keyframe gradients through the projection and
 //                      the keyframe transforms to the rest vertices.
