@@ -1873,17 +1873,24 @@ __global__ __launch_bounds__(64 * kResWaves) void k_resolve(const Inst *__restri
 #pragma unroll
     for (int ch = 0; ch <= NCH; ++ch) acc[ch] = 0.0;
     if (in) {
+        // the record's slots are loaded with the visibility, not after it,
+        // so that a sub-frame waits for one round of loads, not two (a
+        // background pixel reads the slots past its two as well)
+        const int nl = max(a.C, 2);
+#pragma unroll 2
         for (int k = w; k < a.K; k += kResWaves) {
             const int vid = a.vis_id[vis_index(a, tile, k, lane)];
+            float v[NCH];
+#pragma unroll
+            for (int sl = 0; sl < NCH; ++sl) v[sl] = sl < nl ? a.pix[pix_index(a, tile, k, sl, lane)] : 0.0f;
             if (vid >= 0) {
 #pragma unroll
                 for (int ch = 0; ch < NCH; ++ch)
-                    if (ch < a.C) acc[ch] += (double)a.pix[pix_index(a, tile, k, ch, lane)];
+                    if (ch < a.C) acc[ch] += (double)v[ch];
                 acc[NCH] += 1.0;
             } else {
-                const float ls = a.pix[pix_index(a, tile, k, 0, lane)];
-                const int nz = __float_as_int(a.pix[pix_index(a, tile, k, 1, lane)]);
-                acc[NCH] += nz > 0 ? 1.0 : (double)(1.0f - exp2f(ls));
+                const int nz = __float_as_int(v[1]);
+                acc[NCH] += nz > 0 ? 1.0 : (double)(1.0f - exp2f(v[0]));
             }
         }
     }
